@@ -1,0 +1,262 @@
+"""CPU FP64 oracle for the smoothed-derivative Monte Carlo estimators.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py, never by the product library.  The arithmetic
+lives in ``orc.c`` (plain C, FP64); this module only marshals numpy arrays
+through ctypes.  It shares no code with ``paper_2412_03489_amd``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liborc.so")
+
+AIS, IS, GAUSS = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile orc.c with gcc into liborc.so (no GPU code involved)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+               "-o", _SO + ".tmp", os.path.join(_HERE, "orc.c"), "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class Opts(C.Structure):
+    _fields_ = [("sampler", C.c_int), ("antithetic", C.c_int),
+                ("hvp_rel_step", C.c_double), ("nthreads", C.c_int),
+                ("s0", C.c_uint64), ("dbg_loss", C.POINTER(C.c_double))]
+
+
+class NcgOpts(C.Structure):
+    _fields_ = [("cg_iters", C.c_int), ("trust_radius", C.c_double),
+                ("use_full_hessian", C.c_int), ("eig_floor", C.c_double),
+                ("hvp_limit", C.c_int)]
+
+
+class NcgReport(C.Structure):
+    _fields_ = [("iters_done", C.c_int), ("hit_trust", C.c_int), ("neg_curv", C.c_int),
+                ("step_norm", C.c_double), ("g_norm", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = C.CDLL(_SO)
+        d, i, u64, u32, vp = C.c_double, C.c_int, C.c_uint64, C.c_uint32, C.c_void_p
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_grad_lobe_icdf.argtypes = [u32, d]; L.orc_grad_lobe_icdf.restype = d
+        L.orc_hdiag_icdf.argtypes = [u32, d]; L.orc_hdiag_icdf.restype = d
+        L.orc_hdiag_cdf.argtypes = [d, d]; L.orc_hdiag_cdf.restype = d
+        L.orc_lambertw.argtypes = [d, i]; L.orc_lambertw.restype = d
+        L.orc_scene_disks.argtypes = [i, i, i, i, i, vp, vp, vp]; L.orc_scene_disks.restype = vp
+        L.orc_scene_pt.argtypes = [i, i, i, i, vp, vp]; L.orc_scene_pt.restype = vp
+        L.orc_scene_quad.argtypes = [i, vp, vp, d]; L.orc_scene_quad.restype = vp
+        L.orc_scene_neggauss.argtypes = [i, d]; L.orc_scene_neggauss.restype = vp
+        L.orc_scene_edge.argtypes = [i, i, i, vp]; L.orc_scene_edge.restype = vp
+        L.orc_scene_free.argtypes = [vp]
+        L.orc_scene_nparams.argtypes = [vp]; L.orc_scene_nparams.restype = i
+        L.orc_render.argtypes = [vp, vp, u64, u32, i, vp]; L.orc_render.restype = i
+        L.orc_loss.argtypes = [vp, vp, u64, u32]; L.orc_loss.restype = d
+        L.orc_draw_tau.argtypes = [i, i, d, u64, u32, i, i, vp, vp]; L.orc_draw_tau.restype = i
+        for nm in ("orc_est_grad", "orc_est_hessian"):
+            getattr(L, nm).argtypes = [vp, vp, d, u64, u64, C.POINTER(Opts), vp]
+            getattr(L, nm).restype = i
+        for nm in ("orc_est_hvp", "orc_est_hvp_limit"):
+            getattr(L, nm).argtypes = [vp, vp, d, u64, u64, vp, C.POINTER(Opts), vp]
+            getattr(L, nm).restype = i
+        L.orc_newton_cg_step.argtypes = [vp, vp, d, u64, u64, C.POINTER(NcgOpts),
+                                         C.POINTER(Opts), C.POINTER(NcgReport)]
+        L.orc_newton_cg_step.restype = i
+        L.orc_jacobi_eig.argtypes = [i, vp, vp, vp]; L.orc_jacobi_eig.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def grad_lobe_icdf(w, sigma):
+    return lib().orc_grad_lobe_icdf(int(w), float(sigma))
+
+
+def hdiag_icdf(w, sigma):
+    return lib().orc_hdiag_icdf(int(w), float(sigma))
+
+
+def hdiag_cdf(u, sigma):
+    return lib().orc_hdiag_cdf(float(u), float(sigma))
+
+
+def lambertw(z, branch):
+    return lib().orc_lambertw(float(z), int(branch))
+
+
+def draw_tau(what, n, sigma, seed, s, sampler, stream=0):
+    tau = np.zeros(n)
+    el = C.c_int(-1)
+    st = lib().orc_draw_tau(int(what), int(n), float(sigma), int(seed), int(s), int(sampler),
+                            int(stream), _p(tau), C.byref(el))
+    if st:
+        raise ValueError(f"orc_draw_tau failed ({st})")
+    return tau, el.value
+
+
+class Scene:
+    """Owns an orc_scene handle and the numpy arrays it was built from."""
+
+    def __init__(self, handle, n, keep=()):
+        if not handle:
+            raise ValueError("oracle rejected the scene description")
+        self.h = handle
+        self.n = n
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.orc_scene_free(self.h)
+            self.h = None
+
+    @staticmethod
+    def disks(W, H, C_, colors, target, radius=None, ppd=3):
+        colors = np.ascontiguousarray(colors, dtype=np.float32)
+        target = np.ascontiguousarray(target, dtype=np.float32)
+        D = colors.shape[0]
+        rad = None if radius is None else np.ascontiguousarray(radius, dtype=np.float32)
+        h = lib().orc_scene_disks(W, H, C_, D, ppd, None if rad is None else _p(rad),
+                                  _p(colors), _p(target))
+        return Scene(h, D * ppd, (colors, target, rad))
+
+    @staticmethod
+    def pt(W, H, spp, desc, target, nspheres=4):
+        desc = np.ascontiguousarray(desc, dtype=np.float64)
+        target = np.ascontiguousarray(target, dtype=np.float32)
+        h = lib().orc_scene_pt(W, H, spp, nspheres, _p(desc), _p(target))
+        return Scene(h, 6, (desc, target))
+
+    @staticmethod
+    def quad(A, b=None, c=0.0):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        n = A.shape[0]
+        b = np.zeros(n) if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        return Scene(lib().orc_scene_quad(n, _p(A), _p(b), float(c)), n, (A, b))
+
+    @staticmethod
+    def neggauss(n, s1):
+        return Scene(lib().orc_scene_neggauss(int(n), float(s1)), n)
+
+    @staticmethod
+    def edge(W, H, n, target):
+        target = np.ascontiguousarray(target, dtype=np.float32)
+        return Scene(lib().orc_scene_edge(W, H, n, _p(target)), n, (target,))
+
+
+def render(scene, theta, H, W, C_, seed=0, s=0, spp=0):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.zeros(H * W * C_)
+    st = lib().orc_render(scene.h, _p(th), int(seed), int(s), int(spp), _p(out))
+    if st:
+        raise ValueError(f"orc_render failed ({st})")
+    return out.reshape(H, W, C_)
+
+
+def loss(scene, theta, seed=0, s=0):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    return lib().orc_loss(scene.h, _p(th), int(seed), int(s))
+
+
+def _opts(sampler, antithetic, hvp_rel_step, nthreads, s0, dbg):
+    o = Opts()
+    o.sampler = sampler
+    o.antithetic = 1 if antithetic else 0
+    o.hvp_rel_step = hvp_rel_step
+    o.nthreads = nthreads
+    o.s0 = s0
+    o.dbg_loss = dbg.ctypes.data_as(C.POINTER(C.c_double)) if dbg is not None else None
+    return o
+
+
+def n_renders(kind, n, N, sampler=AIS, antithetic=True):
+    """Renders an estimator call makes (table of evaluation counts, x2 antithetic)."""
+    A = 2 if antithetic else 1
+    K = n * (n + 1) // 2 if kind == "hess" else n
+    streams = K if (sampler == IS and kind != "hvp_limit") else 1
+    per = 2 if kind == "hvp" else 1
+    return streams * N * A * per
+
+
+def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic=True,
+             hvp_rel_step=0.1, nthreads=None, s0=0, return_losses=False):
+    """kind in {'grad', 'hess', 'hvp', 'hvp_limit'}; returns numpy array(s)."""
+    n = scene.n
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    dbg = np.zeros(n_renders(kind, n, N, sampler, antithetic)) if return_losses else None
+    o = _opts(sampler, antithetic, hvp_rel_step, nthreads, s0, dbg)
+    L = lib()
+    if kind == "grad":
+        out = np.zeros(n)
+        st = L.orc_est_grad(scene.h, _p(th), float(sigma), int(N), int(seed), C.byref(o), _p(out))
+    elif kind == "hess":
+        out = np.zeros((n, n))
+        st = L.orc_est_hessian(scene.h, _p(th), float(sigma), int(N), int(seed), C.byref(o),
+                               _p(out))
+    elif kind in ("hvp", "hvp_limit"):
+        vv = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.zeros(n)
+        fn = L.orc_est_hvp if kind == "hvp" else L.orc_est_hvp_limit
+        st = fn(scene.h, _p(th), float(sigma), int(N), int(seed), _p(vv), C.byref(o), _p(out))
+    else:
+        raise ValueError(kind)
+    if st:
+        raise ValueError(f"oracle estimator {kind} failed ({st})")
+    return (out, dbg) if return_losses else out
+
+
+def newton_cg_step(scene, theta, sigma, N, seed, cg_iters=10, trust_radius=1.0,
+                   use_full_hessian=False, eig_floor=1e-6, hvp_limit=False, sampler=AIS,
+                   antithetic=True, hvp_rel_step=0.1, nthreads=None):
+    th = np.array(theta, dtype=np.float64)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    o = _opts(sampler, antithetic, hvp_rel_step, nthreads, 0, None)
+    no = NcgOpts(cg_iters, trust_radius, 1 if use_full_hessian else 0, eig_floor,
+                 1 if hvp_limit else 0)
+    rep = NcgReport()
+    st = lib().orc_newton_cg_step(scene.h, _p(th), float(sigma), int(N), int(seed),
+                                  C.byref(no), C.byref(o), C.byref(rep))
+    if st:
+        raise ValueError(f"orc_newton_cg_step failed ({st})")
+    return th, {"iters_done": rep.iters_done, "hit_trust": rep.hit_trust,
+                "neg_curv": rep.neg_curv, "step_norm": rep.step_norm, "g_norm": rep.g_norm}
+
+
+def jacobi_eig(A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    ev = np.zeros(n)
+    V = np.zeros((n, n))
+    lib().orc_jacobi_eig(n, _p(A), _p(ev), _p(V))
+    return ev, V

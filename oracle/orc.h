@@ -1,0 +1,107 @@
+/*
+ * orc.h -- plain, slow CPU FP64 oracle for the smoothed-derivative Monte Carlo
+ * estimators of "Stochastic Gradient Estimation for Higher-order
+ * Differentiable Rendering" (Wang, Fischer, Ritschel, ICCV 2025).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP
+ * implementation; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.  It shares no code, header or table with the HIP
+ * library under paper_2412_03489_amd/.
+ *
+ * All arithmetic is IEEE double precision, in the order the paper's
+ * definitions state it.  Every function cites the passage it follows.
+ *
+ * Return convention: 0 on success, negative on invalid arguments
+ * (-1 invalid value, -4 unsupported combination).
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_scene orc_scene;
+
+/* Sampler choice (section "Aggregate", table of evaluation counts). */
+#define ORC_AIS   0  /* aggregate importance sampling: one render per draw     */
+#define ORC_IS    1  /* per-element importance sampling: K renders per draw    */
+#define ORC_GAUSS 2  /* plain Gaussian draws, weight = kernel factor ("no IS") */
+
+typedef struct {
+  int sampler;          /* ORC_AIS / ORC_IS / ORC_GAUSS                       */
+  int antithetic;       /* 1: pair every tau with -tau (A = 2); 0: A = 1     */
+  double hvp_rel_step;  /* h = hvp_rel_step * sigma for the central difference */
+  int nthreads;         /* worker threads over samples (>= 1)                 */
+  uint64_t s0;          /* first sample index (prefix/sub-range evaluation)   */
+  double* dbg_loss;     /* optional: per-render loss, canonical render order  */
+} orc_opts;
+
+/* ---- random numbers (Salmon et al., SC'11) ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* ---- 1-D samplers (sections "Gradients: Sampling", "Hessians: Sampling") -- */
+double orc_grad_lobe_icdf(uint32_t w, double sigma);   /* uniform word -> tau */
+double orc_hdiag_icdf(uint32_t w, double sigma);       /* uniform word -> tau */
+double orc_hdiag_cdf(double u, double sigma);          /* three-branch CDF    */
+double orc_lambertw(double z, int branch);             /* branch 0 or -1      */
+
+/* ---- scenes ---- */
+orc_scene* orc_scene_disks(int W, int H, int C, int D, int ppd, const float* radius,
+                           const float* colors, const float* target);
+orc_scene* orc_scene_pt(int W, int H, int spp, int nspheres, const double* desc,
+                        const float* target);
+orc_scene* orc_scene_quad(int n, const double* A, const double* b, double c);
+orc_scene* orc_scene_neggauss(int n, double s1);
+orc_scene* orc_scene_edge(int W, int H, int n, const float* target);
+void orc_scene_free(orc_scene* sc);
+int orc_scene_nparams(const orc_scene* sc);
+
+/* render (image scenes only): out has H*W*C doubles; `s` selects the per-sample
+ * pixel randomness of the path tracer (ignored by the rasterizer). */
+int orc_render(const orc_scene* sc, const double* theta, uint64_t seed, uint32_t s,
+               int spp_override, double* out);
+/* the loss f(theta) = mean over H*W*C of (I - T)^2, or the analytic function */
+double orc_loss(const orc_scene* sc, const double* theta, uint64_t seed, uint32_t s);
+
+/* ---- draws: tau for one sample (for sampler tests) ---- */
+int orc_draw_tau(int what, int n, double sigma, uint64_t seed, uint32_t s, int sampler,
+                 int stream, double* tau, int* element);
+
+/* ---- estimators (sections "Gradients", "Hessians", "Hessian-vector product",
+ *      "Aggregate") ---- */
+int orc_est_grad(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
+                 uint64_t seed, const orc_opts* o, double* g);
+int orc_est_hessian(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
+                    uint64_t seed, const orc_opts* o, double* H);
+int orc_est_hvp(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
+                uint64_t seed, const double* v, const orc_opts* o, double* Hv);
+/* HVP through the sampled Hessian kernel applied to v (epsilon -> 0 limit of
+ * the central difference), one render per draw. */
+int orc_est_hvp_limit(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
+                      uint64_t seed, const double* v, const orc_opts* o, double* Hv);
+
+/* ---- Newton-CG / modified Newton (section "Previous Work", PSD appendix) ---- */
+typedef struct {
+  int cg_iters;          /* maximum CG iterations                                 */
+  double trust_radius;   /* Delta: alpha = min(alpha, Delta/|v|)                  */
+  int use_full_hessian;  /* 1: modified Newton on the estimated H                */
+  double eig_floor;      /* full-H mode: lambda <- max(|lambda|, eig_floor)       */
+  int hvp_limit;         /* 1: CG products through the limit-kernel HVP          */
+} orc_ncg_opts;
+
+typedef struct {
+  int iters_done, hit_trust, neg_curv;
+  double step_norm, g_norm;
+} orc_ncg_report;
+
+int orc_newton_cg_step(const orc_scene* sc, double* theta, double sigma, uint64_t N,
+                       uint64_t seed, const orc_ncg_opts* no, const orc_opts* o,
+                       orc_ncg_report* rep);
+int orc_jacobi_eig(int n, const double* A, double* evals, double* evecs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,207 @@
+"""Pins of the oracle's random numbers and one-dimensional samplers.
+
+Each test checks the oracle against something other than itself: numerical
+quadrature of the kernel densities (scipy.integrate), scipy's Lambert W, the
+Gaussian CDF (scipy.stats), the CDF anchors the paper states, and statistical
+properties of the Philox words.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+FACTS = json.load(open(os.path.join(HERE, "golden", "paper_facts.json")))
+
+
+def phi(u, s):
+    return np.exp(-u * u / (2 * s * s)) / (s * math.sqrt(2 * math.pi))
+
+
+def qint(f, a, b, s, breaks=()):
+    """Integral of f(u, s) over [a, b] (a, b may be +-inf, read as +-40 s),
+    split at the kernel's break points so quadpack sees smooth pieces."""
+    a = -40 * s if a == -np.inf else a
+    b = 40 * s if b == np.inf else b
+    pts = [a] + sorted(p for p in breaks if a < p < b) + [b]
+    return sum(integrate.quad(f, lo, hi, args=(s,), epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+               for lo, hi in zip(pts[:-1], pts[1:]))
+
+
+def grad_density(u, s):
+    """|d/du N(u; 0, s^2)| normalised by quadrature (section "Gradients")."""
+    return abs(u) / s**2 * phi(u, s)
+
+
+def hdiag_density(u, s):
+    """|d^2/du^2 N(u; 0, s^2)| (section "Hessians", diagonal kernel)."""
+    return abs(u * u / s**4 - 1 / s**2) * phi(u, s)
+
+
+def test_lobe_masses_by_quadrature():
+    s = 0.05
+    zg = qint(grad_density, -np.inf, np.inf, s, (0.0,))
+    assert zg == pytest.approx(math.sqrt(2 / math.pi) / s, rel=1e-9)
+    left = qint(hdiag_density, -np.inf, -s, s)
+    inner = qint(hdiag_density, -s, s, s, (0.0,))
+    right = qint(hdiag_density, s, np.inf, s)
+    zd = 4 * math.exp(-0.5) / (s * s * math.sqrt(2 * math.pi))
+    assert left + inner + right == pytest.approx(zd, rel=1e-9)
+    # equal positive and negative mass; 1:2:1 split of tails and inner lobe
+    assert left + right == pytest.approx(inner, rel=1e-9)
+    assert left == pytest.approx(right, rel=1e-12)
+
+
+def test_lambertw_against_mpmath_and_scipy(orc):
+    """mpmath at 40 digits is the reference (scipy's W_{-1} loses digits within
+    ~1e-9 of the branch point, so scipy is only used away from it)."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    zs = np.concatenate([-np.exp(-1) + np.logspace(-14, -1, 20), -np.logspace(-12, -0.44, 30)])
+    for z in zs:
+        if z < -np.exp(-1):
+            continue
+        w0 = orc.lambertw(z, 0)
+        wm = orc.lambertw(z, -1)
+        assert w0 == pytest.approx(float(mp.lambertw(mp.mpf(z), 0)), rel=1e-12, abs=1e-15)
+        assert wm == pytest.approx(float(mp.lambertw(mp.mpf(z), -1)), rel=1e-12, abs=1e-15)
+        if z + np.exp(-1) > 1e-6:
+            assert w0 == pytest.approx(special.lambertw(z, 0).real, rel=1e-12, abs=1e-15)
+            assert wm == pytest.approx(special.lambertw(z, -1).real, rel=1e-12, abs=1e-15)
+        assert w0 >= -1.0 >= wm
+
+
+@pytest.mark.parametrize("xi", [1e-9, 1e-4, 0.01, 0.1, 0.3, 0.4999, 0.5001, 0.7, 0.99, 1 - 1e-7])
+def test_grad_lobe_icdf_inverts_quadrature_cdf(orc, xi):
+    s = 0.7
+    w = min(int(xi * 2**32), 2**32 - 1)
+    u = orc.grad_lobe_icdf(w, s)
+    zg = math.sqrt(2 / math.pi) / s
+    cdf = qint(grad_density, -np.inf, u, s, (0.0,)) / zg
+    assert cdf == pytest.approx((w + 0.5) / 2**32, rel=1e-7, abs=1e-10)
+
+
+@pytest.mark.parametrize("xi", [1e-9, 1e-3, 0.1, 0.2499, 0.2501, 0.3, 0.4999, 0.5001, 0.6,
+                                0.7499, 0.7501, 0.9, 1 - 1e-6])
+def test_hdiag_icdf_inverts_quadrature_cdf(orc, xi):
+    s = 1.3
+    w = min(int(xi * 2**32), 2**32 - 1)
+    u = orc.hdiag_icdf(w, s)
+    zd = 4 * math.exp(-0.5) / (s * s * math.sqrt(2 * math.pi))
+    cdf = qint(hdiag_density, -np.inf, u, s, (-s, 0.0, s)) / zd
+    assert cdf == pytest.approx((w + 0.5) / 2**32, rel=1e-7, abs=1e-11)
+
+
+def test_hdiag_cdf_matches_quadrature_and_anchors(orc):
+    s = 0.05
+    facts = FACTS["hessian_diag_cdf"]
+    assert orc.hdiag_cdf(-s, s) == pytest.approx(facts["cdf_at_minus_sigma"], abs=1e-15)
+    assert orc.hdiag_cdf(0.0, s) == pytest.approx(facts["cdf_at_zero"], abs=1e-15)
+    assert orc.hdiag_cdf(s, s) == pytest.approx(facts["cdf_at_plus_sigma"], abs=1e-15)
+    zd = 4 * math.exp(-0.5) / (s * s * math.sqrt(2 * math.pi))
+    for u in np.linspace(-5 * s, 5 * s, 23):
+        q = qint(hdiag_density, -np.inf, u, s, (-s, 0.0, s)) / zd
+        assert orc.hdiag_cdf(u, s) == pytest.approx(q, abs=1e-10)
+    # kernel roots at +-sigma
+    for r in facts["roots_in_sigma"]:
+        assert (r * s) ** 2 / s**4 - 1 / s**2 == pytest.approx(0.0, abs=1e-9)
+
+
+def test_hdiag_icdf_branch_points(orc):
+    s = 2.0
+    # xi just below/above 1/4 and 3/4 land next to -s and +s
+    assert orc.hdiag_icdf(2**30 - 1, s) == pytest.approx(-s, rel=1e-4)
+    assert orc.hdiag_icdf(2**30, s) == pytest.approx(-s, rel=1e-4)
+    assert orc.hdiag_icdf(3 * 2**30 - 1, s) == pytest.approx(s, rel=1e-4)
+    assert orc.hdiag_icdf(3 * 2**30, s) == pytest.approx(s, rel=1e-4)
+    assert abs(orc.hdiag_icdf(2**31, s)) < 1e-8
+
+
+def _ks_draws(orc, what, n, s, sampler, stream, count):
+    taus, els = [], []
+    for i in range(count):
+        t, e = orc.draw_tau(what, n, s, 11, i, sampler, stream)
+        taus.append(t)
+        els.append(e)
+    return np.array(taus), np.array(els)
+
+
+def test_gradient_is_stream_marginals(orc):
+    s, n = 0.3, 3
+    taus, els = _ks_draws(orc, 0, n, s, orc.IS, 1, 4000)
+    assert (els == 1).all()
+    zg = math.sqrt(2 / math.pi) / s
+    cdf = lambda u: np.where(u < 0, 0.5 * np.exp(-u * u / (2 * s * s)),
+                             1 - 0.5 * np.exp(-u * u / (2 * s * s)))
+    assert stats.kstest(taus[:, 1], cdf).pvalue > 1e-3
+    for j in (0, 2):
+        assert stats.kstest(taus[:, j], stats.norm(0, s).cdf).pvalue > 1e-3
+    # E|tau| for the Rayleigh magnitude = s sqrt(pi/2)
+    assert np.abs(taus[:, 1]).mean() == pytest.approx(s * math.sqrt(math.pi / 2), rel=0.05)
+    del zg
+
+
+def test_hessian_diag_is_stream_marginals(orc):
+    s, n = 0.5, 2
+    # element 0 of the upper triangle is (0,0)
+    taus, els = _ks_draws(orc, 1, n, s, orc.IS, 0, 4000)
+    assert stats.kstest(taus[:, 0], lambda u: np.array([orc.hdiag_cdf(x, s) for x in u])).pvalue > 1e-3
+    assert stats.kstest(taus[:, 1], stats.norm(0, s).cdf).pvalue > 1e-3
+    # P(|tau| > sigma) = 1/2
+    assert (np.abs(taus[:, 0]) > s).mean() == pytest.approx(0.5, abs=0.03)
+
+
+def test_hessian_offdiag_is_stream_marginals(orc):
+    s, n = 0.5, 3
+    # element 1 of the upper triangle is (0,1): both dims from the gradient lobes
+    taus, _ = _ks_draws(orc, 1, n, s, orc.IS, 1, 3000)
+    cdf = lambda u: np.where(u < 0, 0.5 * np.exp(-u * u / (2 * s * s)),
+                             1 - 0.5 * np.exp(-u * u / (2 * s * s)))
+    assert stats.kstest(taus[:, 0], cdf).pvalue > 1e-3
+    assert stats.kstest(taus[:, 1], cdf).pvalue > 1e-3
+    assert stats.kstest(taus[:, 2], stats.norm(0, s).cdf).pvalue > 1e-3
+    assert abs(np.corrcoef(taus[:, 0], taus[:, 1])[0, 1]) < 0.06
+
+
+def test_ais_selector_uniform(orc):
+    n = 3
+    K = n * (n + 1) // 2
+    _, els = _ks_draws(orc, 1, n, 0.1, orc.AIS, 0, 6000)
+    counts = np.bincount(els, minlength=K)
+    assert stats.chisquare(counts).pvalue > 1e-3
+
+
+def test_gauss_sampler_is_isotropic_gaussian(orc):
+    taus, els = _ks_draws(orc, 0, 4, 0.2, orc.GAUSS, 0, 3000)
+    assert (els == -1).all()
+    for j in range(4):
+        assert stats.kstest(taus[:, j], stats.norm(0, 0.2).cdf).pvalue > 1e-3
+    c = np.corrcoef(taus.T)
+    assert np.abs(c - np.eye(4)).max() < 0.07
+
+
+def test_philox_statistics(orc):
+    key = np.array([0x12345678, 0x9ABCDEF0], dtype=np.uint32)
+    words = np.array([orc.philox([i, 0, 0, 7], key) for i in range(4096)], dtype=np.uint64)
+    flat = words.reshape(-1)
+    # uniform 8-bit buckets
+    counts = np.bincount((flat >> np.uint64(24)).astype(np.int64), minlength=256)
+    assert stats.chisquare(counts).pvalue > 1e-4
+    # every bit is balanced
+    for b in range(32):
+        frac = ((flat >> np.uint64(b)) & np.uint64(1)).mean()
+        assert abs(frac - 0.5) < 0.02
+    # avalanche: flipping one counter bit flips ~half of the 128 output bits
+    flips = []
+    for i in range(256):
+        a = orc.philox([i, 5, 6, 7], key)
+        b = orc.philox([i ^ 1, 5, 6, 7], key)
+        x = np.bitwise_xor(a, b)
+        flips.append(sum(bin(int(v)).count("1") for v in x))
+    assert np.mean(flips) == pytest.approx(64, abs=3)
+    # the key matters; outputs are distinct across counters
+    assert not np.array_equal(orc.philox([1, 2, 3, 4], key), orc.philox([1, 2, 3, 4], key + 1))
+    assert len({tuple(w) for w in words.tolist()}) == len(words)
