@@ -1,0 +1,225 @@
+/*
+ * hrest.h -- C ABI of the MI355X (gfx950) library that estimates gradients,
+ * Hessians and Hessian-vector products of a Gaussian-smoothed rendering loss
+ * by importance-sampled Monte Carlo, and takes Newton-CG steps with them.
+ *
+ * Method: Z. Wang, M. Fischer, T. Ritschel, "Stochastic Gradient Estimation
+ * for Higher-order Differentiable Rendering", ICCV 2025 (arXiv 2412.03489).
+ *   - problem statement and smoothing by convolution: section "Our approach",
+ *     "Background" (D S R = integral of D kappa(tau) R(theta - tau));
+ *   - gradient kernel and its lobe sampler: section "Gradients";
+ *   - Hessian kernel, diagonal CDF and off-diagonal product sampler:
+ *     section "Hessians";
+ *   - Hessian-vector product by central differences of gradient estimators:
+ *     section "Hessian-vector product";
+ *   - aggregate importance sampling and the evaluation-count table:
+ *     section "Aggregate";
+ *   - Newton-CG with Fletcher-Reeves and trust truncation: section
+ *     "Previous Work", and the appendix on non-PSD Hessians;
+ *   - antithetic pairs: appendix "Hyperparameters".
+ *
+ * Conventions (every entry point):
+ *   - returns hr_status: 0 on success, negative on failure; no C++ exception
+ *     crosses the ABI; hr_last_error() returns a thread-local message for the
+ *     last failure on the calling thread;
+ *   - "host" pointers are plain CPU memory owned by the caller and never
+ *     retained after the call returns; "_dev" entry points take device
+ *     pointers (HBM of the context's GPU), owned by the caller, and enqueue
+ *     their work asynchronously on the context's stream;
+ *   - all parameter vectors are FP64; images are FP32, row-major
+ *     (y, x, channel), y pointing down;
+ *   - theta layout of a disk scene: per disk (cx, cy) or (cx, cy, r),
+ *     interleaved, in image-normalised coordinates; of a path-traced scene:
+ *     (light centre x, y, z, sphere-0 centre x, y, z);
+ *   - estimates use N draws tau_s, s = 0..N-1, from one Philox4x32-10 stream
+ *     keyed by `seed`; with antithetic pairs every draw is rendered at
+ *     theta - tau and theta + tau.  Results at N' < N are the estimates over
+ *     the first N' draws (counter-based random numbers).
+ *   - invalid input (sigma <= 0 or non-finite, N == 0 or N >= 2^32, non-finite
+ *     theta or v, NULL pointers, unsupported option) returns HR_EINVAL and
+ *     writes nothing; a request larger than the context's memory budget
+ *     returns HR_ENOMEM; a HIP runtime failure returns HR_EDEVICE.
+ */
+#ifndef HREST_H
+#define HREST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HR_OK = 0,
+  HR_EINVAL = -1,
+  HR_ENOMEM = -2,
+  HR_EDEVICE = -3,
+  HR_EUNSUPPORTED = -4,
+} hr_status;
+
+/* Sampler (section "Aggregate", table of evaluations per draw).
+ *   HR_AIS  : aggregate importance sampling -- draw the element uniformly, draw
+ *             tau from that element's lobe density, weight every element by
+ *             d_m(tau) / q(tau) with q the mixture of all element densities;
+ *             one render per draw.
+ *   HR_IS   : per-element importance sampling, one stream of N draws per
+ *             element (K renders per draw), weight sgn(d_m) Z_m.
+ *   HR_GAUSS: plain Gaussian draws, weight d_m(tau) ("no IS" column). */
+typedef enum { HR_AIS = 0, HR_IS = 1, HR_GAUSS = 2 } hr_sampler;
+
+typedef struct hr_ctx hr_ctx;      /* one per GPU: stream, workspace, timers   */
+typedef struct hr_scene hr_scene;  /* device-resident scene and target image   */
+
+typedef struct {
+  int sampler;          /* hr_sampler; default HR_AIS                                 */
+  int antithetic;       /* 1 (default): pair tau with -tau; 0: single draws             */
+  double hvp_rel_step;  /* HVP central-difference step h = hvp_rel_step * sigma (0.1) */
+  int accum_fp64;       /* 0 (default): compensated-FP32 lobe sums; 1: FP64 sums        */
+  int samples_per_block;/* renders per raster/path-tracer block; 0 = library choice     */
+  double* dbg_loss;     /* optional host buffer receiving every render's loss, in the
+                           order ((stream*N + s)*A + a)*S + shift, with a = 0 for
+                           theta - tau, 1 for theta + tau, shift = 0 for +h, 1 for -h
+                           (S = 2 for the HVP, else 1); NULL = not wanted           */
+  double* dbg_tau;      /* optional host buffer receiving the draws tau, streams*N*n
+                           doubles in the order (stream*N + s)*n + j; NULL = not wanted */
+} hr_opts;
+
+/* Fills the defaults listed above. */
+void hr_opts_default(hr_opts* o);
+
+/* ---- context ------------------------------------------------------------ */
+/* Creates a context on HIP device `device`: one stream of default priority and
+ * an empty workspace.  Errors: HR_EINVAL (bad device), HR_EDEVICE. */
+hr_status hr_ctx_create(int device, hr_ctx** out);
+void hr_ctx_destroy(hr_ctx* ctx);
+/* Makes `stream` (a hipStream_t of the context's device, e.g. a torch stream)
+ * the stream all "_dev" calls enqueue on; NULL restores the context's own. */
+hr_status hr_ctx_set_stream(hr_ctx* ctx, void* stream);
+/* Upper bound on workspace bytes one call may hold (default: 64 GiB). */
+hr_status hr_ctx_set_memory_budget(hr_ctx* ctx, uint64_t bytes);
+/* Waits for all work enqueued by the context. */
+hr_status hr_ctx_synchronize(hr_ctx* ctx);
+/* Kernel timing: when enabled, HIP events bracket every launch of the named
+ * kernel on the stream it is launched on; stats report launch count and the
+ * summed event time in milliseconds.  Names: "raster_loss", "pt_loss",
+ * "sample", "records", "accumulate". */
+hr_status hr_ctx_enable_timing(hr_ctx* ctx, int enable);
+hr_status hr_ctx_kernel_stats(hr_ctx* ctx, const char* name, uint64_t* launches,
+                              double* total_ms);
+hr_status hr_ctx_reset_stats(hr_ctx* ctx);
+const char* hr_last_error(void);
+
+/* ---- device memory for the "_dev" entry points ---------------------------
+ * Plain HBM allocations on the context's device, so callers need no other GPU
+ * runtime in the process.  hr_memcpy copies `bytes` between host and device
+ * (kind 0: host -> device, 1: device -> host, 2: device -> device) in order on
+ * the context stream and returns when the copy is complete. */
+hr_status hr_dev_alloc(hr_ctx* ctx, size_t bytes, void** out);
+hr_status hr_dev_free(hr_ctx* ctx, void* ptr);
+hr_status hr_memcpy(hr_ctx* ctx, void* dst, const void* src, size_t bytes, int kind);
+
+/* ---- scenes (copied to the device at creation; immutable) ---------------- */
+/* Disks in painter's order on a black background (the plateau tasks of
+ * section "Methods", with disks for squares).  A pixel centre
+ * ((x + 1/2)/W, (y + 1/2)/H) takes the colour of the last disk with positive
+ * radius whose squared distance to it is below r^2.
+ *   params_per_disk 2: theta = (cx, cy) per disk, radii from `radius` (D floats);
+ *   params_per_disk 3: theta = (cx, cy, r) per disk, `radius` ignored.
+ *   colors: D*C floats; target: H*W*C floats.  C in 1..4, D in 1..1024. */
+hr_status hr_scene_disks(hr_ctx* ctx, int W, int H, int C, int n_disks, int params_per_disk,
+                         const float* radius, const float* colors, const float* target,
+                         hr_scene** out);
+/* Path-traced scene (section "Background": Monte Carlo light transport).
+ * Diffuse spheres on the ground plane y = 0, one square light facing -y,
+ * pinhole camera; per pixel `spp` jittered paths with next-event estimation at
+ * the first two surface hits and one cosine-weighted bounce; black background.
+ * desc (FP64): eye[3], look_at[3], vfov_deg, light_side, Le, ground_albedo[3],
+ * then per sphere centre[3], radius, albedo[3] (sphere 0's centre comes from
+ * theta).  Pixel randomness of draw s is shared by all renders of that draw.
+ * nspheres in 1..16; target H*W*3 floats. */
+hr_status hr_scene_pt(hr_ctx* ctx, int W, int H, int spp, int nspheres, const double* desc,
+                      const float* target, hr_scene** out);
+/* Analytic test scenes: f = 1/2 theta^T A theta + b^T theta + c (the quadratic
+ * task of section "Methods"), and f = -N(theta; 0, s1^2 I) (appendix on
+ * non-PSD Hessians).  n in 1..128. */
+hr_status hr_scene_quad(hr_ctx* ctx, int n, const double* A, const double* b, double c,
+                        hr_scene** out);
+hr_status hr_scene_neggauss(hr_ctx* ctx, int n, double s1, hr_scene** out);
+void hr_scene_destroy(hr_scene* sc);
+int hr_scene_nparams(const hr_scene* sc);
+
+/* Renders an image scene at theta (host FP64) into `image` (host, H*W*C
+ * floats).  For the path tracer, `s` selects the draw's pixel randomness and
+ * `spp` > 0 overrides the scene's samples per pixel. */
+hr_status hr_render(hr_scene* sc, const double* theta, uint64_t seed, uint32_t s, int spp,
+                    float* image);
+
+/* ---- estimators (host pointers; synchronous) ---------------------------- */
+/* g (n doubles) of the smoothed loss: gradient kernel -tau_i/sigma^2 N(tau)
+ * (section "Gradients"). */
+hr_status hr_est_grad(hr_scene* sc, const double* theta, double sigma, uint64_t N,
+                      uint64_t seed, const hr_opts* opts, double* g);
+/* H (n*n doubles, row-major, symmetric): Hessian kernel (section "Hessians");
+ * only the n(n+1)/2 elements i <= j are estimated, then mirrored. */
+hr_status hr_est_hessian(hr_scene* sc, const double* theta, double sigma, uint64_t N,
+                         uint64_t seed, const hr_opts* opts, double* H);
+/* Hv (n doubles): |v| (g(theta + h u) - g(theta - h u)) / (2h), u = v/|v|,
+ * h = hvp_rel_step * sigma, both gradients from the same draws (section
+ * "Hessian-vector product").  v = 0 returns 0 without rendering. */
+hr_status hr_est_hvp(hr_scene* sc, const double* theta, double sigma, uint64_t N,
+                     uint64_t seed, const double* v, const hr_opts* opts, double* Hv);
+/* Hv through the sampled Hessian kernel applied to v (the epsilon -> 0 limit of
+ * the central difference): one render per draw, linear in v.  HR_AIS or
+ * HR_GAUSS only (HR_EUNSUPPORTED for HR_IS). */
+hr_status hr_est_hvp_limit(hr_scene* sc, const double* theta, double sigma, uint64_t N,
+                           uint64_t seed, const double* v, const hr_opts* opts, double* Hv);
+
+/* ---- estimators (device pointers; asynchronous on the context stream) ---- */
+/* Same results as the host versions.  d_theta, d_v: n FP64 on the device;
+ * outputs n (grad, HVP) or n*n (Hessian) FP64 on the device.  d_v == 0 gives
+ * a zero result.  dbg_loss is ignored. */
+hr_status hr_est_grad_dev(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                          uint64_t seed, const hr_opts* opts, double* d_g);
+hr_status hr_est_hessian_dev(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                             uint64_t seed, const hr_opts* opts, double* d_H);
+hr_status hr_est_hvp_dev(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                         uint64_t seed, const double* d_v, const hr_opts* opts, double* d_Hv);
+
+/* ---- Newton-CG step (section "Previous Work") ---------------------------- */
+typedef struct {
+  int cg_iters;          /* maximum inner CG iterations (default 10)                 */
+  double trust_radius;   /* Delta: each CG step length alpha <= Delta/|v| (default 1) */
+  int use_full_hessian;  /* 1: modified Newton on the estimated H (eigenvalues
+                            clamped to max(|lambda|, eig_floor)), step scaled into
+                            Delta; 0: Newton-CG with HVPs (default)                  */
+  double eig_floor;      /* default 1e-6                                             */
+  int hvp_limit;         /* 1: CG products through hr_est_hvp_limit                  */
+} hr_ncg_opts;
+
+typedef struct {
+  int iters_done;        /* HVP products used (1 in full-Hessian mode)               */
+  int hit_trust;         /* a step was truncated at Delta                            */
+  int neg_curv;          /* v^T H v <= 0 was met                                     */
+  double step_norm;      /* |theta_new - theta|                                      */
+  double g_norm;         /* |g(theta)|                                               */
+} hr_ncg_report;
+
+void hr_ncg_opts_default(hr_ncg_opts* o);
+/* One step: g = est_grad(theta); inner Fletcher-Reeves CG on H d = -g at the
+ * fixed theta with HVPs from the same seed; alpha = r^T r / v^T H v truncated
+ * to Delta/|v| (then the loop ends); v^T H v <= 0 moves to the trust boundary
+ * along v and ends; |r| <= 1e-10 |g| ends.  theta (host, n) is updated in
+ * place.  All vector arithmetic of the solve runs in FP64 on the GPU. */
+hr_status hr_newton_cg_step(hr_scene* sc, double* theta, double sigma, uint64_t N,
+                            uint64_t seed, const hr_ncg_opts* ncg, const hr_opts* opts,
+                            hr_ncg_report* report);
+/* Same with theta in device memory (updated in place). */
+hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uint64_t N,
+                                uint64_t seed, const hr_ncg_opts* ncg, const hr_opts* opts,
+                                hr_ncg_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HREST_H */

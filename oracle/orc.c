@@ -520,7 +520,22 @@ double orc_loss(const orc_scene* sc, const double* theta, uint64_t seed, uint32_
 /* ========================================================================= */
 /* Element sets: gradient K = n (element m = dimension m); Hessian K = n(n+1)/2
  * over i <= j (section "Hessians": the symmetry is exploited), enumerated row
- * by row: (0,0), (0,1), ..., (0,n-1), (1,1), ... */
+ * by row: (0,0), (0,1), ..., (0,n-1), (1,1), ...  The (i, j) of every element
+ * is listed once per estimator call in a table. */
+typedef struct { int* i; int* j; int K; } tri_table;
+
+static tri_table tri_make(int n) {
+  tri_table t;
+  t.K = n * (n + 1) / 2;
+  t.i = (int*)malloc((size_t)t.K * sizeof(int));
+  t.j = (int*)malloc((size_t)t.K * sizeof(int));
+  int idx = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) { t.i[idx] = i; t.j[idx] = j; ++idx; }
+  return t;
+}
+static void tri_free(tri_table* t) { free(t->i); free(t->j); }
+
 static void hess_ij(int n, int m, int* pi, int* pj) {
   int idx = 0;
   for (int i = 0; i < n; ++i)
@@ -542,19 +557,16 @@ static double Z_diag(double sg) { return 4.0 * exp(-0.5) / (sg * sg * sqrt(2.0 *
  * gradient eq. (gradient kernel): -tau_m / sigma^2;
  * Hessian (Hessian kernel): tau_i^2/sigma^4 - 1/sigma^2 on the diagonal and
  * tau_i tau_j / sigma^4 off it. */
-static double kfac(int hess, int n, int m, const double* tau, double sg) {
+static double kfac(int hess, const tri_table* T, int m, const double* tau, double sg) {
   double s2 = sg * sg;
   if (!hess) return -tau[m] / s2;
-  int i, j;
-  hess_ij(n, m, &i, &j);
+  int i = T->i[m], j = T->j[m];
   if (i == j) return tau[i] * tau[i] / (s2 * s2) - 1.0 / s2;
   return tau[i] * tau[j] / (s2 * s2);
 }
-static double kmass(int hess, int n, int m, double sg) {
+static double kmass(int hess, const tri_table* T, int m, double sg) {
   if (!hess) return Z_grad(sg);
-  int i, j;
-  hess_ij(n, m, &i, &j);
-  return i == j ? Z_diag(sg) : Z_grad(sg) * Z_grad(sg);
+  return T->i[m] == T->j[m] ? Z_diag(sg) : Z_grad(sg) * Z_grad(sg);
 }
 
 /* ========================================================================= */
@@ -611,20 +623,26 @@ int orc_draw_tau(int what, int n, double sigma, uint64_t seed, uint32_t s, int s
   return 0;
 }
 
-/* Weight of element m for the draw tau:
+/* Weights of all K elements for the draw tau:
  *  IS   : d_m N / p_m = sgn(d_m) Z_m
  *  AIS  : d_m N / q   with q = (1/K) sum_k |d_k| N / Z_k  (mixture of all K
  *         element densities, the "average of all stencils")
  *  GAUSS: d_m N / N = d_m */
-static double weight(int hess, int n, int m, const double* tau, double sg, int sampler) {
-  double dm = kfac(hess, n, m, tau, sg);
-  if (sampler == ORC_GAUSS) return dm;
-  if (sampler == ORC_IS) return (dm > 0.0 ? 1.0 : (dm < 0.0 ? -1.0 : 0.0)) * kmass(hess, n, m, sg);
-  int K = hess ? n * (n + 1) / 2 : n;
-  double q = 0.0;
-  for (int k = 0; k < K; ++k) q += fabs(kfac(hess, n, k, tau, sg)) / kmass(hess, n, k, sg);
-  q /= K;
-  return dm / q;
+static void weights(int hess, const tri_table* T, int K, const double* tau, double sg,
+                    int sampler, double* w) {
+  double q = 1.0;
+  if (sampler == ORC_AIS) {
+    q = 0.0;
+    for (int k = 0; k < K; ++k) q += fabs(kfac(hess, T, k, tau, sg)) / kmass(hess, T, k, sg);
+    q /= K;
+  }
+  for (int m = 0; m < K; ++m) {
+    double dm = kfac(hess, T, m, tau, sg);
+    if (sampler == ORC_GAUSS) w[m] = dm;
+    else if (sampler == ORC_IS)
+      w[m] = (dm > 0.0 ? 1.0 : (dm < 0.0 ? -1.0 : 0.0)) * kmass(hess, T, m, sg);
+    else w[m] = dm / q;
+  }
 }
 
 /* ========================================================================= */
@@ -643,6 +661,7 @@ typedef struct {
   uint64_t N, seed, s0;
   double* contrib;       /* per item: K values (AIS/GAUSS) or 1 value (IS) */
   double* dbg;
+  const tri_table* T;    /* (i, j) of the Hessian elements */
   uint64_t lo, hi;       /* item range for one worker */
 } job_t;
 
@@ -684,7 +703,7 @@ static void run_item(const job_t* J, uint64_t item) {
     double q = 1.0;
     if (J->sampler == ORC_AIS) {
       q = 0.0;
-      for (int k = 0; k < K; ++k) q += fabs(kfac(1, n, k, tau, J->sg)) / kmass(1, n, k, J->sg);
+      for (int k = 0; k < K; ++k) q += fabs(kfac(1, J->T, k, tau, J->sg)) / kmass(1, J->T, k, J->sg);
       q /= K;
     }
     double fs = 0.0;
@@ -695,31 +714,34 @@ static void run_item(const job_t* J, uint64_t item) {
       for (int j = 0; j < n; ++j) {
         int a = i < j ? i : j, b = i < j ? j : i;
         int m = a * n - a * (a - 1) / 2 + (b - a);
-        acc += J->v[j] * kfac(1, n, m, tau, J->sg);
+        acc += J->v[j] * kfac(1, J->T, m, tau, J->sg);
       }
       /* the Hessian kernel is even in tau, so both antithetic renders share it */
       c[i] = acc / q * fs;
     }
-  } else if (J->sampler == ORC_IS) {
-    int m = (int)stream;
-    double val = 0.0;
-    for (int ai = 0; ai < J->A; ++ai) {
-      double w = weight(hess_kernel, n, m, ai == 0 ? tau : ntau, J->sg, J->sampler);
-      double fv = J->what == W_HVP ? J->vnorm * (f[ai][0] - f[ai][1]) / (2.0 * J->h) : f[ai][0];
-      val += w * fv;
-    }
-    J->contrib[item] = val;
   } else {
-    double* c = J->contrib + item * (uint64_t)J->K;
-    for (int m = 0; m < J->K; ++m) {
+    double* w[2];
+    w[0] = (double*)malloc((size_t)J->K * sizeof(double));
+    w[1] = (double*)malloc((size_t)J->K * sizeof(double));
+    for (int ai = 0; ai < J->A; ++ai)
+      weights(hess_kernel, J->T, J->K, ai == 0 ? tau : ntau, J->sg, J->sampler, w[ai]);
+    double fv[2];
+    for (int ai = 0; ai < J->A; ++ai)
+      fv[ai] = J->what == W_HVP ? J->vnorm * (f[ai][0] - f[ai][1]) / (2.0 * J->h) : f[ai][0];
+    if (J->sampler == ORC_IS) {
+      int m = (int)stream;
       double val = 0.0;
-      for (int ai = 0; ai < J->A; ++ai) {
-        double w = weight(hess_kernel, n, m, ai == 0 ? tau : ntau, J->sg, J->sampler);
-        double fv = J->what == W_HVP ? J->vnorm * (f[ai][0] - f[ai][1]) / (2.0 * J->h) : f[ai][0];
-        val += w * fv;
+      for (int ai = 0; ai < J->A; ++ai) val += w[ai][m] * fv[ai];
+      J->contrib[item] = val;
+    } else {
+      double* c = J->contrib + item * (uint64_t)J->K;
+      for (int m = 0; m < J->K; ++m) {
+        double val = 0.0;
+        for (int ai = 0; ai < J->A; ++ai) val += w[ai][m] * fv[ai];
+        c[m] = val;
       }
-      c[m] = val;
     }
+    free(w[0]); free(w[1]);
   }
   (void)elem;
   free(tau); free(ntau); free(p);
@@ -786,6 +808,8 @@ static int run_estimator(const orc_scene* sc, int what, const double* theta, dou
   uint64_t per_item = (o->sampler == ORC_IS && what != W_HVPL) ? 1 : (uint64_t)(what == W_HVPL ? n : K);
   J.contrib = (double*)malloc(items * per_item * sizeof(double));
   if (!J.contrib) { free(u); return -2; }
+  tri_table tri = tri_make(n);
+  J.T = &tri;
 
   int T = o->nthreads > 0 ? o->nthreads : 1;
   if ((uint64_t)T > items) T = (int)items;
@@ -814,15 +838,14 @@ static int run_estimator(const orc_scene* sc, int what, const double* theta, dou
   }
   if (what == W_HESS) {   /* mirror the upper triangle */
     for (int m = 0; m < K; ++m) {
-      int i, j;
-      hess_ij(n, m, &i, &j);
-      out[i * n + j] = est[m];
-      out[j * n + i] = est[m];
+      out[tri.i[m] * n + tri.j[m]] = est[m];
+      out[tri.j[m] * n + tri.i[m]] = est[m];
     }
   } else {
     for (int m = 0; m < n; ++m) out[m] = est[m];
   }
   free(est); free(J.contrib); free(th); free(jobs); free(u);
+  tri_free(&tri);
   return 0;
 }
 

@@ -1,0 +1,668 @@
+// hr_api.hip -- host runtime behind include/hrest.h: contexts, device-resident
+// scenes, workspace carving, the estimator pipeline
+//   draw tau -> perturbed renders + per-render loss -> per-draw weights ->
+//   compensated lobe sums -> FP64 finalisation
+// and the Newton-CG driver whose vector arithmetic runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hrest.h"
+#include "hr_kernels.h"
+
+using namespace hr;
+
+namespace {
+
+thread_local std::string g_err;
+
+hr_status fail(hr_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HR_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(HR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct hr_ctx {
+  int device = 0;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* stage = nullptr;      // host-call staging: theta, v, outputs
+  size_t stage_bytes = 0;
+  void* cg = nullptr;         // Newton-CG vectors and state
+  size_t cg_bytes = 0;
+  uint64_t budget = 64ull << 30;
+  bool timing = false;
+  struct Pending { std::string name; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<uint64_t, double>> stats;
+};
+
+enum SceneKind { kDisks = 0, kPT = 1, kQuad = 2, kNegGauss = 3 };
+
+struct hr_scene {
+  hr_ctx* ctx = nullptr;
+  int kind = kDisks;
+  int n = 0;
+  int W = 0, H = 0, C = 0;
+  float* target = nullptr;
+  int D = 0, ppd = 0;
+  float* colors = nullptr;
+  float* radius = nullptr;
+  std::vector<float> hradius;
+  int spp = 0, nspheres = 0;
+  std::vector<float> pt_desc;   // FP32 description + derived camera basis
+  double* A = nullptr;
+  double* b = nullptr;
+  double c = 0.0, s1 = 1.0;
+};
+
+namespace {
+
+hr_status ensure(hr_ctx* ctx, void** buf, size_t* have, size_t need) {
+  if (need <= *have) return HR_OK;
+  if (*buf) {
+    HR_HIP(hipStreamSynchronize(ctx->stream));
+    HR_HIP(hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+  }
+  size_t sz = align256(need + need / 4);
+  hipError_t e = hipMalloc(buf, sz);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    (void)hipGetLastError();
+    return fail(HR_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+  }
+  *have = sz;
+  return HR_OK;
+}
+
+template <class F>
+void timed(hr_ctx* ctx, const char* name, F&& fn) {
+  if (!ctx->timing) {
+    fn();
+    return;
+  }
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) { fn(); return; }
+  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); fn(); return; }
+  (void)hipEventRecord(a, ctx->stream);
+  fn();
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->pending.push_back({name, a, b});
+}
+
+hr_status drain_timers(hr_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    HR_HIP(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    HR_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& s = ctx->stats[p.name];
+    s.first += 1;
+    s.second += ms;
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  ctx->pending.clear();
+  return HR_OK;
+}
+
+bool finite_all(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+hr_opts resolve(const hr_opts* o) {
+  hr_opts r;
+  hr_opts_default(&r);
+  if (o) r = *o;
+  return r;
+}
+
+// the estimator pipeline on device pointers
+hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, uint64_t N,
+                  uint64_t seed, const double* d_v, const hr_opts& o, double* d_out,
+                  double* h_dbg, double* h_tau) {
+  hr_ctx* ctx = sc->ctx;
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(HR_EINVAL, "sigma must be positive and finite");
+  if (N == 0 || N >= 0xFFFFFFFFull) return fail(HR_EINVAL, "N must be in [1, 2^32 - 1)");
+  if (o.sampler < 0 || o.sampler > 2) return fail(HR_EINVAL, "unknown sampler");
+  if ((what == kHvp || what == kHvpLimit) && !d_v) return fail(HR_EINVAL, "v is NULL");
+  if (what == kHvpLimit && o.sampler == kIS)
+    return fail(HR_EUNSUPPORTED, "the limit-kernel HVP supports the aggregate and Gaussian samplers");
+  if (what == kHvp && !(o.hvp_rel_step > 0.0) ) return fail(HR_EINVAL, "hvp_rel_step must be positive");
+  if (sc->n < 1 || sc->n > 6144) return fail(HR_EINVAL, "parameter count out of range");
+  HR_HIP(hipSetDevice(ctx->device));
+
+  EstShape e{};
+  e.what = what;
+  e.sampler = o.sampler;
+  e.n = sc->n;
+  e.hessk = (what == kHess || what == kHvpLimit) ? 1 : 0;
+  e.K = e.hessk ? e.n * (e.n + 1) / 2 : e.n;
+  e.nout = what == kHess ? e.K : e.n;
+  e.N = N;
+  e.streams = (o.sampler == kIS && what != kHvpLimit) ? (uint64_t)e.K : 1;
+  e.A = o.antithetic ? 2 : 1;
+  e.NH = what == kHvp ? 2 : 1;
+  e.R = e.streams * N * (uint64_t)e.A * (uint64_t)e.NH;
+  e.sigma = sigma;
+  e.h = what == kHvp ? o.hvp_rel_step * sigma : 0.0;
+  e.seed = seed;
+
+  const int chunk = accum_chunk(e);
+  const uint64_t nchunks = (N + chunk - 1) / chunk;
+  const int tiles = sc->kind == kDisks ? raster_tiles(sc->W, sc->H)
+                    : sc->kind == kPT  ? pt_tiles(sc->W, sc->H)
+                                       : 0;
+  const size_t b_tau = align256(e.streams * N * (uint64_t)e.n * 8);
+  const size_t b_u = align256((size_t)e.n * 8 + 8);
+  const size_t b_rec = sc->kind == kDisks ? align256(e.R * (uint64_t)sc->D * 16) : 0;
+  const size_t b_part = tiles ? align256(e.R * (uint64_t)tiles * 4) : 0;
+  const size_t b_f = align256(e.R * 8);
+  const size_t b_Fq = align256(e.streams * N * 8);
+  const size_t b_vt = align256(N * 8);
+  const size_t b_acc = align256(nchunks * (uint64_t)e.nout * 16);
+  const size_t total = b_tau + b_u + b_rec + b_part + b_f + b_Fq + b_vt + b_acc;
+  if (total > ctx->budget)
+    return fail(HR_ENOMEM, "request needs " + std::to_string(total) + " bytes of workspace, budget is " +
+                               std::to_string(ctx->budget));
+  hr_status st = ensure(ctx, &ctx->ws, &ctx->ws_bytes, total);
+  if (st) return st;
+  char* p = (char*)ctx->ws;
+  double* tau = (double*)p; p += b_tau;
+  double* u = (double*)p;
+  double* vnorm = u + e.n;
+  p += b_u;
+  float4* rec = (float4*)p; p += b_rec;
+  float* partial = (float*)p; p += b_part;
+  double* f = (double*)p; p += b_f;
+  double* Fq = (double*)p; p += b_Fq;
+  double* vt = (double*)p; p += b_vt;
+  void* acc = (void*)p;
+
+  hipStream_t s = ctx->stream;
+  if (what == kHvp || what == kHvpLimit) launch_vnorm(s, e.n, d_v, u, vnorm);
+  timed(ctx, "sample", [&] { launch_sample(s, e, tau); });
+  const int spb = o.samples_per_block;
+  if (sc->kind == kDisks) {
+    DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};
+    timed(ctx, "records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
+    RasterExact ex{d_theta, tau, u, sc->radius, e.n, sc->ppd, e.A, e.NH, e.h};
+    timed(ctx, "raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, ex, partial); });
+    launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
+  } else if (sc->kind == kPT) {
+    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data()};
+    timed(ctx, "pt_loss", [&] { launch_pt_loss(s, e, ps, d_theta, tau, u, spb, partial); });
+    launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f);
+  } else {
+    AnalyticScene as{sc->kind == kQuad ? 0 : 1, sc->n, sc->A, sc->b, sc->c, sc->s1};
+    launch_analytic(s, e, as, d_theta, tau, u, f);
+  }
+  launch_prep(s, e, f, tau, vnorm, d_v, Fq, vt);
+  timed(ctx, "accumulate", [&] { launch_accum(s, e, tau, Fq, vt, d_v, o.accum_fp64, acc, chunk); });
+  launch_finalize(s, e, acc, o.accum_fp64, chunk, d_out);
+  HR_HIP(hipGetLastError());
+  if (h_dbg) HR_HIP(hipMemcpyAsync(h_dbg, f, e.R * 8, hipMemcpyDeviceToHost, s));
+  if (h_tau) HR_HIP(hipMemcpyAsync(h_tau, tau, e.streams * N * (uint64_t)e.n * 8, hipMemcpyDeviceToHost, s));
+  if (h_dbg || h_tau) HR_HIP(hipStreamSynchronize(s));
+  return HR_OK;
+}
+
+// host-pointer wrapper: stage theta / v, run, copy the result back
+hr_status run_host(hr_scene* sc, int what, const double* theta, double sigma, uint64_t N,
+                   uint64_t seed, const double* v, const hr_opts* opts, double* out) {
+  if (!sc || !theta || !out) return fail(HR_EINVAL, "NULL argument");
+  const int n = sc->n;
+  if (!finite_all(theta, n)) return fail(HR_EINVAL, "theta has a non-finite entry");
+  if (what == kHvp || what == kHvpLimit) {
+    if (!v) return fail(HR_EINVAL, "v is NULL");
+    if (!finite_all(v, n)) return fail(HR_EINVAL, "v has a non-finite entry");
+  }
+  hr_opts o = resolve(opts);
+  hr_ctx* ctx = sc->ctx;
+  HR_HIP(hipSetDevice(ctx->device));
+  const size_t nout = what == kHess ? (size_t)n * n : (size_t)n;
+  if (what == kHvp || what == kHvpLimit) {
+    bool zero = true;
+    for (int i = 0; i < n; ++i) zero = zero && v[i] == 0.0;
+    if (zero && sigma > 0.0 && std::isfinite(sigma) && N > 0 && N < 0xFFFFFFFFull) {
+      for (size_t i = 0; i < nout; ++i) out[i] = 0.0;
+      return HR_OK;
+    }
+  }
+  hr_status st = ensure(ctx, &ctx->stage, &ctx->stage_bytes, (2 * (size_t)n + nout) * 8);
+  if (st) return st;
+  double* d_theta = (double*)ctx->stage;
+  double* d_v = d_theta + n;
+  double* d_out = d_v + n;
+  HR_HIP(hipMemcpyAsync(d_theta, theta, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+  if (v) HR_HIP(hipMemcpyAsync(d_v, v, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+  st = run_est(sc, what, d_theta, sigma, N, seed, v ? d_v : nullptr, o, d_out, o.dbg_loss, o.dbg_tau);
+  if (st) return st;
+  HR_HIP(hipMemcpyAsync(out, d_out, nout * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HR_HIP(hipStreamSynchronize(ctx->stream));
+  return HR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hr_opts_default(hr_opts* o) {
+  if (!o) return;
+  o->sampler = HR_AIS;
+  o->antithetic = 1;
+  o->hvp_rel_step = 0.1;
+  o->accum_fp64 = 0;
+  o->samples_per_block = 0;
+  o->dbg_loss = nullptr;
+  o->dbg_tau = nullptr;
+}
+
+void hr_ncg_opts_default(hr_ncg_opts* o) {
+  if (!o) return;
+  o->cg_iters = 10;
+  o->trust_radius = 1.0;
+  o->use_full_hessian = 0;
+  o->eig_floor = 1e-6;
+  o->hvp_limit = 0;
+}
+
+const char* hr_last_error(void) { return g_err.c_str(); }
+
+hr_status hr_ctx_create(int device, hr_ctx** out) {
+  if (!out) return fail(HR_EINVAL, "out is NULL");
+  int count = 0;
+  HR_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(HR_EINVAL, "no such device");
+  HR_HIP(hipSetDevice(device));
+  hr_ctx* c = new hr_ctx();
+  c->device = device;
+  hipError_t e = hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(HR_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+  }
+  c->stream = c->own;
+  *out = c;
+  return HR_OK;
+}
+
+void hr_ctx_destroy(hr_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)drain_timers(ctx);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->stage) (void)hipFree(ctx->stage);
+  if (ctx->cg) (void)hipFree(ctx->cg);
+  if (ctx->own) (void)hipStreamDestroy(ctx->own);
+  delete ctx;
+}
+
+hr_status hr_ctx_set_stream(hr_ctx* ctx, void* stream) {
+  if (!ctx) return fail(HR_EINVAL, "ctx is NULL");
+  ctx->stream = stream ? (hipStream_t)stream : ctx->own;
+  return HR_OK;
+}
+
+hr_status hr_ctx_set_memory_budget(hr_ctx* ctx, uint64_t bytes) {
+  if (!ctx || bytes == 0) return fail(HR_EINVAL, "bad budget");
+  ctx->budget = bytes;
+  return HR_OK;
+}
+
+hr_status hr_ctx_synchronize(hr_ctx* ctx) {
+  if (!ctx) return fail(HR_EINVAL, "ctx is NULL");
+  HR_HIP(hipSetDevice(ctx->device));
+  HR_HIP(hipStreamSynchronize(ctx->stream));
+  return HR_OK;
+}
+
+hr_status hr_ctx_enable_timing(hr_ctx* ctx, int enable) {
+  if (!ctx) return fail(HR_EINVAL, "ctx is NULL");
+  ctx->timing = enable != 0;
+  return HR_OK;
+}
+
+hr_status hr_ctx_kernel_stats(hr_ctx* ctx, const char* name, uint64_t* launches, double* total_ms) {
+  if (!ctx || !name) return fail(HR_EINVAL, "NULL argument");
+  hr_status st = drain_timers(ctx);
+  if (st) return st;
+  auto it = ctx->stats.find(name);
+  if (launches) *launches = it == ctx->stats.end() ? 0 : it->second.first;
+  if (total_ms) *total_ms = it == ctx->stats.end() ? 0.0 : it->second.second;
+  return HR_OK;
+}
+
+hr_status hr_ctx_reset_stats(hr_ctx* ctx) {
+  if (!ctx) return fail(HR_EINVAL, "ctx is NULL");
+  hr_status st = drain_timers(ctx);
+  ctx->stats.clear();
+  return st;
+}
+
+// ---------------------------------------------------------- device memory
+hr_status hr_dev_alloc(hr_ctx* ctx, size_t bytes, void** out) {
+  if (!ctx || !out || bytes == 0) return fail(HR_EINVAL, "bad allocation request");
+  HR_HIP(hipSetDevice(ctx->device));
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return fail(HR_ENOMEM, "device allocation failed");
+  }
+  return HR_OK;
+}
+
+hr_status hr_dev_free(hr_ctx* ctx, void* ptr) {
+  if (!ctx) return fail(HR_EINVAL, "ctx is NULL");
+  if (!ptr) return HR_OK;
+  HR_HIP(hipSetDevice(ctx->device));
+  HR_HIP(hipStreamSynchronize(ctx->stream));
+  HR_HIP(hipFree(ptr));
+  return HR_OK;
+}
+
+hr_status hr_memcpy(hr_ctx* ctx, void* dst, const void* src, size_t bytes, int kind) {
+  if (!ctx || (!dst && bytes) || (!src && bytes)) return fail(HR_EINVAL, "NULL argument");
+  if (kind < 0 || kind > 2) return fail(HR_EINVAL, "kind must be 0, 1 or 2");
+  if (bytes == 0) return HR_OK;
+  HR_HIP(hipSetDevice(ctx->device));
+  const hipMemcpyKind k = kind == 0 ? hipMemcpyHostToDevice
+                          : kind == 1 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  HR_HIP(hipMemcpyAsync(dst, src, bytes, k, ctx->stream));
+  HR_HIP(hipStreamSynchronize(ctx->stream));
+  return HR_OK;
+}
+
+// ---------------------------------------------------------------- scenes
+static hr_status upload(const void* src, size_t bytes, void** dst) {
+  HR_HIP(hipMalloc(dst, bytes));
+  HR_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return HR_OK;
+}
+
+hr_status hr_scene_disks(hr_ctx* ctx, int W, int H, int C, int D, int ppd, const float* radius,
+                         const float* colors, const float* target, hr_scene** out) {
+  if (!ctx || !out || !colors || !target) return fail(HR_EINVAL, "NULL argument");
+  if (W <= 0 || H <= 0 || W > 16384 || H > 16384) return fail(HR_EINVAL, "bad image size");
+  if (C < 1 || C > 4) return fail(HR_EINVAL, "channels must be 1..4");
+  if (D < 1 || D > 1024) return fail(HR_EINVAL, "disk count must be 1..1024");
+  if (ppd != 2 && ppd != 3) return fail(HR_EINVAL, "params_per_disk must be 2 or 3");
+  if (ppd == 2 && !radius) return fail(HR_EINVAL, "radius is NULL");
+  HR_HIP(hipSetDevice(ctx->device));
+  hr_scene* sc = new hr_scene();
+  sc->ctx = ctx;
+  sc->kind = kDisks;
+  sc->W = W; sc->H = H; sc->C = C; sc->D = D; sc->ppd = ppd;
+  sc->n = D * ppd;
+  hr_status st = upload(target, (size_t)W * H * C * 4, (void**)&sc->target);
+  if (!st) st = upload(colors, (size_t)D * C * 4, (void**)&sc->colors);
+  if (!st && ppd == 2) {
+    st = upload(radius, (size_t)D * 4, (void**)&sc->radius);
+    sc->hradius.assign(radius, radius + D);
+  }
+  if (st) { hr_scene_destroy(sc); return st; }
+  *out = sc;
+  return HR_OK;
+}
+
+hr_status hr_scene_pt(hr_ctx* ctx, int W, int H, int spp, int nspheres, const double* desc,
+                      const float* target, hr_scene** out) {
+  if (!ctx || !out || !desc || !target) return fail(HR_EINVAL, "NULL argument");
+  if (W <= 0 || H <= 0 || W > 8192 || H > 8192) return fail(HR_EINVAL, "bad image size");
+  if (spp < 1 || spp > 65536) return fail(HR_EINVAL, "spp must be 1..65536");
+  if (nspheres < 1 || nspheres > 16) return fail(HR_EINVAL, "nspheres must be 1..16");
+  if (!finite_all(desc, 12 + 7 * (size_t)nspheres)) return fail(HR_EINVAL, "non-finite description");
+  HR_HIP(hipSetDevice(ctx->device));
+  hr_scene* sc = new hr_scene();
+  sc->ctx = ctx;
+  sc->kind = kPT;
+  sc->W = W; sc->H = H; sc->C = 3; sc->spp = spp; sc->nspheres = nspheres;
+  sc->n = 6;
+  // camera basis in FP64, stored as FP32: fwd = unit(look - eye),
+  // right = unit(fwd x (0,1,0)), up = right x fwd
+  double f[3] = {desc[3] - desc[0], desc[4] - desc[1], desc[5] - desc[2]};
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  for (double& x : f) x /= fl;
+  double r[3] = {-f[2], 0.0, f[0]};   // fwd x (0,1,0)
+  double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  for (double& x : r) x /= rl;
+  double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+  const double th = std::tan(0.5 * desc[6] * 3.14159265358979323846 / 180.0);
+  std::vector<float>& d = sc->pt_desc;
+  d.assign(23 + 7 * nspheres, 0.0f);
+  for (int i = 0; i < 12; ++i) d[i] = (float)desc[i];
+  for (int i = 0; i < 3; ++i) {
+    d[12 + i] = (float)f[i];
+    d[15 + i] = (float)r[i];
+    d[18 + i] = (float)u[i];
+  }
+  d[21] = (float)(th * (double)W / (double)H);
+  d[22] = (float)th;
+  for (int i = 0; i < 7 * nspheres; ++i) d[23 + i] = (float)desc[12 + i];
+  hr_status st = upload(target, (size_t)W * H * 3 * 4, (void**)&sc->target);
+  if (st) { hr_scene_destroy(sc); return st; }
+  *out = sc;
+  return HR_OK;
+}
+
+hr_status hr_scene_quad(hr_ctx* ctx, int n, const double* A, const double* b, double c,
+                        hr_scene** out) {
+  if (!ctx || !out || !A) return fail(HR_EINVAL, "NULL argument");
+  if (n < 1 || n > 128) return fail(HR_EINVAL, "n must be 1..128");
+  HR_HIP(hipSetDevice(ctx->device));
+  hr_scene* sc = new hr_scene();
+  sc->ctx = ctx;
+  sc->kind = kQuad;
+  sc->n = n;
+  sc->c = c;
+  std::vector<double> bb(n, 0.0);
+  if (b) bb.assign(b, b + n);
+  hr_status st = upload(A, (size_t)n * n * 8, (void**)&sc->A);
+  if (!st) st = upload(bb.data(), (size_t)n * 8, (void**)&sc->b);
+  if (st) { hr_scene_destroy(sc); return st; }
+  *out = sc;
+  return HR_OK;
+}
+
+hr_status hr_scene_neggauss(hr_ctx* ctx, int n, double s1, hr_scene** out) {
+  if (!ctx || !out) return fail(HR_EINVAL, "NULL argument");
+  if (n < 1 || n > 128 || !(s1 > 0.0) || !std::isfinite(s1)) return fail(HR_EINVAL, "bad negated-Gaussian scene");
+  hr_scene* sc = new hr_scene();
+  sc->ctx = ctx;
+  sc->kind = kNegGauss;
+  sc->n = n;
+  sc->s1 = s1;
+  *out = sc;
+  return HR_OK;
+}
+
+void hr_scene_destroy(hr_scene* sc) {
+  if (!sc) return;
+  (void)hipSetDevice(sc->ctx->device);
+  (void)hipStreamSynchronize(sc->ctx->stream);
+  if (sc->target) (void)hipFree(sc->target);
+  if (sc->colors) (void)hipFree(sc->colors);
+  if (sc->radius) (void)hipFree(sc->radius);
+  if (sc->A) (void)hipFree(sc->A);
+  if (sc->b) (void)hipFree(sc->b);
+  delete sc;
+}
+
+int hr_scene_nparams(const hr_scene* sc) { return sc ? sc->n : -1; }
+
+hr_status hr_render(hr_scene* sc, const double* theta, uint64_t seed, uint32_t s, int spp,
+                    float* image) {
+  if (!sc || !theta || !image) return fail(HR_EINVAL, "NULL argument");
+  if (sc->kind != kDisks && sc->kind != kPT) return fail(HR_EUNSUPPORTED, "analytic scenes have no image");
+  if (!finite_all(theta, sc->n)) return fail(HR_EINVAL, "theta has a non-finite entry");
+  hr_ctx* ctx = sc->ctx;
+  HR_HIP(hipSetDevice(ctx->device));
+  const size_t img = (size_t)sc->W * sc->H * sc->C * 4;
+  hr_status st = ensure(ctx, &ctx->ws, &ctx->ws_bytes, align256(img) + (size_t)sc->n * 8);
+  if (st) return st;
+  float* d_img = (float*)ctx->ws;
+  if (sc->kind == kDisks) {
+    double* d_theta = (double*)((char*)ctx->ws + align256(img));
+    HR_HIP(hipMemcpyAsync(d_theta, theta, (size_t)sc->n * 8, hipMemcpyHostToDevice, ctx->stream));
+    DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};
+    RasterExact ex{d_theta, nullptr, nullptr, sc->radius, sc->n, sc->ppd, 1, 1, 0.0};
+    launch_render_disks(ctx->stream, ds, ex, d_img);
+  } else {
+    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data()};
+    launch_pt_render(ctx->stream, ps, theta, seed, s, spp > 0 ? spp : sc->spp, d_img);
+  }
+  HR_HIP(hipGetLastError());
+  HR_HIP(hipMemcpyAsync(image, d_img, img, hipMemcpyDeviceToHost, ctx->stream));
+  HR_HIP(hipStreamSynchronize(ctx->stream));
+  return HR_OK;
+}
+
+// ------------------------------------------------------------ estimators
+hr_status hr_est_grad(hr_scene* sc, const double* theta, double sigma, uint64_t N, uint64_t seed,
+                      const hr_opts* opts, double* g) {
+  return run_host(sc, kGrad, theta, sigma, N, seed, nullptr, opts, g);
+}
+hr_status hr_est_hessian(hr_scene* sc, const double* theta, double sigma, uint64_t N,
+                         uint64_t seed, const hr_opts* opts, double* H) {
+  return run_host(sc, kHess, theta, sigma, N, seed, nullptr, opts, H);
+}
+hr_status hr_est_hvp(hr_scene* sc, const double* theta, double sigma, uint64_t N, uint64_t seed,
+                     const double* v, const hr_opts* opts, double* Hv) {
+  return run_host(sc, kHvp, theta, sigma, N, seed, v, opts, Hv);
+}
+hr_status hr_est_hvp_limit(hr_scene* sc, const double* theta, double sigma, uint64_t N,
+                           uint64_t seed, const double* v, const hr_opts* opts, double* Hv) {
+  return run_host(sc, kHvpLimit, theta, sigma, N, seed, v, opts, Hv);
+}
+
+hr_status hr_est_grad_dev(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                          uint64_t seed, const hr_opts* opts, double* d_g) {
+  if (!sc || !d_theta || !d_g) return fail(HR_EINVAL, "NULL argument");
+  hr_opts o = resolve(opts);
+  o.dbg_loss = nullptr;
+  o.dbg_tau = nullptr;
+  return run_est(sc, kGrad, d_theta, sigma, N, seed, nullptr, o, d_g, nullptr, nullptr);
+}
+hr_status hr_est_hessian_dev(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                             uint64_t seed, const hr_opts* opts, double* d_H) {
+  if (!sc || !d_theta || !d_H) return fail(HR_EINVAL, "NULL argument");
+  hr_opts o = resolve(opts);
+  o.dbg_loss = nullptr;
+  o.dbg_tau = nullptr;
+  return run_est(sc, kHess, d_theta, sigma, N, seed, nullptr, o, d_H, nullptr, nullptr);
+}
+hr_status hr_est_hvp_dev(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                         uint64_t seed, const double* d_v, const hr_opts* opts, double* d_Hv) {
+  if (!sc || !d_theta || !d_v || !d_Hv) return fail(HR_EINVAL, "NULL argument");
+  hr_opts o = resolve(opts);
+  o.dbg_loss = nullptr;
+  o.dbg_tau = nullptr;
+  return run_est(sc, kHvp, d_theta, sigma, N, seed, d_v, o, d_Hv, nullptr, nullptr);
+}
+
+// ------------------------------------------------------------ Newton-CG
+hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uint64_t N,
+                                uint64_t seed, const hr_ncg_opts* ncg, const hr_opts* opts,
+                                hr_ncg_report* report) {
+  if (!sc || !d_theta) return fail(HR_EINVAL, "NULL argument");
+  hr_ncg_opts no;
+  hr_ncg_opts_default(&no);
+  if (ncg) no = *ncg;
+  if (!(no.trust_radius > 0.0) || !std::isfinite(no.trust_radius))
+    return fail(HR_EINVAL, "trust_radius must be positive");
+  if (no.cg_iters < 0 || no.cg_iters > 10000) return fail(HR_EINVAL, "cg_iters out of range");
+  if (!(no.eig_floor >= 0.0)) return fail(HR_EINVAL, "eig_floor must be >= 0");
+  hr_opts o = resolve(opts);
+  o.dbg_loss = nullptr;
+  o.dbg_tau = nullptr;
+  hr_ctx* ctx = sc->ctx;
+  HR_HIP(hipSetDevice(ctx->device));
+  const int n = sc->n;
+  const size_t nv = align256((size_t)n * 8);
+  const size_t need = 5 * nv + align256((size_t)n * n * 8) * 3 + align256(sizeof(CgState));
+  hr_status st = ensure(ctx, &ctx->cg, &ctx->cg_bytes, need);
+  if (st) return st;
+  char* p = (char*)ctx->cg;
+  double* g = (double*)p; p += nv;
+  double* r = (double*)p; p += nv;
+  double* pv = (double*)p; p += nv;
+  double* d = (double*)p; p += nv;
+  double* Hp = (double*)p; p += nv;
+  double* Hm = (double*)p; p += align256((size_t)n * n * 8);
+  double* work = (double*)p; p += 2 * align256((size_t)n * n * 8);
+  CgState* cs = (CgState*)p;
+  hipStream_t s = ctx->stream;
+
+  st = run_est(sc, kGrad, d_theta, sigma, N, seed, nullptr, o, g, nullptr, nullptr);
+  if (st) return st;
+  CgState h{};
+  if (no.use_full_hessian) {
+    st = run_est(sc, kHess, d_theta, sigma, N, seed, nullptr, o, Hm, nullptr, nullptr);
+    if (st) return st;
+    launch_newton_full(s, n, Hm, g, no.trust_radius, no.eig_floor, work, d, cs);
+  } else {
+    launch_cg_init(s, n, g, no.trust_radius, r, pv, d, cs);
+    for (int k = 0; k < no.cg_iters; ++k) {
+      HR_HIP(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      HR_HIP(hipStreamSynchronize(s));
+      if (h.stop) break;
+      st = run_est(sc, no.hvp_limit ? kHvpLimit : kHvp, d_theta, sigma, N, seed, pv, o, Hp, nullptr, nullptr);
+      if (st) return st;
+      launch_cg_update(s, n, Hp, r, pv, d, cs);
+    }
+  }
+  launch_cg_apply(s, n, d, d_theta, cs);
+  HR_HIP(hipGetLastError());
+  HR_HIP(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, s));
+  HR_HIP(hipStreamSynchronize(s));
+  if (report) {
+    report->iters_done = h.iters;
+    report->hit_trust = h.hit_trust;
+    report->neg_curv = h.neg_curv;
+    report->step_norm = h.step_norm;
+    report->g_norm = h.gnorm;
+  }
+  return HR_OK;
+}
+
+hr_status hr_newton_cg_step(hr_scene* sc, double* theta, double sigma, uint64_t N, uint64_t seed,
+                            const hr_ncg_opts* ncg, const hr_opts* opts, hr_ncg_report* report) {
+  if (!sc || !theta) return fail(HR_EINVAL, "NULL argument");
+  const int n = sc->n;
+  if (!finite_all(theta, n)) return fail(HR_EINVAL, "theta has a non-finite entry");
+  hr_ctx* ctx = sc->ctx;
+  HR_HIP(hipSetDevice(ctx->device));
+  hr_status st = ensure(ctx, &ctx->stage, &ctx->stage_bytes, (size_t)n * 8 * 3 + (size_t)n * n * 8);
+  if (st) return st;
+  double* d_theta = (double*)ctx->stage;
+  HR_HIP(hipMemcpyAsync(d_theta, theta, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+  st = hr_newton_cg_step_dev(sc, d_theta, sigma, N, seed, ncg, opts, report);
+  if (st) return st;
+  HR_HIP(hipMemcpyAsync(theta, d_theta, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HR_HIP(hipStreamSynchronize(ctx->stream));
+  return HR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// hr_estim.hip -- draws, analytic test scenes, lobe weights and accumulation.
+//
+// Estimator (sections "Gradients", "Hessians", "Hessian-vector product",
+// "Aggregate" of Wang, Fischer, Ritschel 2025), for element m with kernel
+// factor d_m (D kappa_m(tau) = d_m(tau) N(tau)):
+//   est_m = 1/(A N) sum_s sum_a w_m(a tau_s) F(theta - a tau_s)
+//   IS    : w_m = sgn(d_m) Z_m     AIS: w_m = d_m / q,  q = 1/K sum_k |d_k|/Z_k
+//   GAUSS : w_m = d_m
+// Gradient factors are odd in tau and Hessian factors even, so the antithetic
+// partner's weight is -w or +w; per draw the renders collapse to one scalar F_s.
+// Contributions c = d_m F_s / q are rounded to FP32 and summed per chunk of
+// draws into positive and negative lobe sums with TwoSum compensation
+// (or in FP64); the chunk sums are combined in fixed order in FP64.
+#include "hr_device.h"
+#include "hr_kernels.h"
+
+namespace hr {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+inline unsigned grid_for(uint64_t total, int block) {
+  uint64_t g = (total + block - 1) / block;
+  return (unsigned)(g > 65536u * 16u ? 65536u * 16u : (g == 0 ? 1 : g));
+}
+
+// one thread per (stream, draw, dimension)
+__global__ void k_sample(int n, int K, int hessk, int sampler, uint64_t N, uint64_t seed,
+                         double sg, uint64_t total, double* __restrict__ tau) {
+  for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
+       gid += (uint64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(gid % (uint64_t)n);
+    const uint64_t sidx = gid / (uint64_t)n;
+    const uint32_t stream = (uint32_t)(sidx / N);
+    const uint32_t s = (uint32_t)(sidx % N);
+    const uint32_t tag = sampler == kIS ? stream : (sampler == kAIS ? kTagAIS : kTagGauss);
+    const u32x4 w = philox_seeded(seed, s, (uint32_t)j, 0u, tag);
+    int m = -1;
+    if (sampler == kIS) m = (int)stream;
+    if (sampler == kAIS) {
+      const u32x4 ws = philox_seeded(seed, s, kDimSelect, 0u, tag);
+      m = (int)(((uint64_t)ws.x * (uint64_t)K) >> 32);
+    }
+    bool lg = false, ld = false;
+    if (m >= 0) {
+      if (!hessk) {
+        lg = (j == m);
+      } else {
+        int i, jj;
+        tri_ij(n, m, i, jj);
+        if (i == jj) ld = (j == i);
+        else lg = (j == i || j == jj);
+      }
+    }
+    double t;
+    if (ld) t = hdiag_lobe(w.z, sg);
+    else if (lg) t = grad_lobe(w.z, sg);
+    else t = sg * sqrt(-2.0 * log(u01_d(w.x))) * cos(2.0 * kPi * u01_d(w.y));
+    tau[gid] = t;
+  }
+}
+
+__global__ void k_vnorm(int n, const double* __restrict__ v, double* __restrict__ u,
+                        double* __restrict__ vnorm) {
+  __shared__ double s_acc[256];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) acc += v[j] * v[j];
+  s_acc[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) s_acc[threadIdx.x] += s_acc[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double nv = sqrt(s_acc[0]);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) u[j] = nv > 0.0 ? v[j] / nv : 0.0;
+  if (threadIdx.x == 0) *vnorm = nv;
+}
+
+// analytic scenes: one thread per render, FP64
+__global__ void k_analytic(int kind, int n, const double* __restrict__ A,
+                           const double* __restrict__ b, double c, double s1,
+                           const double* __restrict__ theta, const double* __restrict__ tau,
+                           const double* __restrict__ u, int Aa, int NH, double h, uint64_t R,
+                           double* __restrict__ f) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < R;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    const int sh = (int)(r % (uint64_t)NH);
+    const uint64_t rem = r / (uint64_t)NH;
+    const int ai = (int)(rem % (uint64_t)Aa);
+    const uint64_t sidx = rem / (uint64_t)Aa;
+    const double* t = tau + sidx * (uint64_t)n;
+    const double a = ai == 0 ? 1.0 : -1.0;
+    const double shift = sh == 0 ? h : -h;
+    auto P = [&](int j) {
+      double base = theta[j];
+      if (NH == 2) base = base + shift * u[j];
+      return base - a * t[j];
+    };
+    double val;
+    if (kind == 0) {
+      val = c;
+      for (int i = 0; i < n; ++i) {
+        const double pi = P(i);
+        val += b[i] * pi;
+        for (int j = 0; j < n; ++j) val += 0.5 * pi * A[i * n + j] * P(j);
+      }
+    } else {
+      double r2 = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double pi = P(i);
+        r2 += pi * pi;
+      }
+      val = -pow(2.0 * kPi * s1 * s1, -0.5 * n) * exp(-r2 / (2.0 * s1 * s1));
+    }
+    f[r] = val;
+  }
+}
+
+__device__ __forceinline__ double z_grad(double sg) { return sqrt(2.0 / kPi) / sg; }
+__device__ __forceinline__ double z_diag(double sg) {
+  return 4.0 * exp(-0.5) / (sg * sg * sqrt(2.0 * kPi));
+}
+
+// per draw: F_s (antithetic pair collapsed, HVP difference quotient applied),
+// divided by the aggregate mixture q(tau_s); v^T tau_s for the limit HVP
+__global__ void k_prep(EstShape e, const double* __restrict__ f, const double* __restrict__ tau,
+                       const double* __restrict__ vnorm, const double* __restrict__ v,
+                       double* __restrict__ Fq, double* __restrict__ vt) {
+  const uint64_t total = e.streams * e.N;
+  for (uint64_t sidx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; sidx < total;
+       sidx += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t r0 = sidx * (uint64_t)(e.A * e.NH);
+    double F0, F1 = 0.0;
+    if (e.what == kHvp) {
+      const double vn = *vnorm;
+      F0 = vn * (f[r0 + 0] - f[r0 + 1]) / (2.0 * e.h);
+      if (e.A == 2) F1 = vn * (f[r0 + 2] - f[r0 + 3]) / (2.0 * e.h);
+    } else {
+      F0 = f[r0];
+      if (e.A == 2) F1 = f[r0 + 1];
+    }
+    double F = F0;
+    if (e.A == 2) F = e.hessk ? F0 + F1 : F0 - F1;
+    const double* t = tau + sidx * (uint64_t)e.n;
+    const double sg = e.sigma, s2 = sg * sg;
+    if (e.sampler == kAIS) {
+      double q = 0.0;
+      if (!e.hessk) {
+        const double zg = z_grad(sg);
+        for (int k = 0; k < e.n; ++k) q += (fabs(t[k]) / s2) / zg;
+      } else {
+        const double zd = z_diag(sg), zo = z_grad(sg) * z_grad(sg);
+        double l1 = 0.0, l2 = 0.0, qd = 0.0;
+        for (int k = 0; k < e.n; ++k) {
+          qd += fabs(t[k] * t[k] / (s2 * s2) - 1.0 / s2) / zd;
+          l1 += fabs(t[k]);
+          l2 += t[k] * t[k];
+        }
+        // sum_{i<j} |t_i t_j| = ((sum |t_i|)^2 - sum t_i^2) / 2
+        q = qd + 0.5 * (l1 * l1 - l2) / (s2 * s2) / zo;
+      }
+      q /= (double)e.K;
+      F /= q;
+    }
+    Fq[sidx] = F;
+    if (e.what == kHvpLimit) {
+      double acc = 0.0;
+      for (int k = 0; k < e.n; ++k) acc += v[k] * t[k];
+      vt[sidx] = acc;
+    }
+  }
+}
+
+// kernel factor d_m(tau) (output m; Hessian elements from (i, j))
+__device__ __forceinline__ double kfac(const EstShape& e, int m, int i, int j,
+                                       const double* t, double vts, const double* v) {
+  const double s2 = e.sigma * e.sigma;
+  if (e.what == kHvpLimit) return t[m] * vts / (s2 * s2) - v[m] / s2;
+  if (!e.hessk) return -t[m] / s2;
+  if (i == j) return t[i] * t[i] / (s2 * s2) - 1.0 / s2;
+  return t[i] * t[j] / (s2 * s2);
+}
+
+struct Lobes32 { fsum2 pos, neg; };
+
+// aggregate / Gaussian / limit HVP: block = chunk of draws, threads = elements
+constexpr int kLdsDoubles = 6144;   // 48 KiB of draws per chunk
+
+__global__ __launch_bounds__(256) void k_accum(EstShape e, const double* __restrict__ tau,
+                                               const double* __restrict__ Fq,
+                                               const double* __restrict__ vt,
+                                               const double* __restrict__ v, int fp64,
+                                               int chunk, void* __restrict__ part) {
+  __shared__ double s_tau[kLdsDoubles];
+  __shared__ double s_F[256];
+  __shared__ double s_vt[256];
+  const uint64_t c = blockIdx.x;
+  const uint64_t s0 = c * (uint64_t)chunk;
+  const int ns = (int)min((uint64_t)chunk, e.N - s0);
+  for (int i = threadIdx.x; i < ns * e.n; i += blockDim.x) s_tau[i] = tau[s0 * e.n + i];
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    s_F[i] = Fq[s0 + i];
+    s_vt[i] = e.what == kHvpLimit ? vt[s0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < e.nout; m += blockDim.x) {
+    int i = 0, j = 0;
+    if (e.hessk && e.what == kHess) tri_ij(e.n, m, i, j);
+    if (fp64) {
+      double pos = 0.0, neg = 0.0;
+      for (int s = 0; s < ns; ++s) {
+        const double cv = kfac(e, m, i, j, s_tau + s * e.n, s_vt[s], v) * s_F[s];
+        if (cv >= 0.0) pos += cv; else neg -= cv;
+      }
+      ((double2*)part)[c * (uint64_t)e.nout + m] = make_double2(pos, neg);
+    } else {
+      Lobes32 L = {{0.f, 0.f}, {0.f, 0.f}};
+      for (int s = 0; s < ns; ++s) {
+        const float cv = (float)(kfac(e, m, i, j, s_tau + s * e.n, s_vt[s], v) * s_F[s]);
+        if (cv >= 0.0f) two_sum_add(L.pos, cv); else two_sum_add(L.neg, -cv);
+      }
+      ((float4*)part)[c * (uint64_t)e.nout + m] = make_float4(L.pos.hi, L.pos.lo, L.neg.hi, L.neg.lo);
+    }
+  }
+}
+
+// per-element IS: thread per (element, chunk), draws of that element's stream
+__global__ void k_accum_is(EstShape e, const double* __restrict__ tau,
+                           const double* __restrict__ Fq, int fp64, int chunk, uint64_t nchunks,
+                           void* __restrict__ part) {
+  const uint64_t total = nchunks * (uint64_t)e.nout;
+  for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
+       gid += (uint64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(gid % (uint64_t)e.nout);
+    const uint64_t c = gid / (uint64_t)e.nout;
+    const uint64_t s0 = c * (uint64_t)chunk;
+    const int ns = (int)min((uint64_t)chunk, e.N - s0);
+    int i = m, j = m;
+    if (e.hessk) tri_ij(e.n, m, i, j);
+    const double zm = !e.hessk ? z_grad(e.sigma) : (i == j ? z_diag(e.sigma) : z_grad(e.sigma) * z_grad(e.sigma));
+    double pos64 = 0.0, neg64 = 0.0;
+    Lobes32 L = {{0.f, 0.f}, {0.f, 0.f}};
+    for (int s = 0; s < ns; ++s) {
+      const uint64_t sidx = (uint64_t)m * e.N + s0 + s;
+      const double* t = tau + sidx * (uint64_t)e.n;
+      const double d = kfac(e, m, i, j, t, 0.0, nullptr);
+      const double w = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) * zm;
+      const double cv = w * Fq[sidx];
+      if (fp64) {
+        if (cv >= 0.0) pos64 += cv; else neg64 -= cv;
+      } else {
+        const float cf = (float)cv;
+        if (cf >= 0.0f) two_sum_add(L.pos, cf); else two_sum_add(L.neg, -cf);
+      }
+    }
+    if (fp64) ((double2*)part)[c * (uint64_t)e.nout + m] = make_double2(pos64, neg64);
+    else ((float4*)part)[c * (uint64_t)e.nout + m] = make_float4(L.pos.hi, L.pos.lo, L.neg.hi, L.neg.lo);
+  }
+}
+
+// FP64 lobe difference over chunks in fixed order; Hessian mirrored
+__global__ void k_finalize(EstShape e, const void* __restrict__ part, int fp64, uint64_t nchunks,
+                           double* __restrict__ out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= e.nout) return;
+  double pos = 0.0, neg = 0.0;
+  for (uint64_t c = 0; c < nchunks; ++c) {
+    if (fp64) {
+      const double2 p = ((const double2*)part)[c * (uint64_t)e.nout + m];
+      pos += p.x;
+      neg += p.y;
+    } else {
+      const float4 p = ((const float4*)part)[c * (uint64_t)e.nout + m];
+      pos += (double)p.x + (double)p.y;
+      neg += (double)p.z + (double)p.w;
+    }
+  }
+  const double est = (pos - neg) / ((double)e.A * (double)e.N);
+  if (e.what == kHess) {
+    int i, j;
+    tri_ij(e.n, m, i, j);
+    out[i * e.n + j] = est;
+    out[j * e.n + i] = est;
+  } else {
+    out[m] = est;
+  }
+}
+
+}  // namespace
+
+void launch_sample(hipStream_t st, const EstShape& e, double* tau) {
+  const uint64_t total = e.streams * e.N * (uint64_t)e.n;
+  hipLaunchKernelGGL(k_sample, dim3(grid_for(total, 256)), dim3(256), 0, st, e.n, e.K, e.hessk,
+                     e.sampler, e.N, e.seed, e.sigma, total, tau);
+}
+
+void launch_vnorm(hipStream_t st, int n, const double* v, double* u, double* vnorm) {
+  hipLaunchKernelGGL(k_vnorm, dim3(1), dim3(256), 0, st, n, v, u, vnorm);
+}
+
+void launch_analytic(hipStream_t st, const EstShape& e, const AnalyticScene& s,
+                     const double* theta, const double* tau, const double* u, double* f) {
+  hipLaunchKernelGGL(k_analytic, dim3(grid_for(e.R, 128)), dim3(128), 0, st, s.kind, s.n, s.A, s.b,
+                     s.c, s.s1, theta, tau, u, e.A, e.NH, e.h, e.R, f);
+}
+
+void launch_prep(hipStream_t st, const EstShape& e, const double* f, const double* tau,
+                 const double* vnorm, const double* v, double* Fq, double* vt) {
+  hipLaunchKernelGGL(k_prep, dim3(grid_for(e.streams * e.N, 128)), dim3(128), 0, st, e, f, tau,
+                     vnorm, v, Fq, vt);
+}
+
+int accum_chunk(const EstShape& e) {
+  if (e.sampler == kIS && e.what != kHvpLimit) return 256;
+  int c = kLdsDoubles / e.n;
+  if (c > 256) c = 256;
+  if (c < 1) c = 1;
+  return c;
+}
+
+void launch_accum(hipStream_t st, const EstShape& e, const double* tau, const double* Fq,
+                  const double* vt, const double* v, int fp64, void* part, int chunk) {
+  const uint64_t nchunks = (e.N + chunk - 1) / chunk;
+  if (e.sampler == kIS && e.what != kHvpLimit) {
+    hipLaunchKernelGGL(k_accum_is, dim3(grid_for(nchunks * e.nout, 128)), dim3(128), 0, st, e, tau,
+                       Fq, fp64, chunk, nchunks, part);
+  } else {
+    hipLaunchKernelGGL(k_accum, dim3((unsigned)nchunks), dim3(256), 0, st, e, tau, Fq, vt, v, fp64,
+                       chunk, part);
+  }
+}
+
+void launch_finalize(hipStream_t st, const EstShape& e, const void* part, int fp64, int chunk,
+                     double* out) {
+  const uint64_t nchunks = (e.N + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_finalize, dim3((e.nout + 127) / 128), dim3(128), 0, st, e, part, fp64,
+                     nchunks, out);
+}
+
+}  // namespace hr

@@ -1,0 +1,297 @@
+// hr_raster.hip -- perturbed disk records and the fused rasterise + MSE kernel.
+//
+// One render = the disk scene at theta_r = theta (+- h u) - a tau_s.  The
+// loss of a render is the mean over H*W*C of (I - T)^2 (the image loss of the
+// paper's tasks, section "Methods").  Work decomposition:
+//   block (256 threads = 4 wave64) = one 32x32 pixel tile x S consecutive
+//   renders; each wave owns a 16x16 sub-tile, each lane one pixel column of 4
+//   rows.  The target tile lives in registers for all S renders; per render a
+//   wave loads the disk records (one disk per lane), culls them against its
+//   sub-tile with a conservative circle/rectangle test, and walks the surviving
+//   disks in painter's order as a wave-uniform bit mask.  Per pixel only the
+//   index of the top disk is kept; its colour comes from LDS.  Loss partials
+//   are reduced across the wave with shuffles and across the block through LDS,
+//   giving one FP32 partial per (render, tile).
+#include "hr_device.h"
+#include "hr_kernels.h"
+
+namespace hr {
+
+namespace {
+
+constexpr int kTile = 32;        // block tile side (pixels)
+constexpr int kSub = 16;         // wave sub-tile side
+constexpr int kRows = 4;         // rows per lane
+constexpr int kMaxS = 64;        // renders per block (upper bound)
+constexpr int kMaxDisks = 1024;  // colour table capacity
+
+// Width of the band around the FP32 coverage test outside which the FP32 and
+// the FP64 decision of (px - cx)^2 + (py - cy)^2 < r^2 provably agree.  FP32
+// rounding of the pixel centre, of the disk centre and of the two products
+// moves d^2 - r^2 by at most about 2^-21 r (1 + |cx| + |cy|) + 2^-22 r^2 near
+// the circle (|dx|, |dy| <= r there); the band is 4-8x that.
+__host__ __device__ inline float ambiguity_band(double cx, double cy, double r) {
+  if (!(r > 0.0)) return 0.0f;
+  const double b = 0x1p-19 * (r * (1.0 + fabs(cx) + fabs(cy)) + r * r);
+  return (float)b;
+}
+
+__global__ void k_records(const double* __restrict__ theta, const double* __restrict__ tau,
+                          const double* __restrict__ u, const float* __restrict__ radius,
+                          int n, int D, int ppd, int A, int NH, double h, uint64_t total,
+                          float4* __restrict__ rec) {
+  for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
+       gid += (uint64_t)gridDim.x * blockDim.x) {
+    int k = (int)(gid % (uint64_t)D);
+    uint64_t r = gid / (uint64_t)D;
+    int sh = (int)(r % (uint64_t)NH);
+    uint64_t rem = r / (uint64_t)NH;
+    int ai = (int)(rem % (uint64_t)A);
+    uint64_t sidx = rem / (uint64_t)A;
+    const double* t = tau + sidx * (uint64_t)n;
+    double a = ai == 0 ? 1.0 : -1.0;
+    double shift = sh == 0 ? h : -h;
+    double p[3];
+    for (int q = 0; q < ppd; ++q) {
+      int j = k * ppd + q;
+      double base = theta[j];
+      if (NH == 2) base = base + shift * u[j];
+      p[q] = base - a * t[j];
+    }
+    double rad = ppd == 3 ? p[2] : (double)radius[k];
+    rec[gid] = make_float4((float)p[0], (float)p[1], rad > 0.0 ? (float)(rad * rad) : -1.0f,
+                           ambiguity_band(p[0], p[1], rad));
+  }
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Exact coverage of pixel (x, y) by disk k of render r, in FP64 from the
+// unrounded parameters theta (+- h u) - a tau (the definition the FP32 fast
+// path approximates); taken only inside the ambiguity band.
+__device__ __noinline__ bool cover_fp64(const RasterExact& ex, uint64_t r, int k, int x, int y,
+                                        int W, int H) {
+  const int sh = (int)(r % (uint64_t)ex.NH);
+  const uint64_t rem = r / (uint64_t)ex.NH;
+  const int ai = (int)(rem % (uint64_t)ex.A);
+  const uint64_t sidx = rem / (uint64_t)ex.A;
+  const double a = ai == 0 ? 1.0 : -1.0;
+  const double shift = sh == 0 ? ex.h : -ex.h;
+  double p[3];
+  for (int q = 0; q < ex.ppd; ++q) {
+    const int j = k * ex.ppd + q;
+    double base = ex.theta[j];
+    if (ex.tau) {
+      if (ex.NH == 2) base = base + shift * ex.u[j];
+      base = base - a * ex.tau[sidx * (uint64_t)ex.n + j];
+    }
+    p[q] = base;
+  }
+  const double rad = ex.ppd == 3 ? p[2] : (double)ex.radius[k];
+  const double px = ((double)x + 0.5) / (double)W, py = ((double)y + 0.5) / (double)H;
+  const double dx = px - p[0], dy = py - p[1];
+  return rad > 0.0 && dx * dx + dy * dy < rad * rad;
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_raster_loss(
+    const float4* __restrict__ rec, const float* __restrict__ target,
+    const float* __restrict__ colors, int W, int H, int D, uint64_t R, int S, int tiles_x,
+    int tiles, uint64_t chunks, uint64_t r_base, RasterExact ex, float* __restrict__ partial) {
+  __shared__ float4 s_col[kMaxDisks + 1];
+  __shared__ float s_part[kMaxS][4];
+
+  // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
+  // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
+  const uint64_t b = blockIdx.x;
+  const uint64_t xcd = b & 7u, j = b >> 3;
+  const uint64_t chunk = (j / (uint64_t)tiles) * 8u + xcd;
+  const int tile = (int)(j % (uint64_t)tiles);
+  if (chunk >= chunks) return;
+  const uint64_t r0 = chunk * (uint64_t)S;
+  const int nr = (int)min((uint64_t)S, R - r0);
+
+  for (int k = threadIdx.x; k <= D; k += blockDim.x) {
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k > 0) {
+      const float* src = colors + (size_t)(k - 1) * C;
+      c.x = src[0];
+      if (C > 1) c.y = src[1];
+      if (C > 2) c.z = src[2];
+      if (C > 3) c.w = src[3];
+    }
+    s_col[k] = c;
+  }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx0 = (tile % tiles_x) * kTile + (wave & 1) * kSub;
+  const int ty0 = (tile / tiles_x) * kTile + (wave >> 1) * kSub;
+  const int x = tx0 + (lane & 15);
+  const int yb = ty0 + (lane >> 4) * kRows;
+  const float invW = 1.0f / (float)W, invH = 1.0f / (float)H;
+  const float px = ((float)x + 0.5f) / (float)W;
+  float py[kRows];
+  float tv[kRows][C];
+  bool valid[kRows];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int y = yb + i;
+    py[i] = ((float)y + 0.5f) / (float)H;
+    valid[i] = (x < W) && (y < H);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      tv[i][c] = valid[i] ? target[((size_t)y * W + x) * C + c] : 0.0f;
+  }
+  // sub-tile rectangle of pixel centres (centre, half extent), widened by a
+  // slack far above FP32 rounding so that culling never drops a covering disk
+  const float mx = ((float)tx0 + 0.5f * kSub) * invW, hx = (0.5f * kSub - 0.5f) * invW + 4e-6f;
+  const float my = ((float)ty0 + 0.5f * kSub) * invH, hy = (0.5f * kSub - 0.5f) * invH + 4e-6f;
+  __syncthreads();
+
+  for (int rr = 0; rr < nr; ++rr) {
+    const float4* rp = rec + (r0 + (uint64_t)rr) * (uint64_t)D;
+    int idx[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) idx[i] = 0;
+    for (int g0 = 0; g0 < D; g0 += 64) {
+      const int k = g0 + lane;
+      float4 q = k < D ? rp[k] : make_float4(0.f, 0.f, -1.f, 0.f);
+      const float ddx = fmaxf(fabsf(q.x - mx) - hx, 0.0f);
+      const float ddy = fmaxf(fabsf(q.y - my) - hy, 0.0f);
+      const bool hit = (q.z > 0.0f) && (ddx * ddx + ddy * ddy <= q.z * 1.00001f);
+      uint64_t mask = __ballot(hit);
+      while (mask) {
+        const int l = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const float cx = lane_bcast(q.x, l);
+        const float cy = lane_bcast(q.y, l);
+        const float r2 = lane_bcast(q.z, l);
+        const float band = lane_bcast(q.w, l);
+        const float dx = px - cx;
+        const float dx2 = dx * dx;
+        const int id = g0 + l + 1;
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+          const float dy = py[i] - cy;
+          const float d2 = fmaf(dy, dy, dx2);
+          bool cov = d2 < r2;
+          if (fabsf(d2 - r2) <= band && valid[i])
+            cov = cover_fp64(ex, r_base + r0 + (uint64_t)rr, id - 1, x, yb + i, W, H);
+          idx[i] = cov ? id : idx[i];
+        }
+      }
+    }
+    float e = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      // pixels of a partial tile outside the image add nothing (target 0 there)
+      const float4 col = s_col[valid[i] ? idx[i] : 0];
+      const float cc[4] = {col.x, col.y, col.z, col.w};
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float d = cc[c] - tv[i][c];
+        e = fmaf(d, d, e);
+      }
+    }
+    e = wave_sum(e);
+    if (lane == 0) s_part[rr][wave] = e;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nr; t += blockDim.x) {
+    const float v = ((s_part[t][0] + s_part[t][1]) + s_part[t][2]) + s_part[t][3];
+    partial[(r0 + (uint64_t)t) * (uint64_t)tiles + tile] = v;
+  }
+}
+
+// one wave per render: fixed-order FP64 sum of the tile partials
+__global__ void k_tile_reduce(const float* __restrict__ partial, uint64_t R, int tiles,
+                              double inv_count, double* __restrict__ f) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t r = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < R;
+       r += waves) {
+    double acc = 0.0;
+    for (int t = lane; t < tiles; t += 64) acc += (double)partial[r * (uint64_t)tiles + t];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) f[r] = acc * inv_count;
+  }
+}
+
+// single render at theta, coverage in FP64 (the definition)
+__global__ void k_render_disks(RasterExact ex, const float* __restrict__ colors, int W, int H,
+                               int C, int D, float* __restrict__ image) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  int top = -1;
+  for (int k = 0; k < D; ++k)
+    if (cover_fp64(ex, 0, k, x, y, W, H)) top = k;
+  for (int c = 0; c < C; ++c)
+    image[((size_t)y * W + x) * C + c] = top >= 0 ? colors[(size_t)top * C + c] : 0.0f;
+}
+
+inline unsigned grid_for(uint64_t total, int block) {
+  uint64_t g = (total + block - 1) / block;
+  return (unsigned)(g > 65536u * 16u ? 65536u * 16u : (g == 0 ? 1 : g));
+}
+
+}  // namespace
+
+void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
+                    const double* tau, const double* u, float4* rec) {
+  const uint64_t total = e.R * (uint64_t)s.D;
+  hipLaunchKernelGGL(k_records, dim3(grid_for(total, 256)), dim3(256), 0, st, theta, tau, u,
+                     s.radius, e.n, s.D, s.ppd, e.A, e.NH, e.h, total, rec);
+}
+
+int raster_tiles(int W, int H) { return ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile); }
+
+void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
+                        int S, const RasterExact& ex, float* partial) {
+  if (S <= 0 || S > kMaxS) S = kMaxS;
+  const int tiles_x = (s.W + kTile - 1) / kTile;
+  const int tiles = raster_tiles(s.W, s.H);
+  const uint64_t chunks = (R + S - 1) / S;
+  // grid: 8 XCD lanes x tiles x ceil(chunks / 8); launched in slices that keep
+  // the block count within the grid limit
+  const uint64_t per_xcd = (chunks + 7) / 8;
+  const uint64_t max_rows = (1ull << 30) / (8ull * (uint64_t)tiles);
+  for (uint64_t row0 = 0; row0 < per_xcd; row0 += max_rows) {
+    const uint64_t rows = umin64(max_rows, per_xcd - row0);
+    const uint64_t sub_chunks = umin64(chunks - row0 * 8, rows * 8);
+    const uint64_t sub_R = umin64(R - row0 * 8 * (uint64_t)S, sub_chunks * (uint64_t)S);
+    const uint64_t r_base = row0 * 8 * (uint64_t)S;
+    const float4* rec_s = rec + r_base * (uint64_t)s.D;
+    float* part_s = partial + row0 * 8 * (uint64_t)S * (uint64_t)tiles;
+    const dim3 grid((unsigned)(8 * tiles * rows));
+    switch (s.C) {
+      case 1: hipLaunchKernelGGL(k_raster_loss<1>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      case 2: hipLaunchKernelGGL(k_raster_loss<2>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      case 3: hipLaunchKernelGGL(k_raster_loss<3>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      default: hipLaunchKernelGGL(k_raster_loss<4>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+    }
+  }
+}
+
+void launch_tile_reduce(hipStream_t st, const float* partial, uint64_t R, int tiles,
+                        double inv_count, double* f) {
+  const uint64_t blocks = (R + 3) / 4;
+  hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)umin64(blocks, 1u << 20)), dim3(256), 0,
+                     st, partial, R, tiles, inv_count, f);
+}
+
+void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& ex, float* image) {
+  hipLaunchKernelGGL(k_render_disks, dim3((s.W + 63) / 64, s.H), dim3(64), 0, st, ex, s.colors,
+                     s.W, s.H, s.C, s.D, image);
+}
+
+}  // namespace hr

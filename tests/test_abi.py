@@ -1,0 +1,67 @@
+"""The C ABI library loads and exports every entry point include/hrest.h
+declares; the oracle and the product share no code.  CPU only (no compute
+calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hrest.h")
+LIB = os.path.join(ROOT, "paper_2412_03489_amd", "libhrest.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_estimator_calls():
+    names = declared()
+    for must in ("hr_est_grad", "hr_est_hessian", "hr_est_hvp", "hr_newton_cg_step"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhrest.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    import paper_2412_03489_amd as P
+    assert set(P.EXPORTED) == set(declared())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhrest.so not built")
+def test_library_is_gfx950_code_object():
+    out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", LIB], capture_output=True, text=True)
+    if out.returncode != 0:
+        pytest.skip("roc-obj-ls unavailable")
+    assert "gfx950" in out.stdout
+
+
+def test_oracle_and_product_share_no_code():
+    pkg = os.path.join(ROOT, "paper_2412_03489_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "orc.h" not in txt and "liborc" not in txt, fn
+    otxt = open(os.path.join(ROOT, "oracle", "orc.c")).read() + open(
+        os.path.join(ROOT, "oracle", "__init__.py")).read()
+    for needle in ("hrest.h", "libhrest", "import paper_2412_03489_amd",
+                   "from paper_2412_03489_amd", "hr_device.h", "hr_kernels.h"):
+        assert needle not in otxt, needle
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib
+
+    import paper_2412_03489_amd as P
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        P.lib()
+    importlib.reload(P)
