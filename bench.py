@@ -1,0 +1,183 @@
+"""Benchmark: one Newton-CG step of the 32-disk workload per timed step.
+
+Workload (256x256 RGB, 32 disks with (cx, cy, r) = 96 parameters, sigma 0.02,
+aggregate-importance-sampled HVPs with N = 65536 draws, 10 CG products per
+Newton step).  A step = hr_newton_cg_step_dev on device-resident theta:
+  1 gradient estimate (2N renders) + up to 10 HVP estimates (4N renders each)
+  + the FP64 CG solve, every step of the path (draws, perturbed records,
+  fused raster + MSE, weights, lobe sums, finalisation, solve) in the
+  library's kernels.  Inputs (scene, target, theta, v) are resident in HBM
+  before the timed region.
+
+metric: perturbed Mpix/s = (renders actually made) * 65536 pixels / time.
+Also reported: p50/p99 latency of single HVP queries, the roofline of the
+dominant kernel (raster + MSE) from HIP events on its stream, and the CPU
+oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Hessian-estimator throughput (perturbed Mpix/s) + p50/p99 HVP-query latency"
+PEAK_FP32_TFLOPS = 157.3          # MI355X fp32 vector (published)
+# algorithmic work per perturbed pixel of the bbox-culled rasteriser + loss:
+# 9 FLOP for the 3-channel squared error, 5 FLOP per disk test times the
+# 0.593 disks whose bounding box holds an average pixel (32 disks, E[r^2]).
+FLOP_PER_PIXEL = 12.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def render_target_on_gpu(P, ctx, w):
+    """The benchmark's target is the library's own render at theta* (the GPU
+    leg never runs the oracle)."""
+    blank = np.zeros((w.H, w.W, w.C), np.float32)
+    s0 = P.Scene.disks(ctx, w.W, w.H, w.C, w.colors, blank, radius=w.radius, ppd=w.ppd)
+    tgt = s0.render(w.theta_star)
+    s0.close()
+    return tgt
+
+
+def cpu_baseline(w, draws):
+    """The oracle, untuned, on the first `draws` draws of the same HVP query."""
+    import oracle as O
+    O.build(force=False)
+    blank = np.zeros((w.H, w.W, w.C), np.float32)
+    sc0 = O.Scene.disks(w.W, w.H, w.C, w.colors, blank, radius=w.radius, ppd=w.ppd)
+    tgt = O.render(sc0, w.theta_star, w.H, w.W, w.C).astype(np.float32)
+    osc = O.Scene.disks(w.W, w.H, w.C, w.colors, tgt, radius=w.radius, ppd=w.ppd)
+    cores = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    O.estimate("hvp", osc, w.theta0, w.sigma, draws, w.seed, v=w.v, nthreads=cores)
+    dt = time.perf_counter() - t0
+    renders = 4 * draws
+    return {"value": renders * w.pixels / dt / 1e6, "unit": "Mpix/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"one AIS HVP query of the same workload at N={draws} draws "
+                      f"({renders} renders of 256x256x3), {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--hvp-queries", type=int, default=30)
+    ap.add_argument("--cpu-draws", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--samples-per-block", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_2412_03489_amd as P
+    import workloads as WL
+
+    w = WL.disks32()
+    ctx = P.Context(0)
+    tgt = render_target_on_gpu(P, ctx, w)
+    sc = P.Scene.disks(ctx, w.W, w.H, w.C, w.colors, tgt, radius=w.radius, ppd=w.ppd)
+    th0 = ctx.alloc(8 * w.n)
+    th = ctx.alloc(8 * w.n)
+    v = ctx.alloc(8 * w.n)
+    out = ctx.alloc(8 * w.n)
+    th0.upload(w.theta0)
+    v.upload(w.v)
+    kw = dict(cg_iters=w.cg_iters, trust_radius=10.0, samples_per_block=args.samples_per_block)
+
+    def step():
+        th.copy_from(th0)
+        return P.newton_cg_step_dev(sc, th.ptr, w.sigma, w.N, w.seed, **kw)
+
+    log(f"bench: workload {w.name}, N={w.N}, warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    ctx.synchronize()
+    ctx.reset_stats()
+    ctx.enable_timing(True)
+    log(f"bench: timing {args.steps} steps")
+    renders = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rep = step()
+        renders += 2 * w.N + rep["iters_done"] * 4 * w.N
+    ctx.synchronize()
+    dt = time.perf_counter() - t0
+    launches, raster_ms = ctx.kernel_stats("raster_loss")
+    ctx.enable_timing(False)
+    log(f"bench: {args.steps} steps in {dt:.3f} s, raster launches {launches}")
+
+    # single-HVP query latency (host wall clock, call to completion)
+    lat = []
+    for q in range(args.hvp_queries):
+        t1 = time.perf_counter()
+        P.estimate_dev("hvp", sc, th0.ptr, w.sigma, w.N, w.seed + 1 + q, out.ptr, d_v=v.ptr)
+        ctx.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    lat = np.array(lat)
+
+    pix_total = renders * w.pixels
+    value = pix_total / dt / 1e6
+    # dominant kernel: raster + MSE; one launch per estimator call, HVP launches
+    # carry 4N renders, the gradient's 2N
+    steps = args.steps
+    hvps = (renders - 2 * w.N * steps) // (4 * w.N)
+    raster_pix = renders * w.pixels
+    avg_ms = raster_ms / max(launches, 1)
+    flop_per_launch = FLOP_PER_PIXEL * raster_pix / max(launches, 1)
+    achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "disks32_256x256_rgb: one Newton-CG step = 1 gradient + up to "
+                               "10 aggregate-sampled HVPs, N=65536 draws, antithetic",
+                   "pixels_per_render": w.pixels, "params": w.n, "sigma": w.sigma,
+                   "draws": w.N, "renders_per_step": renders // steps,
+                   "hvps_per_step": hvps / steps},
+        "hvp_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3),
+                           "queries": int(lat.size)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None, "kernel": "k_raster_loss",
+                     "avg_launch_ms": round(avg_ms, 4), "launches": int(launches),
+                     "flop_per_pixel": FLOP_PER_PIXEL},
+        "cpu_baseline": None,
+    }
+    for b in (th0, th, v, out):
+        b.free()
+    sc.close()
+    ctx.close()
+    if not args.no_cpu:
+        log(f"bench: CPU oracle baseline at N={args.cpu_draws}")
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_draws)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

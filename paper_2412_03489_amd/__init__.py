@@ -186,6 +186,12 @@ class DeviceBuffer:
         _check(lib().hr_memcpy(self.ctx.h, _p(out), C.c_void_p(self.ptr), out.nbytes, 1))
         return out
 
+    def copy_from(self, other):
+        """Device-to-device copy of other's bytes into this buffer."""
+        assert other.nbytes <= self.nbytes
+        _check(lib().hr_memcpy(self.ctx.h, C.c_void_p(self.ptr), C.c_void_p(other.ptr),
+                               other.nbytes, 2))
+
     def free(self):
         if self.ptr:
             _check(lib().hr_dev_free(self.ctx.h, C.c_void_p(self.ptr)))
