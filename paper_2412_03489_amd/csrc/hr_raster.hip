@@ -5,13 +5,24 @@
 // paper's tasks, section "Methods").  Work decomposition:
 //   block (256 threads = 4 wave64) = one 32x32 pixel tile x S consecutive
 //   renders; each wave owns a 16x16 sub-tile, each lane one pixel column of 4
-//   rows.  The target tile lives in registers for all S renders; per render a
-//   wave loads the disk records (one disk per lane), culls them against its
-//   sub-tile with a conservative circle/rectangle test, and walks the surviving
-//   disks in painter's order as a wave-uniform bit mask.  Per pixel only the
-//   index of the top disk is kept; its colour comes from LDS.  Loss partials
-//   are reduced across the wave with shuffles and across the block through LDS,
-//   giving one FP32 partial per (render, tile).
+//   rows.  The target tile lives in registers for all S renders.  Per render a
+//   wave loads the disk records (one disk per lane, the next render's records
+//   already in flight), culls them against its sub-tile with a conservative
+//   circle/rectangle test, and walks the surviving disks in painter's order as
+//   a wave-uniform bit mask.  Per pixel only the index of the top disk is
+//   kept; its colour comes from LDS.
+//
+// Coverage is decided exactly as the FP64 definition: every record carries
+// r^2 widened and narrowed by the FP32 error band of the test; the FP32 test
+// against the narrowed r^2 is exact outside the band, and a disk with any
+// pixel inside its band takes a wave-uniform branch that rebuilds that disk's
+// unrounded parameters and decides those pixels in FP64 (rare).
+//
+// A sub-tile that no disk reaches renders as background; its loss is the
+// sub-tile's sum of T^2, computed once per block with the same arithmetic.
+// Per render each wave folds its lanes in quads (two DPP adds) and parks 16
+// partials in LDS; after the S renders the block sums them in a fixed order,
+// giving one FP32 partial per (render, tile).
 #include "hr_device.h"
 #include "hr_kernels.h"
 
@@ -23,62 +34,58 @@ constexpr int kTile = 32;        // block tile side (pixels)
 constexpr int kSub = 16;         // wave sub-tile side
 constexpr int kRows = 4;         // rows per lane
 constexpr int kMaxS = 64;        // renders per block (upper bound)
-constexpr int kMaxDisks = 1024;  // colour table capacity
+constexpr int kQuadStride = 17;  // 16 quad partials per wave-render, padded
+constexpr float kFar = 1.0e18f;  // centre of pixels outside the image
 
-// Width of the band around the FP32 coverage test outside which the FP32 and
-// the FP64 decision of (px - cx)^2 + (py - cy)^2 < r^2 provably agree.  FP32
-// rounding of the pixel centre, of the disk centre and of the two products
-// moves d^2 - r^2 by at most about 2^-21 r (1 + |cx| + |cy|) + 2^-22 r^2 near
-// the circle (|dx|, |dy| <= r there); the band is 4-8x that.
-__host__ __device__ inline float ambiguity_band(double cx, double cy, double r) {
-  if (!(r > 0.0)) return 0.0f;
-  const double b = 0x1p-19 * (r * (1.0 + fabs(cx) + fabs(cy)) + r * r);
-  return (float)b;
+// Half-width of the band around r^2 outside which the FP32 and the FP64
+// decision of (px - cx)^2 + (py - cy)^2 < r^2 provably agree.  FP32 rounding
+// of the pixel centre, of the disk centre and of the products moves
+// d^2 - r^2 by at most about 2^-21 r (1 + |cx| + |cy|) + 2^-22 r^2 near the
+// circle (|dx|, |dy| <= r there); the band is 4-8x that.
+__host__ __device__ inline double ambiguity_band(double cx, double cy, double r) {
+  return 0x1p-19 * (r * (1.0 + fabs(cx) + fabs(cy)) + r * r);
 }
 
+// record: (cx, cy, r^2 + band, r^2 - band) in FP32; r <= 0: never covered
 __global__ void k_records(const double* __restrict__ theta, const double* __restrict__ tau,
                           const double* __restrict__ u, const float* __restrict__ radius,
                           int n, int D, int ppd, int A, int NH, double h, uint64_t total,
                           float4* __restrict__ rec) {
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
        gid += (uint64_t)gridDim.x * blockDim.x) {
-    int k = (int)(gid % (uint64_t)D);
-    uint64_t r = gid / (uint64_t)D;
-    int sh = (int)(r % (uint64_t)NH);
-    uint64_t rem = r / (uint64_t)NH;
-    int ai = (int)(rem % (uint64_t)A);
-    uint64_t sidx = rem / (uint64_t)A;
+    const int k = (int)(gid % (uint64_t)D);
+    const uint64_t r = gid / (uint64_t)D;
+    const int sh = (int)(r % (uint64_t)NH);
+    const uint64_t rem = r / (uint64_t)NH;
+    const int ai = (int)(rem % (uint64_t)A);
+    const uint64_t sidx = rem / (uint64_t)A;
     const double* t = tau + sidx * (uint64_t)n;
-    double a = ai == 0 ? 1.0 : -1.0;
-    double shift = sh == 0 ? h : -h;
+    const double a = ai == 0 ? 1.0 : -1.0;
+    const double shift = sh == 0 ? h : -h;
     double p[3];
     for (int q = 0; q < ppd; ++q) {
-      int j = k * ppd + q;
+      const int j = k * ppd + q;
       double base = theta[j];
       if (NH == 2) base = base + shift * u[j];
       p[q] = base - a * t[j];
     }
-    double rad = ppd == 3 ? p[2] : (double)radius[k];
-    rec[gid] = make_float4((float)p[0], (float)p[1], rad > 0.0 ? (float)(rad * rad) : -1.0f,
-                           ambiguity_band(p[0], p[1], rad));
+    const double rad = ppd == 3 ? p[2] : (double)radius[k];
+    float4 out = make_float4((float)p[0], (float)p[1], -1.0f, -1.0f);
+    if (rad > 0.0) {
+      const double r2 = (double)(float)(rad * rad);
+      const double band = ambiguity_band(p[0], p[1], rad);
+      out.z = (float)(r2 + band);
+      out.w = (float)(r2 - band);
+    }
+    rec[gid] = out;
   }
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ float lane_bcast(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
 // Exact coverage of pixel (x, y) by disk k of render r, in FP64 from the
-// unrounded parameters theta (+- h u) - a tau (the definition the FP32 fast
-// path approximates); taken only inside the ambiguity band.
-__device__ __noinline__ bool cover_fp64(const RasterExact& ex, uint64_t r, int k, int x, int y,
-                                        int W, int H) {
+// unrounded parameters theta (+- h u) - a tau (the definition the FP32 test
+// approximates).
+__device__ __noinline__ bool cover_fp64(RasterExact ex, uint64_t r, int k, int x, int y, int W,
+                                        int H) {
   const int sh = (int)(r % (uint64_t)ex.NH);
   const uint64_t rem = r / (uint64_t)ex.NH;
   const int ai = (int)(rem % (uint64_t)ex.A);
@@ -101,13 +108,25 @@ __device__ __noinline__ bool cover_fp64(const RasterExact& ex, uint64_t r, int k
   return rad > 0.0 && dx * dx + dy * dy < rad * rad;
 }
 
+__device__ __forceinline__ float dpp_quad_sum(float v) {
+  // lanes (0,1,2,3) of every quad end with the quad's sum: xor 1, then xor 2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void k_raster_loss(
     const float4* __restrict__ rec, const float* __restrict__ target,
     const float* __restrict__ colors, int W, int H, int D, uint64_t R, int S, int tiles_x,
     int tiles, uint64_t chunks, uint64_t r_base, RasterExact ex, float* __restrict__ partial) {
-  __shared__ float4 s_col[kMaxDisks + 1];
-  __shared__ float s_part[kMaxS][4];
+  extern __shared__ float4 smem[];
+  float4* s_col = smem;                        // D + 1 colours, index 0 = background
+  float* s_q = (float*)(smem + (D + 1));       // [S][4 waves][kQuadStride]
 
   // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
   // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
@@ -137,76 +156,138 @@ __global__ __launch_bounds__(256) void k_raster_loss(
   const int x = tx0 + (lane & 15);
   const int yb = ty0 + (lane >> 4) * kRows;
   const float invW = 1.0f / (float)W, invH = 1.0f / (float)H;
-  const float px = ((float)x + 0.5f) / (float)W;
+  const float px = x < W ? ((float)x + 0.5f) / (float)W : kFar;
   float py[kRows];
   float tv[kRows][C];
-  bool valid[kRows];
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
     const int y = yb + i;
-    py[i] = ((float)y + 0.5f) / (float)H;
-    valid[i] = (x < W) && (y < H);
+    const bool valid = (x < W) && (y < H);
+    py[i] = y < H ? ((float)y + 0.5f) / (float)H : kFar;
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      tv[i][c] = valid[i] ? target[((size_t)y * W + x) * C + c] : 0.0f;
+      tv[i][c] = valid ? target[((size_t)y * W + x) * C + c] : 0.0f;
   }
+  // background loss of this lane's pixels, same arithmetic as the main path
+  float e_empty = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float d = 0.0f - tv[i][c];
+      e_empty = fmaf(d, d, e_empty);
+    }
+  e_empty = dpp_quad_sum(e_empty);
   // sub-tile rectangle of pixel centres (centre, half extent), widened by a
   // slack far above FP32 rounding so that culling never drops a covering disk
   const float mx = ((float)tx0 + 0.5f * kSub) * invW, hx = (0.5f * kSub - 0.5f) * invW + 4e-6f;
   const float my = ((float)ty0 + 0.5f * kSub) * invH, hy = (0.5f * kSub - 0.5f) * invH + 4e-6f;
   __syncthreads();
 
+  const float4* rp0 = rec + r0 * (uint64_t)D;
+  float4 q_next = (D <= 64 && lane < D) ? rp0[lane] : make_float4(0.f, 0.f, -1.f, -1.f);
   for (int rr = 0; rr < nr; ++rr) {
-    const float4* rp = rec + (r0 + (uint64_t)rr) * (uint64_t)D;
+    const float4* rp = rp0 + (uint64_t)rr * D;
     int idx[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) idx[i] = 0;
+    uint64_t any = 0;
     for (int g0 = 0; g0 < D; g0 += 64) {
-      const int k = g0 + lane;
-      float4 q = k < D ? rp[k] : make_float4(0.f, 0.f, -1.f, 0.f);
+      float4 q;
+      if (D <= 64) {
+        q = q_next;
+        if (rr + 1 < nr && lane < D) q_next = rp[D + lane];   // next render's record
+      } else {
+        const int k = g0 + lane;
+        q = k < D ? rp[k] : make_float4(0.f, 0.f, -1.f, -1.f);
+      }
       const float ddx = fmaxf(fabsf(q.x - mx) - hx, 0.0f);
       const float ddy = fmaxf(fabsf(q.y - my) - hy, 0.0f);
-      const bool hit = (q.z > 0.0f) && (ddx * ddx + ddy * ddy <= q.z * 1.00001f);
+      const bool hit = (q.z > 0.0f) && (fmaf(ddy, ddy, ddx * ddx) <= q.z * 1.00001f);
       uint64_t mask = __ballot(hit);
+      any |= mask;
       while (mask) {
         const int l = __builtin_ctzll(mask);
         mask &= mask - 1;
         const float cx = lane_bcast(q.x, l);
         const float cy = lane_bcast(q.y, l);
-        const float r2 = lane_bcast(q.z, l);
-        const float band = lane_bcast(q.w, l);
+        const float r2hi = lane_bcast(q.z, l);
+        const float r2lo = lane_bcast(q.w, l);
         const float dx = px - cx;
         const float dx2 = dx * dx;
         const int id = g0 + l + 1;
+        uint64_t amb[kRows];   // lanes whose squared distance fell inside the band
+        uint64_t amb_any = 0;
 #pragma unroll
         for (int i = 0; i < kRows; ++i) {
           const float dy = py[i] - cy;
           const float d2 = fmaf(dy, dy, dx2);
-          bool cov = d2 < r2;
-          if (fabsf(d2 - r2) <= band && valid[i])
-            cov = cover_fp64(ex, r_base + r0 + (uint64_t)rr, id - 1, x, yb + i, W, H);
-          idx[i] = cov ? id : idx[i];
+          // lane masks straight from the compares (v_cmp into SGPRs)
+          const uint64_t m_hi = __builtin_amdgcn_fcmpf(d2, r2hi, 4 /* ordered < */);
+          const uint64_t m_lo = __builtin_amdgcn_fcmpf(d2, r2lo, 4 /* ordered < */);
+          amb[i] = m_hi & ~m_lo;
+          amb_any |= amb[i];
+          idx[i] = d2 < r2lo ? id : idx[i];
+        }
+        if (amb_any) {
+          // rare: decide the band's pixels in FP64 from the unrounded parameters
+          const uint64_t r = r_base + r0 + (uint64_t)rr;
+          const int sh = (int)(r % (uint64_t)ex.NH);
+          const uint64_t rem = r / (uint64_t)ex.NH;
+          const double a = (rem % (uint64_t)ex.A) == 0 ? 1.0 : -1.0;
+          const double* ts = ex.tau + (rem / (uint64_t)ex.A) * (uint64_t)ex.n;
+          const double shift = sh == 0 ? ex.h : -ex.h;
+          const int k = id - 1;
+          double p[3];
+          for (int qq = 0; qq < ex.ppd; ++qq) {
+            const int jj = k * ex.ppd + qq;
+            double base = ex.theta[jj];
+            if (ex.NH == 2) base = base + shift * ex.u[jj];
+            p[qq] = base - a * ts[jj];
+          }
+          const double rad = ex.ppd == 3 ? p[2] : (double)ex.radius[k];
+          const double dxd = ((double)x + 0.5) / (double)W - p[0];
+#pragma unroll
+          for (int i = 0; i < kRows; ++i) {
+            if ((amb[i] >> lane) & 1) {
+              const double dyd = ((double)(yb + i) + 0.5) / (double)H - p[1];
+              const bool cov = rad > 0.0 && dxd * dxd + dyd * dyd < rad * rad;
+              idx[i] = cov ? id : idx[i];
+            }
+          }
         }
       }
     }
-    float e = 0.0f;
+    float e;
+    if (any == 0) {
+      e = e_empty;
+    } else {
+      e = 0.0f;
 #pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      // pixels of a partial tile outside the image add nothing (target 0 there)
-      const float4 col = s_col[valid[i] ? idx[i] : 0];
-      const float cc[4] = {col.x, col.y, col.z, col.w};
+      for (int i = 0; i < kRows; ++i) {
+        const float4 col = s_col[idx[i]];
+        const float cc[4] = {col.x, col.y, col.z, col.w};
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const float d = cc[c] - tv[i][c];
-        e = fmaf(d, d, e);
+        for (int c = 0; c < C; ++c) {
+          const float d = cc[c] - tv[i][c];
+          e = fmaf(d, d, e);
+        }
       }
+      e = dpp_quad_sum(e);
     }
-    e = wave_sum(e);
-    if (lane == 0) s_part[rr][wave] = e;
+    if ((lane & 3) == 0) s_q[(rr * 4 + wave) * kQuadStride + (lane >> 2)] = e;
+  }
+  __syncthreads();
+  // fixed-order sums: 16 quads per wave, then the 4 waves
+  for (int t = threadIdx.x; t < nr * 4; t += blockDim.x) {
+    float acc = 0.0f;
+    for (int qd = 0; qd < 16; ++qd) acc += s_q[t * kQuadStride + qd];
+    s_q[t * kQuadStride + 16] = acc;
   }
   __syncthreads();
   for (int t = threadIdx.x; t < nr; t += blockDim.x) {
-    const float v = ((s_part[t][0] + s_part[t][1]) + s_part[t][2]) + s_part[t][3];
+    const float* w4 = s_q + (t * 4) * kQuadStride + 16;
+    const float v = ((w4[0] + w4[kQuadStride]) + w4[2 * kQuadStride]) + w4[3 * kQuadStride];
     partial[(r0 + (uint64_t)t) * (uint64_t)tiles + tile] = v;
   }
 }
@@ -261,6 +342,7 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
   const int tiles_x = (s.W + kTile - 1) / kTile;
   const int tiles = raster_tiles(s.W, s.H);
   const uint64_t chunks = (R + S - 1) / S;
+  const size_t lds = (size_t)(s.D + 1) * sizeof(float4) + (size_t)S * 4 * kQuadStride * sizeof(float);
   // grid: 8 XCD lanes x tiles x ceil(chunks / 8); launched in slices that keep
   // the block count within the grid limit
   const uint64_t per_xcd = (chunks + 7) / 8;
@@ -268,16 +350,16 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
   for (uint64_t row0 = 0; row0 < per_xcd; row0 += max_rows) {
     const uint64_t rows = umin64(max_rows, per_xcd - row0);
     const uint64_t sub_chunks = umin64(chunks - row0 * 8, rows * 8);
-    const uint64_t sub_R = umin64(R - row0 * 8 * (uint64_t)S, sub_chunks * (uint64_t)S);
     const uint64_t r_base = row0 * 8 * (uint64_t)S;
+    const uint64_t sub_R = umin64(R - r_base, sub_chunks * (uint64_t)S);
     const float4* rec_s = rec + r_base * (uint64_t)s.D;
-    float* part_s = partial + row0 * 8 * (uint64_t)S * (uint64_t)tiles;
+    float* part_s = partial + r_base * (uint64_t)tiles;
     const dim3 grid((unsigned)(8 * tiles * rows));
     switch (s.C) {
-      case 1: hipLaunchKernelGGL(k_raster_loss<1>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
-      case 2: hipLaunchKernelGGL(k_raster_loss<2>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
-      case 3: hipLaunchKernelGGL(k_raster_loss<3>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
-      default: hipLaunchKernelGGL(k_raster_loss<4>, grid, dim3(256), 0, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      case 1: hipLaunchKernelGGL(k_raster_loss<1>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      case 2: hipLaunchKernelGGL(k_raster_loss<2>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      case 3: hipLaunchKernelGGL(k_raster_loss<3>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      default: hipLaunchKernelGGL(k_raster_loss<4>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
     }
   }
 }
@@ -285,8 +367,8 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
 void launch_tile_reduce(hipStream_t st, const float* partial, uint64_t R, int tiles,
                         double inv_count, double* f) {
   const uint64_t blocks = (R + 3) / 4;
-  hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)umin64(blocks, 1u << 20)), dim3(256), 0,
-                     st, partial, R, tiles, inv_count, f);
+  hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)umin64(blocks, 1u << 20)), dim3(256), 0, st,
+                     partial, R, tiles, inv_count, f);
 }
 
 void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& ex, float* image) {
