@@ -119,7 +119,7 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <int C>
+template <int C, bool kOneGroup>
 __global__ __launch_bounds__(256) void k_raster_loss(
     const float4* __restrict__ rec, const float* __restrict__ target,
     const float* __restrict__ colors, int W, int H, int D, uint64_t R, int S, int tiles_x,
@@ -185,7 +185,10 @@ __global__ __launch_bounds__(256) void k_raster_loss(
   __syncthreads();
 
   const float4* rp0 = rec + r0 * (uint64_t)D;
-  float4 q_next = (D <= 64 && lane < D) ? rp0[lane] : make_float4(0.f, 0.f, -1.f, -1.f);
+  // single group (D <= 64): lane l holds disk l; the next render's record is
+  // loaded while this render is processed (clamped on the last render)
+  const int lane_d = lane < D ? lane : D - 1;
+  float4 q_next = rp0[lane_d];
   for (int rr = 0; rr < nr; ++rr) {
     const float4* rp = rp0 + (uint64_t)rr * D;
     int idx[kRows];
@@ -194,17 +197,20 @@ __global__ __launch_bounds__(256) void k_raster_loss(
     uint64_t any = 0;
     for (int g0 = 0; g0 < D; g0 += 64) {
       float4 q;
-      if (D <= 64) {
+      if (kOneGroup) {
         q = q_next;
-        if (rr + 1 < nr && lane < D) q_next = rp[D + lane];   // next render's record
+        q_next = rp0[(uint64_t)min(rr + 1, nr - 1) * D + lane_d];
       } else {
         const int k = g0 + lane;
         q = k < D ? rp[k] : make_float4(0.f, 0.f, -1.f, -1.f);
       }
       const float ddx = fmaxf(fabsf(q.x - mx) - hx, 0.0f);
       const float ddy = fmaxf(fabsf(q.y - my) - hy, 0.0f);
-      const bool hit = (q.z > 0.0f) && (fmaf(ddy, ddy, ddx * ddx) <= q.z * 1.00001f);
-      uint64_t mask = __ballot(hit);
+      // r <= 0 records carry r^2 = -1 and never pass; lanes >= D repeat disk
+      // D-1 and are masked out
+      uint64_t mask = __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z * 1.00001f,
+                                             5 /* ordered <= */);
+      if (kOneGroup && D < 64) mask &= (1ull << D) - 1;
       any |= mask;
       while (mask) {
         const int l = __builtin_ctzll(mask);
@@ -355,12 +361,18 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
     const float4* rec_s = rec + r_base * (uint64_t)s.D;
     float* part_s = partial + r_base * (uint64_t)tiles;
     const dim3 grid((unsigned)(8 * tiles * rows));
+#define HR_RASTER(CC, ONE)                                                                \
+  hipLaunchKernelGGL((k_raster_loss<CC, ONE>), grid, dim3(256), lds, st, rec_s, s.target,   \
+                     s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, \
+                     ex, part_s)
+    const bool one = s.D <= 64;
     switch (s.C) {
-      case 1: hipLaunchKernelGGL(k_raster_loss<1>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
-      case 2: hipLaunchKernelGGL(k_raster_loss<2>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
-      case 3: hipLaunchKernelGGL(k_raster_loss<3>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
-      default: hipLaunchKernelGGL(k_raster_loss<4>, grid, dim3(256), lds, st, rec_s, s.target, s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, ex, part_s); break;
+      case 1: if (one) HR_RASTER(1, true); else HR_RASTER(1, false); break;
+      case 2: if (one) HR_RASTER(2, true); else HR_RASTER(2, false); break;
+      case 3: if (one) HR_RASTER(3, true); else HR_RASTER(3, false); break;
+      default: if (one) HR_RASTER(4, true); else HR_RASTER(4, false); break;
     }
+#undef HR_RASTER
   }
 }
 
