@@ -259,13 +259,16 @@ __global__ void k_accum_is(EstShape e, const double* __restrict__ tau,
   }
 }
 
-// FP64 lobe difference over chunks in fixed order; Hessian mirrored
-__global__ void k_finalize(EstShape e, const void* __restrict__ part, int fp64, uint64_t nchunks,
-                           double* __restrict__ out) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= e.nout) return;
+// FP64 lobe difference over chunks in fixed order; Hessian mirrored.
+// One block per element: thread t sums chunks t, t + 256, ... and the 256
+// partial sums meet in a fixed pairing tree.
+__global__ __launch_bounds__(256) void k_finalize(EstShape e, const void* __restrict__ part,
+                                                  int fp64, uint64_t nchunks,
+                                                  double* __restrict__ out) {
+  __shared__ double s_pos[256], s_neg[256];
+  const int m = blockIdx.x;
   double pos = 0.0, neg = 0.0;
-  for (uint64_t c = 0; c < nchunks; ++c) {
+  for (uint64_t c = threadIdx.x; c < nchunks; c += blockDim.x) {
     if (fp64) {
       const double2 p = ((const double2*)part)[c * (uint64_t)e.nout + m];
       pos += p.x;
@@ -276,7 +279,18 @@ __global__ void k_finalize(EstShape e, const void* __restrict__ part, int fp64, 
       neg += (double)p.z + (double)p.w;
     }
   }
-  const double est = (pos - neg) / ((double)e.A * (double)e.N);
+  s_pos[threadIdx.x] = pos;
+  s_neg[threadIdx.x] = neg;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s_pos[threadIdx.x] += s_pos[threadIdx.x + off];
+      s_neg[threadIdx.x] += s_neg[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double est = (s_pos[0] - s_neg[0]) / ((double)e.A * (double)e.N);
   if (e.what == kHess) {
     int i, j;
     tri_ij(e.n, m, i, j);
@@ -334,8 +348,8 @@ void launch_accum(hipStream_t st, const EstShape& e, const double* tau, const do
 void launch_finalize(hipStream_t st, const EstShape& e, const void* part, int fp64, int chunk,
                      double* out) {
   const uint64_t nchunks = (e.N + chunk - 1) / chunk;
-  hipLaunchKernelGGL(k_finalize, dim3((e.nout + 127) / 128), dim3(128), 0, st, e, part, fp64,
-                     nchunks, out);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)e.nout), dim3(256), 0, st, e, part, fp64, nchunks,
+                     out);
 }
 
 }  // namespace hr

@@ -46,7 +46,7 @@ __host__ __device__ inline double ambiguity_band(double cx, double cy, double r)
   return 0x1p-19 * (r * (1.0 + fabs(cx) + fabs(cy)) + r * r);
 }
 
-// record: (cx, cy, r^2 + band, r^2 - band) in FP32; r <= 0: never covered
+// record: (cx, cy, (r^2 + band)(1 + 1e-5), r^2 - band) in FP32; r <= 0: never covered
 __global__ void k_records(const double* __restrict__ theta, const double* __restrict__ tau,
                           const double* __restrict__ u, const float* __restrict__ radius,
                           int n, int D, int ppd, int A, int NH, double h, uint64_t total,
@@ -72,9 +72,11 @@ __global__ void k_records(const double* __restrict__ theta, const double* __rest
     const double rad = ppd == 3 ? p[2] : (double)radius[k];
     float4 out = make_float4((float)p[0], (float)p[1], -1.0f, -1.0f);
     if (rad > 0.0) {
+      // r^2 +- band; the upper value is also the cull radius, widened by a
+      // further 1e-5 relative so that culling stays conservative in FP32
       const double r2 = (double)(float)(rad * rad);
       const double band = ambiguity_band(p[0], p[1], rad);
-      out.z = (float)(r2 + band);
+      out.z = (float)((r2 + band) * 1.00001);
       out.w = (float)(r2 - band);
     }
     rec[gid] = out;
@@ -127,6 +129,7 @@ __global__ __launch_bounds__(256) void k_raster_loss(
   extern __shared__ float4 smem[];
   float4* s_col = smem;                        // D + 1 colours, index 0 = background
   float* s_q = (float*)(smem + (D + 1));       // [S][4 waves][kQuadStride]
+  float* s_cc = s_q + S * 4 * kQuadStride;     // D + 1 squared norms (C == 4)
 
   // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
   // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
@@ -138,16 +141,15 @@ __global__ __launch_bounds__(256) void k_raster_loss(
   const uint64_t r0 = chunk * (uint64_t)S;
   const int nr = (int)min((uint64_t)S, R - r0);
 
+  // colour table: channels, and |c|^2 in .w (C <= 3) or in s_cc (C == 4)
   for (int k = threadIdx.x; k <= D; k += blockDim.x) {
-    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (k > 0) {
-      const float* src = colors + (size_t)(k - 1) * C;
-      c.x = src[0];
-      if (C > 1) c.y = src[1];
-      if (C > 2) c.z = src[2];
-      if (C > 3) c.w = src[3];
-    }
-    s_col[k] = c;
+    float cc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (k > 0)
+      for (int c = 0; c < C; ++c) cc[c] = colors[(size_t)(k - 1) * C + c];
+    float n2 = 0.0f;
+    for (int c = 0; c < C; ++c) n2 = fmaf(cc[c], cc[c], n2);
+    s_col[k] = make_float4(cc[0], cc[1], cc[2], C == 4 ? cc[3] : n2);
+    if (C == 4) s_cc[k] = n2;
   }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -157,27 +159,26 @@ __global__ __launch_bounds__(256) void k_raster_loss(
   const int yb = ty0 + (lane >> 4) * kRows;
   const float invW = 1.0f / (float)W, invH = 1.0f / (float)H;
   const float px = x < W ? ((float)x + 0.5f) / (float)W : kFar;
+  // per pixel loss written as |T|^2 + (|c|^2 - 2 c.T): the lane keeps -2T
+  // in registers and the sum of |T|^2 over its pixels; a background pixel
+  // (c = 0) adds exactly nothing to the second part
   float py[kRows];
-  float tv[kRows][C];
+  float tm2[kRows][C];
+  float t2 = 0.0f;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
     const int y = yb + i;
     const bool valid = (x < W) && (y < H);
     py[i] = y < H ? ((float)y + 0.5f) / (float)H : kFar;
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      tv[i][c] = valid ? target[((size_t)y * W + x) * C + c] : 0.0f;
-  }
-  // background loss of this lane's pixels, same arithmetic as the main path
-  float e_empty = 0.0f;
-#pragma unroll
-  for (int i = 0; i < kRows; ++i)
-#pragma unroll
     for (int c = 0; c < C; ++c) {
-      const float d = 0.0f - tv[i][c];
-      e_empty = fmaf(d, d, e_empty);
+      const float t = valid ? target[((size_t)y * W + x) * C + c] : 0.0f;
+      tm2[i][c] = -2.0f * t;
+      t2 = fmaf(t, t, t2);
     }
-  e_empty = dpp_quad_sum(e_empty);
+  }
+  // loss of an all-background sub-tile: the same arithmetic as the main path
+  const float e_empty = dpp_quad_sum(t2);
   // sub-tile rectangle of pixel centres (centre, half extent), widened by a
   // slack far above FP32 rounding so that culling never drops a covering disk
   const float mx = ((float)tx0 + 0.5f * kSub) * invW, hx = (0.5f * kSub - 0.5f) * invW + 4e-6f;
@@ -208,8 +209,7 @@ __global__ __launch_bounds__(256) void k_raster_loss(
       const float ddy = fmaxf(fabsf(q.y - my) - hy, 0.0f);
       // r <= 0 records carry r^2 = -1 and never pass; lanes >= D repeat disk
       // D-1 and are masked out
-      uint64_t mask = __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z * 1.00001f,
-                                             5 /* ordered <= */);
+      uint64_t mask = __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z, 5 /* ordered <= */);
       if (kOneGroup && D < 64) mask &= (1ull << D) - 1;
       any |= mask;
       while (mask) {
@@ -268,16 +268,15 @@ __global__ __launch_bounds__(256) void k_raster_loss(
     if (any == 0) {
       e = e_empty;
     } else {
-      e = 0.0f;
+      e = t2;
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
         const float4 col = s_col[idx[i]];
         const float cc[4] = {col.x, col.y, col.z, col.w};
+        float pe = C == 4 ? s_cc[idx[i]] : col.w;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const float d = cc[c] - tv[i][c];
-          e = fmaf(d, d, e);
-        }
+        for (int c = 0; c < C; ++c) pe = fmaf(cc[c], tm2[i][c], pe);
+        e += pe;
       }
       e = dpp_quad_sum(e);
     }
@@ -348,7 +347,8 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
   const int tiles_x = (s.W + kTile - 1) / kTile;
   const int tiles = raster_tiles(s.W, s.H);
   const uint64_t chunks = (R + S - 1) / S;
-  const size_t lds = (size_t)(s.D + 1) * sizeof(float4) + (size_t)S * 4 * kQuadStride * sizeof(float);
+  const size_t lds = (size_t)(s.D + 1) * sizeof(float4) + (size_t)S * 4 * kQuadStride * sizeof(float) +
+                    (size_t)(s.D + 1) * sizeof(float);
   // grid: 8 XCD lanes x tiles x ceil(chunks / 8); launched in slices that keep
   // the block count within the grid limit
   const uint64_t per_xcd = (chunks + 7) / 8;
