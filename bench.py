@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--hvp-queries", type=int, default=30)
-    ap.add_argument("--cpu-draws", type=int, default=4096)
+    ap.add_argument("--cpu-draws", type=int, default=24576)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--samples-per-block", type=int, default=0)
     args = ap.parse_args()
@@ -98,7 +98,11 @@ def main():
     out = ctx.alloc(8 * w.n)
     th0.upload(w.theta0)
     v.upload(w.v)
-    kw = dict(cg_iters=w.cg_iters, trust_radius=10.0, samples_per_block=args.samples_per_block)
+    # Hessian modification inside CG (curvature |v^T H v|, steps truncated to
+    # Delta = 0.05, the scale of the disks' offsets): every step makes its 10
+    # HVP products
+    kw = dict(cg_iters=w.cg_iters, trust_radius=0.05, modified=True,
+              samples_per_block=args.samples_per_block)
 
     def step():
         th.copy_from(th0)
@@ -154,8 +158,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "disks32_256x256_rgb: one Newton-CG step = 1 gradient + up to "
-                               "10 aggregate-sampled HVPs, N=65536 draws, antithetic",
+        "config": {"workload": "disks32_256x256_rgb: one Newton-CG step = 1 gradient + "
+                               "10 aggregate-sampled HVPs (CG with Hessian modification), "
+                               "N=65536 draws, antithetic",
                    "pixels_per_render": w.pixels, "params": w.n, "sigma": w.sigma,
                    "draws": w.N, "renders_per_step": renders // steps,
                    "hvps_per_step": hvps / steps},

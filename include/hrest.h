@@ -195,6 +195,10 @@ typedef struct {
                             Delta; 0: Newton-CG with HVPs (default)                  */
   double eig_floor;      /* default 1e-6                                             */
   int hvp_limit;         /* 1: CG products through hr_est_hvp_limit                  */
+  int modified;          /* 0 (default): Steihaug exits above; 1: Hessian modification
+                            inside CG -- v^T H v replaced by max(|v^T H v|,
+                            eig_floor |v|^2), truncated steps continue, so all
+                            cg_iters products are made unless |r| <= 1e-10 |g|   */
 } hr_ncg_opts;
 
 typedef struct {

@@ -38,7 +38,7 @@ class Opts(C.Structure):
 class NcgOpts(C.Structure):
     _fields_ = [("cg_iters", C.c_int), ("trust_radius", C.c_double),
                 ("use_full_hessian", C.c_int), ("eig_floor", C.c_double),
-                ("hvp_limit", C.c_int)]
+                ("hvp_limit", C.c_int), ("modified", C.c_int)]
 
 
 class NcgReport(C.Structure):
@@ -237,13 +237,13 @@ def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic
 
 def newton_cg_step(scene, theta, sigma, N, seed, cg_iters=10, trust_radius=1.0,
                    use_full_hessian=False, eig_floor=1e-6, hvp_limit=False, sampler=AIS,
-                   antithetic=True, hvp_rel_step=0.1, nthreads=None):
+                   antithetic=True, hvp_rel_step=0.1, nthreads=None, modified=False):
     th = np.array(theta, dtype=np.float64)
     if nthreads is None:
         nthreads = os.cpu_count() or 1
     o = _opts(sampler, antithetic, hvp_rel_step, nthreads, 0, None)
     no = NcgOpts(cg_iters, trust_radius, 1 if use_full_hessian else 0, eig_floor,
-                 1 if hvp_limit else 0)
+                 1 if hvp_limit else 0, 1 if modified else 0)
     rep = NcgReport()
     st = lib().orc_newton_cg_step(scene.h, _p(th), float(sigma), int(N), int(seed),
                                   C.byref(no), C.byref(o), C.byref(rep))

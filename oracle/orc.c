@@ -981,6 +981,28 @@ int orc_newton_cg_step(const orc_scene* sc, double* theta, double sigma, uint64_
       if (st) goto done;
       R.iters_done = k + 1;
       double curv = vdot(n, p, Hp);
+      if (no->modified) {
+        /* reading of the paper's "Hessian modification and truncation to a
+         * trust region" inside CG: a non-positive curvature is replaced by its
+         * magnitude (floored), alpha = min(alpha, Delta/|v|), and CG goes on */
+        double kappa = fabs(curv);
+        if (curv <= 0.0) R.neg_curv = 1;
+        if (kappa < no->eig_floor * pn * pn) kappa = no->eig_floor * pn * pn;
+        if (kappa == 0.0) break;
+        double alpha = rr / kappa;
+        if (alpha > no->trust_radius / pn) {
+          alpha = no->trust_radius / pn;
+          R.hit_trust = 1;
+        }
+        for (int i = 0; i < n; ++i) d[i] += alpha * p[i];
+        for (int i = 0; i < n; ++i) r[i] -= alpha * Hp[i];
+        double rr_new = vdot(n, r, r);
+        if (sqrt(rr_new) <= 1e-10 * R.g_norm) break;
+        double beta = rr_new / rr;
+        for (int i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        continue;
+      }
       if (curv <= 0.0) {
         double a = no->trust_radius / pn;
         for (int i = 0; i < n; ++i) d[i] += a * p[i];

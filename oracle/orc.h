@@ -89,6 +89,9 @@ typedef struct {
   int use_full_hessian;  /* 1: modified Newton on the estimated H                */
   double eig_floor;      /* full-H mode: lambda <- max(|lambda|, eig_floor)       */
   int hvp_limit;         /* 1: CG products through the limit-kernel HVP          */
+  int modified;          /* 1: Hessian modification inside CG: curvature v^T H v
+                            replaced by max(|v^T H v|, eig_floor |v|^2), truncated
+                            steps continue; all cg_iters products are used      */
 } orc_ncg_opts;
 
 typedef struct {

@@ -46,7 +46,8 @@ class Opts(C.Structure):
 
 class NcgOpts(C.Structure):
     _fields_ = [("cg_iters", C.c_int), ("trust_radius", C.c_double),
-                ("use_full_hessian", C.c_int), ("eig_floor", C.c_double), ("hvp_limit", C.c_int)]
+                ("use_full_hessian", C.c_int), ("eig_floor", C.c_double), ("hvp_limit", C.c_int),
+                ("modified", C.c_int)]
 
 
 class NcgReport(C.Structure):
@@ -321,11 +322,12 @@ def estimate_dev(kind, scene, d_theta, sigma, N, seed, d_out, d_v=None, sampler=
 
 def newton_cg_step(scene, theta, sigma, N, seed, cg_iters=10, trust_radius=1.0,
                    use_full_hessian=False, eig_floor=1e-6, hvp_limit=False, sampler=AIS,
-                   antithetic=True, hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0):
+                   antithetic=True, hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0,
+                   modified=False):
     th = np.array(theta, dtype=np.float64)
     o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block)
     no = NcgOpts(int(cg_iters), float(trust_radius), 1 if use_full_hessian else 0,
-                 float(eig_floor), 1 if hvp_limit else 0)
+                 float(eig_floor), 1 if hvp_limit else 0, 1 if modified else 0)
     rep = NcgReport()
     _check(lib().hr_newton_cg_step(scene.h, _p(th), float(sigma), int(N), int(seed),
                                    C.byref(no), C.byref(o), C.byref(rep)))
@@ -335,10 +337,11 @@ def newton_cg_step(scene, theta, sigma, N, seed, cg_iters=10, trust_radius=1.0,
 
 def newton_cg_step_dev(scene, d_theta, sigma, N, seed, cg_iters=10, trust_radius=1.0,
                        use_full_hessian=False, eig_floor=1e-6, hvp_limit=False, sampler=AIS,
-                       antithetic=True, hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0):
+                       antithetic=True, hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0,
+                       modified=False):
     o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block)
     no = NcgOpts(int(cg_iters), float(trust_radius), 1 if use_full_hessian else 0,
-                 float(eig_floor), 1 if hvp_limit else 0)
+                 float(eig_floor), 1 if hvp_limit else 0, 1 if modified else 0)
     rep = NcgReport()
     _check(lib().hr_newton_cg_step_dev(scene.h, C.c_void_p(d_theta), float(sigma), int(N),
                                        int(seed), C.byref(no), C.byref(o), C.byref(rep)))

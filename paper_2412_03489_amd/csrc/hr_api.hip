@@ -285,6 +285,7 @@ void hr_ncg_opts_default(hr_ncg_opts* o) {
   o->use_full_hessian = 0;
   o->eig_floor = 1e-6;
   o->hvp_limit = 0;
+  o->modified = 0;
 }
 
 const char* hr_last_error(void) { return g_err.c_str(); }
@@ -623,7 +624,7 @@ hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uin
     if (st) return st;
     launch_newton_full(s, n, Hm, g, no.trust_radius, no.eig_floor, work, d, cs);
   } else {
-    launch_cg_init(s, n, g, no.trust_radius, r, pv, d, cs);
+    launch_cg_init(s, n, g, no.trust_radius, no.modified, no.eig_floor, r, pv, d, cs);
     for (int k = 0; k < no.cg_iters; ++k) {
       HR_HIP(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, s));
       HR_HIP(hipStreamSynchronize(s));

@@ -87,11 +87,11 @@ void launch_finalize(hipStream_t st, const EstShape& e, const void* part, int fp
 
 // ---- solver ----
 struct CgState {
-  int stop, iters, hit_trust, neg_curv;
-  double rr, gnorm, delta, step_norm;
+  int stop, iters, hit_trust, neg_curv, modified, pad;
+  double rr, gnorm, delta, step_norm, eig_floor;
 };
-void launch_cg_init(hipStream_t st, int n, const double* g, double delta, double* r, double* p,
-                    double* d, CgState* cs);
+void launch_cg_init(hipStream_t st, int n, const double* g, double delta, int modified,
+                    double eig_floor, double* r, double* p, double* d, CgState* cs);
 void launch_cg_update(hipStream_t st, int n, const double* Hp, double* r, double* p, double* d,
                       CgState* cs);
 void launch_cg_apply(hipStream_t st, int n, const double* d, double* theta, CgState* cs);

@@ -5,6 +5,9 @@
 //   alpha <- min(alpha, Delta / |v|) (trust truncation, ends the inner loop);
 //   v^T H v <= 0 -> move to the trust boundary along v and stop;
 //   r <- r - alpha H v;  beta = r_new^T r_new / r^T r (Fletcher-Reeves);  v <- r + beta v.
+// With `modified` set the exits are replaced by the paper's Hessian
+// modification: the curvature becomes max(|v^T H v|, floor |v|^2), the step is
+// truncated to Delta/|v| and CG continues for all its iterations.
 // Modified Newton on a full estimate (appendix on non-PSD Hessians): cyclic
 // Jacobi eigen-decomposition, |lambda| floored, step scaled into Delta.
 #include "hr_kernels.h"
@@ -29,7 +32,8 @@ __device__ double block_sum(double v, double* sh) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_cg_init(int n, const double* __restrict__ g,
-                                                      double delta, double* r, double* p,
+                                                      double delta, int modified,
+                                                      double eig_floor, double* r, double* p,
                                                       double* d, CgState* cs) {
   __shared__ double sh[kThreads];
   double acc = 0.0;
@@ -48,6 +52,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(int n, const double* __res
     cs->hit_trust = 0;
     cs->neg_curv = 0;
     cs->step_norm = 0.0;
+    cs->modified = modified;
+    cs->eig_floor = eig_floor;
     cs->stop = gg == 0.0 ? 1 : 0;
   }
 }
@@ -71,6 +77,25 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int n, const double* __r
     if (pn == 0.0) {
       s_mode = 3;
       s_alpha = 0.0;
+    } else if (cs->modified) {
+      // Hessian modification inside CG: |curvature|, floored; truncated
+      // steps continue
+      double kappa = fabs(curv);
+      if (curv <= 0.0) cs->neg_curv = 1;
+      const double fl = cs->eig_floor * pn * pn;
+      if (kappa < fl) kappa = fl;
+      if (kappa == 0.0) {
+        s_mode = 3;
+        s_alpha = 0.0;
+      } else {
+        double alpha = cs->rr / kappa;
+        if (alpha > cs->delta / pn) {
+          alpha = cs->delta / pn;
+          cs->hit_trust = 1;
+        }
+        s_mode = 0;
+        s_alpha = alpha;
+      }
     } else if (curv <= 0.0) {
       s_mode = 1;
       s_alpha = cs->delta / pn;
@@ -219,9 +244,10 @@ __global__ __launch_bounds__(kThreads) void k_newton_full(int n, const double* _
 
 }  // namespace
 
-void launch_cg_init(hipStream_t st, int n, const double* g, double delta, double* r, double* p,
-                    double* d, CgState* cs) {
-  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kThreads), 0, st, n, g, delta, r, p, d, cs);
+void launch_cg_init(hipStream_t st, int n, const double* g, double delta, int modified,
+                    double eig_floor, double* r, double* p, double* d, CgState* cs) {
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kThreads), 0, st, n, g, delta, modified, eig_floor,
+                     r, p, d, cs);
 }
 void launch_cg_update(hipStream_t st, int n, const double* Hp, double* r, double* p, double* d,
                       CgState* cs) {

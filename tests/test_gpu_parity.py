@@ -296,6 +296,29 @@ def test_newton_cg_step_parity_one_disk(P, one_disk):
     assert rel_inf(got - w.theta0, ref - w.theta0) < 1e-3
 
 
+def test_newton_cg_modified_parity(P, ctx, disks32):
+    """Hessian-modification CG (all products used) on the negated Gaussian and
+    on the 32-disk scene at reduced N."""
+    osc = O.Scene.neggauss(2, 1.0)
+    gsc = P.Scene.neggauss(ctx, 2, 1.0)
+    th0 = np.array([2.5, 0.1])
+    say("newton-cg modified negated gaussian")
+    ref, rr = O.newton_cg_step(osc, th0, 0.5, 4000, 5, cg_iters=4, trust_radius=0.2, modified=True)
+    got, gr = P.newton_cg_step(gsc, th0, 0.5, 4000, 5, cg_iters=4, trust_radius=0.2, modified=True,
+                               accum_fp64=True)
+    for key in ("iters_done", "neg_curv", "hit_trust"):
+        assert gr[key] == rr[key], key
+    assert rel_inf(got - th0, ref - th0) < 1e-8
+    w, osc2, gsc2 = disks32
+    say("newton-cg modified disks32 N=64")
+    ref, rr = O.newton_cg_step(osc2, w.theta0, w.sigma, 64, w.seed, cg_iters=3, trust_radius=0.05,
+                               modified=True)
+    got, gr = P.newton_cg_step(gsc2, w.theta0, w.sigma, 64, w.seed, cg_iters=3, trust_radius=0.05,
+                               modified=True)
+    assert gr["iters_done"] == rr["iters_done"] == 3
+    assert rel_inf(got - w.theta0, ref - w.theta0) < 1e-3
+
+
 def test_newton_cg_negative_curvature_parity(P, ctx):
     osc = O.Scene.neggauss(2, 1.0)
     gsc = P.Scene.neggauss(ctx, 2, 1.0)

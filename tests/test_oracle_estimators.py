@@ -308,3 +308,34 @@ def test_invalid_arguments_rejected(orc, quad):
         orc.estimate("grad", sc, [np.nan, 0.0], 0.1, 10, 1)
     with pytest.raises(ValueError):
         orc.estimate("hvp_limit", sc, [0.0, 0.0], 0.1, 10, 1, v=[1.0, 0.0], sampler=1)
+
+
+def test_modified_cg_equals_steihaug_on_psd_quadratic(orc):
+    """With a positive definite H and no truncation the modification never
+    triggers, so both CG variants take the same step."""
+    A = WL.quad_paper()
+    b = np.array([1.0, -2.0])
+    th0 = np.array([1.0, 1.0])
+    sc = orc.Scene.quad(A, b, -(0.5 * th0 @ A @ th0 + b @ th0))
+    a, ra = orc.newton_cg_step(sc, th0, 0.2, 20000, 3, cg_iters=2, trust_radius=10.0)
+    m, rm = orc.newton_cg_step(sc, th0, 0.2, 20000, 3, cg_iters=2, trust_radius=10.0,
+                               modified=True)
+    assert np.array_equal(a, m)
+    assert ra == rm
+
+
+def test_modified_cg_uses_all_products_and_descends(orc):
+    """Negated Gaussian away from its centre: negative curvature is met, the
+    modified variant keeps iterating (all products used), each step is at most
+    Delta long, and the smoothed loss decreases."""
+    s1, sg = 1.0, 0.5
+    sc = orc.Scene.neggauss(2, s1)
+    th0 = np.array([2.5, 0.1])
+    th, rep = orc.newton_cg_step(sc, th0, sg, 20000, 5, cg_iters=4, trust_radius=0.2,
+                                 modified=True)
+    assert rep["iters_done"] == 4
+    assert rep["neg_curv"] == 1
+    assert rep["step_norm"] <= 4 * 0.2 + 1e-12
+    F0, _, _ = E.neggauss_exact(th0, s1, sg)
+    F1, _, _ = E.neggauss_exact(th, s1, sg)
+    assert F1 < F0
