@@ -35,6 +35,19 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X fp32 vector (published)
 # 9 FLOP for the 3-channel squared error, 5 FLOP per disk test times the
 # 0.593 disks whose bounding box holds an average pixel (32 disks, E[r^2]).
 FLOP_PER_PIXEL = 12.0
+# HBM bytes per k_raster_loss launch (mean over a step's launches) from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
+# (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
+# this SHA-256; reported as null once the source has changed.
+TRAFFIC_BYTES_PER_LAUNCH = 274287888
+TRAFFIC_SOURCE_SHA256 = "26c254cacdec508817dc37aac572635f4b81768273be7dee047f97ac7e5a374f"
+
+
+def raster_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2412_03489_amd", "csrc", "hr_raster.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return TRAFFIC_BYTES_PER_LAUNCH if digest == TRAFFIC_SOURCE_SHA256 else None
 
 
 def log(msg):
@@ -79,6 +92,9 @@ def main():
     ap.add_argument("--cpu-draws", type=int, default=24576)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--samples-per-block", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="after the run, one device-to-device copy of this many MiB "
+                         "(a kernel of known traffic for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -133,7 +149,15 @@ def main():
         P.estimate_dev("hvp", sc, th0.ptr, w.sigma, w.N, w.seed + 1 + q, out.ptr, d_v=v.ptr)
         ctx.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.array([float("nan")])
+    if args.calibrate_copy_mb > 0:
+        nb = args.calibrate_copy_mb << 20
+        src, dst = ctx.alloc(nb), ctx.alloc(nb)
+        dst.copy_from(src)
+        ctx.synchronize()
+        src.free()
+        dst.free()
+        log(f"bench: calibration copy of {nb} bytes done")
 
     pix_total = renders * w.pixels
     value = pix_total / dt / 1e6
@@ -166,10 +190,10 @@ def main():
                    "hvps_per_step": hvps / steps},
         "hvp_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                            "p99": round(float(np.percentile(lat, 99)), 3),
-                           "queries": int(lat.size)},
+                           "queries": int(args.hvp_queries)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": None, "kernel": "k_raster_loss",
+                     "traffic": raster_traffic(), "kernel": "k_raster_loss",
                      "avg_launch_ms": round(avg_ms, 4), "launches": int(launches),
                      "flop_per_pixel": FLOP_PER_PIXEL},
         "cpu_baseline": None,
