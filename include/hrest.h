@@ -65,8 +65,12 @@ typedef enum {
  *             one render per draw.
  *   HR_IS   : per-element importance sampling, one stream of N draws per
  *             element (K renders per draw), weight sgn(d_m) Z_m.
- *   HR_GAUSS: plain Gaussian draws, weight d_m(tau) ("no IS" column). */
-typedef enum { HR_AIS = 0, HR_IS = 1, HR_GAUSS = 2 } hr_sampler;
+ *   HR_GAUSS: plain Gaussian draws, weight d_m(tau) ("no IS" column).
+ *   HR_FR22 : comparator of the gradient-derivation appendix: per-element
+ *             streams like HR_IS but only the differentiated dimension is
+ *             blurred (all other components of tau are 0); gradient and HVP
+ *             only (HR_EUNSUPPORTED for Hessians). */
+typedef enum { HR_AIS = 0, HR_IS = 1, HR_GAUSS = 2, HR_FR22 = 3 } hr_sampler;
 
 typedef struct hr_ctx hr_ctx;      /* one per GPU: stream, workspace, timers   */
 typedef struct hr_scene hr_scene;  /* device-resident scene and target image   */
@@ -146,6 +150,9 @@ hr_status hr_scene_pt(hr_ctx* ctx, int W, int H, int spp, int nspheres, const do
 hr_status hr_scene_quad(hr_ctx* ctx, int n, const double* A, const double* b, double c,
                         hr_scene** out);
 hr_status hr_scene_neggauss(hr_ctx* ctx, int n, double s1, hr_scene** out);
+/* Frees a scene.  A scene belongs to its context: destroying the context
+ * first releases the scene's device memory and orphans it -- every later call
+ * with it returns HR_EINVAL, and hr_scene_destroy still frees the handle. */
 void hr_scene_destroy(hr_scene* sc);
 int hr_scene_nparams(const hr_scene* sc);
 
@@ -174,6 +181,26 @@ hr_status hr_est_hvp(hr_scene* sc, const double* theta, double sigma, uint64_t N
  * HR_GAUSS only (HR_EUNSUPPORTED for HR_IS). */
 hr_status hr_est_hvp_limit(hr_scene* sc, const double* theta, double sigma, uint64_t N,
                            uint64_t seed, const double* v, const hr_opts* opts, double* Hv);
+
+/* ---- grey-box composition (appendix "Grey-box differentials") -----------
+ * The scene's parameters y = g(x) come from a caller-side inner map with known
+ * Jacobian J = dg/dx: n rows (scene parameters) x n_in columns, row-major,
+ * host FP64.  The outer derivatives are sampled at y exactly as by the plain
+ * estimators and composed in FP64 on the GPU:
+ *   gx  = J^T g_y                          (n_in doubles)
+ *   Hx  = J^T H_y J (inner second derivatives dropped, as in the appendix)
+ *                                           (n_in * n_in doubles, row-major)
+ *   Hvx = J^T H_y (J vx)  with H_y (J vx) by hr_est_hvp's central difference
+ * n_in in 1..4096; errors as for the plain estimators. */
+hr_status hr_est_grad_greybox(hr_scene* sc, const double* y, const double* J, int n_in,
+                              double sigma, uint64_t N, uint64_t seed, const hr_opts* opts,
+                              double* gx);
+hr_status hr_est_hessian_greybox(hr_scene* sc, const double* y, const double* J, int n_in,
+                                 double sigma, uint64_t N, uint64_t seed, const hr_opts* opts,
+                                 double* Hx);
+hr_status hr_est_hvp_greybox(hr_scene* sc, const double* y, const double* J, int n_in,
+                             double sigma, uint64_t N, uint64_t seed, const double* vx,
+                             const hr_opts* opts, double* Hvx);
 
 /* ---- estimators (device pointers; asynchronous on the context stream) ---- */
 /* Same results as the host versions.  d_theta, d_v: n FP64 on the device;

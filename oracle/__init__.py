@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
 
-AIS, IS, GAUSS = 0, 1, 2
+AIS, IS, GAUSS, FR22 = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -81,6 +81,11 @@ def lib():
                                          C.POINTER(Opts), C.POINTER(NcgReport)]
         L.orc_newton_cg_step.restype = i
         L.orc_jacobi_eig.argtypes = [i, vp, vp, vp]; L.orc_jacobi_eig.restype = i
+        for nm in ("orc_est_grad_greybox", "orc_est_hessian_greybox"):
+            getattr(L, nm).argtypes = [vp, vp, vp, i, d, u64, u64, C.POINTER(Opts), vp]
+            getattr(L, nm).restype = i
+        L.orc_est_hvp_greybox.argtypes = [vp, vp, vp, i, d, u64, u64, vp, C.POINTER(Opts), vp]
+        L.orc_est_hvp_greybox.restype = i
         _lib = L
     return _lib
 
@@ -201,7 +206,7 @@ def n_renders(kind, n, N, sampler=AIS, antithetic=True):
     """Renders an estimator call makes (table of evaluation counts, x2 antithetic)."""
     A = 2 if antithetic else 1
     K = n * (n + 1) // 2 if kind == "hess" else n
-    streams = K if (sampler == IS and kind != "hvp_limit") else 1
+    streams = K if (sampler in (IS, FR22) and kind != "hvp_limit") else 1
     per = 2 if kind == "hvp" else 1
     return streams * N * A * per
 
@@ -260,3 +265,33 @@ def jacobi_eig(A):
     V = np.zeros((n, n))
     lib().orc_jacobi_eig(n, _p(A), _p(ev), _p(V))
     return ev, V
+
+
+def estimate_greybox(kind, scene, y, J, sigma, N, seed, vx=None, sampler=AIS, antithetic=True,
+                     hvp_rel_step=0.1, nthreads=None):
+    """Grey-box composition: kind in {'grad', 'hess', 'hvp'}; J is (n, n_in)."""
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    JJ = np.ascontiguousarray(J, dtype=np.float64)
+    n_in = JJ.shape[1]
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    o = _opts(sampler, antithetic, hvp_rel_step, nthreads, 0, None)
+    L = lib()
+    if kind == "grad":
+        out = np.zeros(n_in)
+        st = L.orc_est_grad_greybox(scene.h, _p(yy), _p(JJ), n_in, float(sigma), int(N),
+                                    int(seed), C.byref(o), _p(out))
+    elif kind == "hess":
+        out = np.zeros((n_in, n_in))
+        st = L.orc_est_hessian_greybox(scene.h, _p(yy), _p(JJ), n_in, float(sigma), int(N),
+                                       int(seed), C.byref(o), _p(out))
+    elif kind == "hvp":
+        v = np.ascontiguousarray(vx, dtype=np.float64)
+        out = np.zeros(n_in)
+        st = L.orc_est_hvp_greybox(scene.h, _p(yy), _p(JJ), n_in, float(sigma), int(N),
+                                   int(seed), _p(v), C.byref(o), _p(out))
+    else:
+        raise ValueError(kind)
+    if st:
+        raise ValueError(f"oracle grey-box {kind} failed ({st})")
+    return out

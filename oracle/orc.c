@@ -578,11 +578,16 @@ static double kmass(int hess, const tri_table* T, int m, double sg) {
  * every other dimension from the Gaussian (section "Gradients", Sampling, and
  * the marginalisation appendix).  The aggregate sampler first draws the element
  * uniformly from the selector block (s, 0xFFFFFFFF, 0, tag). */
+/* per-element streams: IS, and the FR22 comparator (appendix on the gradient
+ * derivation: FR22 blurs only the dimension it differentiates, so every other
+ * dimension of its draw is zero) */
+static int per_element(int sampler) { return sampler == ORC_IS || sampler == ORC_FR22; }
+
 static void draw(int hess, int n, double sg, uint64_t seed, uint32_t s, int sampler,
                  int stream, double* tau, int* elem) {
   int K = hess ? n * (n + 1) / 2 : n;
-  uint32_t tag = sampler == ORC_IS ? (uint32_t)stream
-                                   : (sampler == ORC_AIS ? TAG_AIS : TAG_GAUSS);
+  uint32_t tag = per_element(sampler) ? (uint32_t)stream
+                                      : (sampler == ORC_AIS ? TAG_AIS : TAG_GAUSS);
   uint32_t* lobe = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
   for (int j = 0; j < n; ++j) {
     uint32_t w[4];
@@ -591,7 +596,9 @@ static void draw(int hess, int n, double sg, uint64_t seed, uint32_t s, int samp
     lobe[j] = w[2];
   }
   int m = -1;
-  if (sampler == ORC_IS) m = stream;
+  if (per_element(sampler)) m = stream;
+  if (sampler == ORC_FR22)
+    for (int j = 0; j < n; ++j) tau[j] = 0.0;
   if (sampler == ORC_AIS) {
     uint32_t w[4];
     philox_words(seed, s, DIM_SELECT, 0u, tag, w);
@@ -639,7 +646,7 @@ static void weights(int hess, const tri_table* T, int K, const double* tau, doub
   for (int m = 0; m < K; ++m) {
     double dm = kfac(hess, T, m, tau, sg);
     if (sampler == ORC_GAUSS) w[m] = dm;
-    else if (sampler == ORC_IS)
+    else if (per_element(sampler))
       w[m] = (dm > 0.0 ? 1.0 : (dm < 0.0 ? -1.0 : 0.0)) * kmass(hess, T, m, sg);
     else w[m] = dm / q;
   }
@@ -667,8 +674,8 @@ typedef struct {
 
 static void run_item(const job_t* J, uint64_t item) {
   int n = J->n;
-  uint64_t stream = J->sampler == ORC_IS ? item / J->N : 0;
-  uint64_t sl = J->sampler == ORC_IS ? item % J->N : item;
+  uint64_t stream = per_element(J->sampler) ? item / J->N : 0;
+  uint64_t sl = per_element(J->sampler) ? item % J->N : item;
   uint32_t s = (uint32_t)(J->s0 + sl);
   int hess_kernel = (J->what == W_HESS || J->what == W_HVPL);
   double* tau = (double*)malloc((size_t)n * sizeof(double));
@@ -728,7 +735,7 @@ static void run_item(const job_t* J, uint64_t item) {
     double fv[2];
     for (int ai = 0; ai < J->A; ++ai)
       fv[ai] = J->what == W_HVP ? J->vnorm * (f[ai][0] - f[ai][1]) / (2.0 * J->h) : f[ai][0];
-    if (J->sampler == ORC_IS) {
+    if (per_element(J->sampler)) {
       int m = (int)stream;
       double val = 0.0;
       for (int ai = 0; ai < J->A; ++ai) val += w[ai][m] * fv[ai];
@@ -770,8 +777,9 @@ static int run_estimator(const orc_scene* sc, int what, const double* theta, dou
   if (!(sg > 0) || !isfinite(sg) || N == 0 || N >= 0xFFFFFFFFull) return -1;
   if (o->s0 + N > 0xFFFFFFFFull) return -1;
   for (int j = 0; j < n; ++j) if (!isfinite(theta[j])) return -1;
-  if (o->sampler < 0 || o->sampler > 2) return -1;
-  if (what == W_HVPL && o->sampler == ORC_IS) return -4;
+  if (o->sampler < 0 || o->sampler > 3) return -1;
+  if (what == W_HVPL && per_element(o->sampler)) return -4;
+  if (o->sampler == ORC_FR22 && what == W_HESS) return -4;
   int hess_kernel = (what == W_HESS || what == W_HVPL);
   int K = hess_kernel ? n * (n + 1) / 2 : n;
   int nout = what == W_HESS ? K : n;
@@ -804,8 +812,8 @@ static int run_estimator(const orc_scene* sc, int what, const double* theta, dou
     J.u = u;
     J.v = v;
   }
-  uint64_t items = o->sampler == ORC_IS ? (uint64_t)K * N : N;
-  uint64_t per_item = (o->sampler == ORC_IS && what != W_HVPL) ? 1 : (uint64_t)(what == W_HVPL ? n : K);
+  uint64_t items = per_element(o->sampler) ? (uint64_t)K * N : N;
+  uint64_t per_item = per_element(o->sampler) ? 1 : (uint64_t)(what == W_HVPL ? n : K);
   J.contrib = (double*)malloc(items * per_item * sizeof(double));
   if (!J.contrib) { free(u); return -2; }
   tri_table tri = tri_make(n);
@@ -830,7 +838,7 @@ static int run_estimator(const orc_scene* sc, int what, const double* theta, dou
     nsum acc = {0.0, 0.0};
     for (uint64_t s = 0; s < N; ++s) {
       double x;
-      if (o->sampler == ORC_IS && what != W_HVPL) x = J.contrib[(uint64_t)m * N + s];
+      if (per_element(o->sampler)) x = J.contrib[(uint64_t)m * N + s];
       else x = J.contrib[s * per_item + (uint64_t)m];
       nsum_add(&acc, x);
     }
@@ -869,6 +877,70 @@ int orc_est_hvp(const orc_scene* sc, const double* theta, double sigma, uint64_t
 int orc_est_hvp_limit(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
                       uint64_t seed, const double* v, const orc_opts* o, double* Hv) {
   return run_estimator(sc, W_HVPL, theta, sigma, N, seed, v, o, Hv);
+}
+
+/* ========================================================================= */
+/* Grey-box composition (appendix "Grey-box differentials"): gradient J^T g_y,
+ * Hessian J^T H_y J, HVP J^T H_y J v, with the outer derivatives sampled.    */
+/* ========================================================================= */
+int orc_est_grad_greybox(const orc_scene* sc, const double* y, const double* J, int n_in,
+                         double sigma, uint64_t N, uint64_t seed, const orc_opts* o, double* gx) {
+  if (!sc || !J || !gx || n_in <= 0) return -1;
+  int n = sc->n;
+  double* gy = (double*)malloc((size_t)n * sizeof(double));
+  int st = orc_est_grad(sc, y, sigma, N, seed, o, gy);
+  if (!st)
+    for (int a = 0; a < n_in; ++a) {
+      double acc = 0.0;
+      for (int i = 0; i < n; ++i) acc += J[(size_t)i * n_in + a] * gy[i];
+      gx[a] = acc;
+    }
+  free(gy);
+  return st;
+}
+
+int orc_est_hessian_greybox(const orc_scene* sc, const double* y, const double* J, int n_in,
+                            double sigma, uint64_t N, uint64_t seed, const orc_opts* o,
+                            double* Hx) {
+  if (!sc || !J || !Hx || n_in <= 0) return -1;
+  int n = sc->n;
+  double* Hy = (double*)malloc((size_t)n * n * sizeof(double));
+  int st = orc_est_hessian(sc, y, sigma, N, seed, o, Hy);
+  if (!st)
+    for (int a = 0; a < n_in; ++a)
+      for (int b = 0; b < n_in; ++b) {
+        double acc = 0.0;
+        for (int i = 0; i < n; ++i)
+          for (int k = 0; k < n; ++k)
+            acc += J[(size_t)i * n_in + a] * Hy[(size_t)i * n + k] * J[(size_t)k * n_in + b];
+        Hx[(size_t)a * n_in + b] = acc;
+      }
+  free(Hy);
+  return st;
+}
+
+int orc_est_hvp_greybox(const orc_scene* sc, const double* y, const double* J, int n_in,
+                        double sigma, uint64_t N, uint64_t seed, const double* vx,
+                        const orc_opts* o, double* Hvx) {
+  if (!sc || !J || !Hvx || !vx || n_in <= 0) return -1;
+  int n = sc->n;
+  double* vy = (double*)malloc((size_t)n * sizeof(double));
+  double* hy = (double*)malloc((size_t)n * sizeof(double));
+  for (int i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int a = 0; a < n_in; ++a) acc += J[(size_t)i * n_in + a] * vx[a];
+    vy[i] = acc;
+  }
+  int st = orc_est_hvp(sc, y, sigma, N, seed, vy, o, hy);
+  if (!st)
+    for (int a = 0; a < n_in; ++a) {
+      double acc = 0.0;
+      for (int i = 0; i < n; ++i) acc += J[(size_t)i * n_in + a] * hy[i];
+      Hvx[a] = acc;
+    }
+  free(vy);
+  free(hy);
+  return st;
 }
 
 /* ========================================================================= */

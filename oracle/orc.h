@@ -28,9 +28,11 @@ typedef struct orc_scene orc_scene;
 #define ORC_AIS   0  /* aggregate importance sampling: one render per draw     */
 #define ORC_IS    1  /* per-element importance sampling: K renders per draw    */
 #define ORC_GAUSS 2  /* plain Gaussian draws, weight = kernel factor ("no IS") */
+#define ORC_FR22  3  /* comparator: per-element streams that blur only the
+                        differentiated dimension (gradient and HVP only)     */
 
 typedef struct {
-  int sampler;          /* ORC_AIS / ORC_IS / ORC_GAUSS                       */
+  int sampler;          /* ORC_AIS / ORC_IS / ORC_GAUSS / ORC_FR22            */
   int antithetic;       /* 1: pair every tau with -tau (A = 2); 0: A = 1     */
   double hvp_rel_step;  /* h = hvp_rel_step * sigma for the central difference */
   int nthreads;         /* worker threads over samples (>= 1)                 */
@@ -81,6 +83,21 @@ int orc_est_hvp(const orc_scene* sc, const double* theta, double sigma, uint64_t
  * the central difference), one render per draw. */
 int orc_est_hvp_limit(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
                       uint64_t seed, const double* v, const orc_opts* o, double* Hv);
+
+/* ---- grey-box composition (appendix "Grey-box differentials") ----
+ * The scene's parameters y = g(x) come from an inner map with known Jacobian
+ * J = dg/dx (n rows = scene parameters, n_in columns, row-major).  The outer
+ * derivatives are sampled at y and composed: grad_x = J^T g_y,
+ * H_x ~ J^T H_y J (the inner map's second derivatives dropped, as in the
+ * appendix), H_x v = J^T (H_y (J v)). */
+int orc_est_grad_greybox(const orc_scene* sc, const double* y, const double* J, int n_in,
+                         double sigma, uint64_t N, uint64_t seed, const orc_opts* o, double* gx);
+int orc_est_hessian_greybox(const orc_scene* sc, const double* y, const double* J, int n_in,
+                            double sigma, uint64_t N, uint64_t seed, const orc_opts* o,
+                            double* Hx);
+int orc_est_hvp_greybox(const orc_scene* sc, const double* y, const double* J, int n_in,
+                        double sigma, uint64_t N, uint64_t seed, const double* vx,
+                        const orc_opts* o, double* Hvx);
 
 /* ---- Newton-CG / modified Newton (section "Previous Work", PSD appendix) ---- */
 typedef struct {

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhrest.so")
 
-AIS, IS, GAUSS = 0, 1, 2
+AIS, IS, GAUSS, FR22 = 0, 1, 2, 3
 STATUS = {0: "HR_OK", -1: "HR_EINVAL", -2: "HR_ENOMEM", -3: "HR_EDEVICE", -4: "HR_EUNSUPPORTED"}
 
 EXPORTED = (
@@ -29,6 +29,7 @@ EXPORTED = (
     "hr_scene_nparams", "hr_render", "hr_est_grad", "hr_est_hessian", "hr_est_hvp",
     "hr_est_hvp_limit", "hr_est_grad_dev", "hr_est_hessian_dev", "hr_est_hvp_dev",
     "hr_newton_cg_step", "hr_newton_cg_step_dev", "hr_dev_alloc", "hr_dev_free", "hr_memcpy",
+    "hr_est_grad_greybox", "hr_est_hessian_greybox", "hr_est_hvp_greybox",
 )
 
 
@@ -96,6 +97,9 @@ def lib():
     for nm in ("hr_newton_cg_step", "hr_newton_cg_step_dev"):
         getattr(L, nm).argtypes = [vp, vp, d, u64, u64, C.POINTER(NcgOpts), C.POINTER(Opts),
                                    C.POINTER(NcgReport)]
+    for nm in ("hr_est_grad_greybox", "hr_est_hessian_greybox"):
+        getattr(L, nm).argtypes = [vp, vp, vp, i, d, u64, u64, C.POINTER(Opts), vp]
+    L.hr_est_hvp_greybox.argtypes = [vp, vp, vp, i, d, u64, u64, vp, C.POINTER(Opts), vp]
     _lib = L
     return L
 
@@ -263,13 +267,13 @@ class Scene:
 def n_renders(kind, n, N, sampler=AIS, antithetic=True):
     A = 2 if antithetic else 1
     K = n * (n + 1) // 2 if kind == "hess" else n
-    streams = K if (sampler == IS and kind != "hvp_limit") else 1
+    streams = K if (sampler in (IS, FR22) and kind != "hvp_limit") else 1
     return streams * N * A * (2 if kind == "hvp" else 1)
 
 
 def n_streams(kind, n, sampler=AIS):
     K = n * (n + 1) // 2 if kind == "hess" else n
-    return K if (sampler == IS and kind != "hvp_limit") else 1
+    return K if (sampler in (IS, FR22) and kind != "hvp_limit") else 1
 
 
 def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic=True,
@@ -347,3 +351,29 @@ def newton_cg_step_dev(scene, d_theta, sigma, N, seed, cg_iters=10, trust_radius
                                        int(seed), C.byref(no), C.byref(o), C.byref(rep)))
     return {"iters_done": rep.iters_done, "hit_trust": rep.hit_trust, "neg_curv": rep.neg_curv,
             "step_norm": rep.step_norm, "g_norm": rep.g_norm}
+
+
+def estimate_greybox(kind, scene, y, J, sigma, N, seed, vx=None, sampler=AIS, antithetic=True,
+                     hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0):
+    """Grey-box composition (hr_est_*_greybox): kind in {'grad', 'hess', 'hvp'};
+    J has shape (n, n_in)."""
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    JJ = np.ascontiguousarray(J, dtype=np.float64)
+    n_in = JJ.shape[1]
+    o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block)
+    L = lib()
+    a = (scene.h, _p(yy), _p(JJ), n_in, float(sigma), int(N), int(seed))
+    if kind == "grad":
+        out = np.zeros(n_in)
+        st = L.hr_est_grad_greybox(*a, C.byref(o), _p(out))
+    elif kind == "hess":
+        out = np.zeros((n_in, n_in))
+        st = L.hr_est_hessian_greybox(*a, C.byref(o), _p(out))
+    elif kind == "hvp":
+        v = np.ascontiguousarray(vx, dtype=np.float64)
+        out = np.zeros(n_in)
+        st = L.hr_est_hvp_greybox(*a, _p(v), C.byref(o), _p(out))
+    else:
+        raise ValueError(kind)
+    _check(st)
+    return out

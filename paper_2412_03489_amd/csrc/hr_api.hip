@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,7 @@ struct hr_ctx {
   struct Pending { std::string name; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::map<std::string, std::pair<uint64_t, double>> stats;
+  std::set<hr_scene*> scenes;   // released (and orphaned) with the context
 };
 
 enum SceneKind { kDisks = 0, kPT = 1, kQuad = 2, kNegGauss = 3 };
@@ -74,6 +76,16 @@ struct hr_scene {
 };
 
 namespace {
+
+void release_scene_memory(hr_scene* sc) {
+  if (sc->target) (void)hipFree(sc->target);
+  if (sc->colors) (void)hipFree(sc->colors);
+  if (sc->radius) (void)hipFree(sc->radius);
+  if (sc->A) (void)hipFree(sc->A);
+  if (sc->b) (void)hipFree(sc->b);
+  sc->target = sc->colors = sc->radius = nullptr;
+  sc->A = sc->b = nullptr;
+}
 
 hr_status ensure(hr_ctx* ctx, void** buf, size_t* have, size_t need) {
   if (need <= *have) return HR_OK;
@@ -142,15 +154,19 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
                   uint64_t seed, const double* d_v, const hr_opts& o, double* d_out,
                   double* h_dbg, double* h_tau) {
   hr_ctx* ctx = sc->ctx;
+  if (!ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(HR_EINVAL, "sigma must be positive and finite");
   if (N == 0 || N >= 0xFFFFFFFFull) return fail(HR_EINVAL, "N must be in [1, 2^32 - 1)");
-  if (o.sampler < 0 || o.sampler > 2) return fail(HR_EINVAL, "unknown sampler");
+  if (o.sampler < 0 || o.sampler > 3) return fail(HR_EINVAL, "unknown sampler");
   if ((what == kHvp || what == kHvpLimit) && !d_v) return fail(HR_EINVAL, "v is NULL");
-  if (what == kHvpLimit && o.sampler == kIS)
+  if (what == kHvpLimit && per_element(o.sampler))
     return fail(HR_EUNSUPPORTED, "the limit-kernel HVP supports the aggregate and Gaussian samplers");
+  if (what == kHess && o.sampler == kFR22)
+    return fail(HR_EUNSUPPORTED, "the FR22 comparator estimates gradients and HVPs only");
   if (what == kHvp && !(o.hvp_rel_step > 0.0) ) return fail(HR_EINVAL, "hvp_rel_step must be positive");
   if (sc->n < 1 || sc->n > 6144) return fail(HR_EINVAL, "parameter count out of range");
   HR_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below report this call's errors only
 
   EstShape e{};
   e.what = what;
@@ -160,7 +176,7 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
   e.K = e.hessk ? e.n * (e.n + 1) / 2 : e.n;
   e.nout = what == kHess ? e.K : e.n;
   e.N = N;
-  e.streams = (o.sampler == kIS && what != kHvpLimit) ? (uint64_t)e.K : 1;
+  e.streams = per_element(o.sampler) ? (uint64_t)e.K : 1;
   e.A = o.antithetic ? 2 : 1;
   e.NH = what == kHvp ? 2 : 1;
   e.R = e.streams * N * (uint64_t)e.A * (uint64_t)e.NH;
@@ -231,6 +247,7 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
 hr_status run_host(hr_scene* sc, int what, const double* theta, double sigma, uint64_t N,
                    uint64_t seed, const double* v, const hr_opts* opts, double* out) {
   if (!sc || !theta || !out) return fail(HR_EINVAL, "NULL argument");
+  if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
   const int n = sc->n;
   if (!finite_all(theta, n)) return fail(HR_EINVAL, "theta has a non-finite entry");
   if (what == kHvp || what == kHvpLimit) {
@@ -313,6 +330,11 @@ void hr_ctx_destroy(hr_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   (void)drain_timers(ctx);
+  for (hr_scene* sc : ctx->scenes) {   // scenes left alive are orphaned
+    release_scene_memory(sc);
+    sc->ctx = nullptr;
+  }
+  ctx->scenes.clear();
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->stage) (void)hipFree(ctx->stage);
   if (ctx->cg) (void)hipFree(ctx->cg);
@@ -424,6 +446,7 @@ hr_status hr_scene_disks(hr_ctx* ctx, int W, int H, int C, int D, int ppd, const
     sc->hradius.assign(radius, radius + D);
   }
   if (st) { hr_scene_destroy(sc); return st; }
+  ctx->scenes.insert(sc);
   *out = sc;
   return HR_OK;
 }
@@ -464,6 +487,7 @@ hr_status hr_scene_pt(hr_ctx* ctx, int W, int H, int spp, int nspheres, const do
   for (int i = 0; i < 7 * nspheres; ++i) d[23 + i] = (float)desc[12 + i];
   hr_status st = upload(target, (size_t)W * H * 3 * 4, (void**)&sc->target);
   if (st) { hr_scene_destroy(sc); return st; }
+  ctx->scenes.insert(sc);
   *out = sc;
   return HR_OK;
 }
@@ -483,6 +507,7 @@ hr_status hr_scene_quad(hr_ctx* ctx, int n, const double* A, const double* b, do
   hr_status st = upload(A, (size_t)n * n * 8, (void**)&sc->A);
   if (!st) st = upload(bb.data(), (size_t)n * 8, (void**)&sc->b);
   if (st) { hr_scene_destroy(sc); return st; }
+  ctx->scenes.insert(sc);
   *out = sc;
   return HR_OK;
 }
@@ -495,19 +520,19 @@ hr_status hr_scene_neggauss(hr_ctx* ctx, int n, double s1, hr_scene** out) {
   sc->kind = kNegGauss;
   sc->n = n;
   sc->s1 = s1;
+  ctx->scenes.insert(sc);
   *out = sc;
   return HR_OK;
 }
 
 void hr_scene_destroy(hr_scene* sc) {
   if (!sc) return;
-  (void)hipSetDevice(sc->ctx->device);
-  (void)hipStreamSynchronize(sc->ctx->stream);
-  if (sc->target) (void)hipFree(sc->target);
-  if (sc->colors) (void)hipFree(sc->colors);
-  if (sc->radius) (void)hipFree(sc->radius);
-  if (sc->A) (void)hipFree(sc->A);
-  if (sc->b) (void)hipFree(sc->b);
+  if (sc->ctx) {   // an orphaned scene (context destroyed first) holds no memory
+    (void)hipSetDevice(sc->ctx->device);
+    (void)hipStreamSynchronize(sc->ctx->stream);
+    release_scene_memory(sc);
+    sc->ctx->scenes.erase(sc);
+  }
   delete sc;
 }
 
@@ -516,6 +541,7 @@ int hr_scene_nparams(const hr_scene* sc) { return sc ? sc->n : -1; }
 hr_status hr_render(hr_scene* sc, const double* theta, uint64_t seed, uint32_t s, int spp,
                     float* image) {
   if (!sc || !theta || !image) return fail(HR_EINVAL, "NULL argument");
+  if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
   if (sc->kind != kDisks && sc->kind != kPT) return fail(HR_EUNSUPPORTED, "analytic scenes have no image");
   if (!finite_all(theta, sc->n)) return fail(HR_EINVAL, "theta has a non-finite entry");
   hr_ctx* ctx = sc->ctx;
@@ -583,11 +609,75 @@ hr_status hr_est_hvp_dev(hr_scene* sc, const double* d_theta, double sigma, uint
   return run_est(sc, kHvp, d_theta, sigma, N, seed, d_v, o, d_Hv, nullptr, nullptr);
 }
 
+// ------------------------------------------------------------ grey-box
+static hr_status run_greybox(hr_scene* sc, int what, const double* y, const double* J, int n_in,
+                             double sigma, uint64_t N, uint64_t seed, const double* vx,
+                             const hr_opts* opts, double* out) {
+  if (!sc || !y || !J || !out || (what == kHvp && !vx)) return fail(HR_EINVAL, "NULL argument");
+  if (n_in < 1 || n_in > 4096) return fail(HR_EINVAL, "n_in must be 1..4096");
+  if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
+  const int n = sc->n;
+  if (!finite_all(y, n)) return fail(HR_EINVAL, "y has a non-finite entry");
+  if (!finite_all(J, (size_t)n * n_in)) return fail(HR_EINVAL, "J has a non-finite entry");
+  if (what == kHvp && !finite_all(vx, n_in)) return fail(HR_EINVAL, "vx has a non-finite entry");
+  hr_opts o = resolve(opts);
+  o.dbg_loss = nullptr;
+  o.dbg_tau = nullptr;
+  hr_ctx* ctx = sc->ctx;
+  HR_HIP(hipSetDevice(ctx->device));
+  const size_t nj = (size_t)n * n_in;
+  const size_t nouty = what == kHess ? (size_t)n * n : (size_t)n;
+  const size_t noutx = what == kHess ? (size_t)n_in * n_in : (size_t)n_in;
+  const size_t need = (2 * (size_t)n + nj + n_in + nouty + nj + noutx) * 8;
+  hr_status st = ensure(ctx, &ctx->stage, &ctx->stage_bytes, need);
+  if (st) return st;
+  double* d_y = (double*)ctx->stage;
+  double* d_vy = d_y + n;
+  double* d_J = d_vy + n;
+  double* d_vx = d_J + nj;
+  double* d_outy = d_vx + n_in;
+  double* d_T = d_outy + nouty;
+  double* d_outx = d_T + nj;
+  hipStream_t s = ctx->stream;
+  HR_HIP(hipMemcpyAsync(d_y, y, (size_t)n * 8, hipMemcpyHostToDevice, s));
+  HR_HIP(hipMemcpyAsync(d_J, J, nj * 8, hipMemcpyHostToDevice, s));
+  if (what == kHvp) {
+    HR_HIP(hipMemcpyAsync(d_vx, vx, (size_t)n_in * 8, hipMemcpyHostToDevice, s));
+    launch_j_vec(s, n, n_in, d_J, d_vx, d_vy);
+  }
+  st = run_est(sc, what, d_y, sigma, N, seed, what == kHvp ? d_vy : nullptr, o, d_outy, nullptr,
+               nullptr);
+  if (st) return st;
+  if (what == kHess) launch_jt_h_j(s, n, n_in, d_J, d_outy, d_T, d_outx);
+  else launch_jt_vec(s, n, n_in, d_J, d_outy, d_outx);
+  HR_HIP(hipGetLastError());
+  HR_HIP(hipMemcpyAsync(out, d_outx, noutx * 8, hipMemcpyDeviceToHost, s));
+  HR_HIP(hipStreamSynchronize(s));
+  return HR_OK;
+}
+
+hr_status hr_est_grad_greybox(hr_scene* sc, const double* y, const double* J, int n_in,
+                              double sigma, uint64_t N, uint64_t seed, const hr_opts* opts,
+                              double* gx) {
+  return run_greybox(sc, kGrad, y, J, n_in, sigma, N, seed, nullptr, opts, gx);
+}
+hr_status hr_est_hessian_greybox(hr_scene* sc, const double* y, const double* J, int n_in,
+                                 double sigma, uint64_t N, uint64_t seed, const hr_opts* opts,
+                                 double* Hx) {
+  return run_greybox(sc, kHess, y, J, n_in, sigma, N, seed, nullptr, opts, Hx);
+}
+hr_status hr_est_hvp_greybox(hr_scene* sc, const double* y, const double* J, int n_in,
+                             double sigma, uint64_t N, uint64_t seed, const double* vx,
+                             const hr_opts* opts, double* Hvx) {
+  return run_greybox(sc, kHvp, y, J, n_in, sigma, N, seed, vx, opts, Hvx);
+}
+
 // ------------------------------------------------------------ Newton-CG
 hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uint64_t N,
                                 uint64_t seed, const hr_ncg_opts* ncg, const hr_opts* opts,
                                 hr_ncg_report* report) {
   if (!sc || !d_theta) return fail(HR_EINVAL, "NULL argument");
+  if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
   hr_ncg_opts no;
   hr_ncg_opts_default(&no);
   if (ncg) no = *ncg;
@@ -651,6 +741,7 @@ hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uin
 hr_status hr_newton_cg_step(hr_scene* sc, double* theta, double sigma, uint64_t N, uint64_t seed,
                             const hr_ncg_opts* ncg, const hr_opts* opts, hr_ncg_report* report) {
   if (!sc || !theta) return fail(HR_EINVAL, "NULL argument");
+  if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
   const int n = sc->n;
   if (!finite_all(theta, n)) return fail(HR_EINVAL, "theta has a non-finite entry");
   hr_ctx* ctx = sc->ctx;

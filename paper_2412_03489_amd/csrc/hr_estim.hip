@@ -34,10 +34,10 @@ __global__ void k_sample(int n, int K, int hessk, int sampler, uint64_t N, uint6
     const uint64_t sidx = gid / (uint64_t)n;
     const uint32_t stream = (uint32_t)(sidx / N);
     const uint32_t s = (uint32_t)(sidx % N);
-    const uint32_t tag = sampler == kIS ? stream : (sampler == kAIS ? kTagAIS : kTagGauss);
+    const uint32_t tag = per_element(sampler) ? stream : (sampler == kAIS ? kTagAIS : kTagGauss);
     const u32x4 w = philox_seeded(seed, s, (uint32_t)j, 0u, tag);
     int m = -1;
-    if (sampler == kIS) m = (int)stream;
+    if (per_element(sampler)) m = (int)stream;
     if (sampler == kAIS) {
       const u32x4 ws = philox_seeded(seed, s, kDimSelect, 0u, tag);
       m = (int)(((uint64_t)ws.x * (uint64_t)K) >> 32);
@@ -56,6 +56,7 @@ __global__ void k_sample(int n, int K, int hessk, int sampler, uint64_t N, uint6
     double t;
     if (ld) t = hdiag_lobe(w.z, sg);
     else if (lg) t = grad_lobe(w.z, sg);
+    else if (sampler == kFR22) t = 0.0;   // only the differentiated dimension is blurred
     else t = sg * sqrt(-2.0 * log(u01_d(w.x))) * cos(2.0 * kPi * u01_d(w.y));
     tau[gid] = t;
   }
@@ -326,7 +327,7 @@ void launch_prep(hipStream_t st, const EstShape& e, const double* f, const doubl
 }
 
 int accum_chunk(const EstShape& e) {
-  if (e.sampler == kIS && e.what != kHvpLimit) return 256;
+  if (per_element(e.sampler)) return 256;
   int c = kLdsDoubles / e.n;
   if (c > 256) c = 256;
   if (c < 1) c = 1;
@@ -336,7 +337,7 @@ int accum_chunk(const EstShape& e) {
 void launch_accum(hipStream_t st, const EstShape& e, const double* tau, const double* Fq,
                   const double* vt, const double* v, int fp64, void* part, int chunk) {
   const uint64_t nchunks = (e.N + chunk - 1) / chunk;
-  if (e.sampler == kIS && e.what != kHvpLimit) {
+  if (per_element(e.sampler)) {
     hipLaunchKernelGGL(k_accum_is, dim3(grid_for(nchunks * e.nout, 128)), dim3(128), 0, st, e, tau,
                        Fq, fp64, chunk, nchunks, part);
   } else {

@@ -9,7 +9,9 @@ namespace hr {
 inline __host__ __device__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
 enum What { kGrad = 0, kHess = 1, kHvp = 2, kHvpLimit = 3 };
-enum Sampler { kAIS = 0, kIS = 1, kGauss = 2 };
+enum Sampler { kAIS = 0, kIS = 1, kGauss = 2, kFR22 = 3 };
+// per-element streams (one stream of draws per estimated element)
+inline __host__ __device__ bool per_element(int sampler) { return sampler == kIS || sampler == kFR22; }
 
 // Shape of one estimator call.  Renders are indexed
 //   r = ((stream * N + s) * A + a) * NH + shift
@@ -97,5 +99,12 @@ void launch_cg_update(hipStream_t st, int n, const double* Hp, double* r, double
 void launch_cg_apply(hipStream_t st, int n, const double* d, double* theta, CgState* cs);
 void launch_newton_full(hipStream_t st, int n, const double* H, const double* g, double delta,
                         double eig_floor, double* work, double* d, CgState* cs);
+
+// ---- grey-box composition (FP64) ----
+// J: n rows (scene parameters) x n_in columns, row-major
+void launch_jt_vec(hipStream_t st, int n, int n_in, const double* J, const double* a, double* out);
+void launch_j_vec(hipStream_t st, int n, int n_in, const double* J, const double* v, double* out);
+void launch_jt_h_j(hipStream_t st, int n, int n_in, const double* J, const double* H, double* T,
+                   double* out);
 
 }  // namespace hr

@@ -242,7 +242,64 @@ __global__ __launch_bounds__(kThreads) void k_newton_full(int n, const double* _
   }
 }
 
+// grey-box composition (appendix "Grey-box differentials"): small FP64
+// contractions with the inner Jacobian, one thread per output element, sums
+// in index order
+__global__ void k_jt_vec(int n, int n_in, const double* __restrict__ J, const double* __restrict__ a,
+                         double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_in) return;
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += J[(size_t)i * n_in + c] * a[i];
+  out[c] = acc;
+}
+
+__global__ void k_j_vec(int n, int n_in, const double* __restrict__ J, const double* __restrict__ v,
+                        double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < n_in; ++c) acc += J[(size_t)i * n_in + c] * v[c];
+  out[i] = acc;
+}
+
+// T = H J (n x n_in)
+__global__ void k_h_j(int n, int n_in, const double* __restrict__ J, const double* __restrict__ H,
+                      double* __restrict__ T) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n_in) return;
+  const int i = (int)(e / n_in), c = (int)(e % n_in);
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) acc += H[(size_t)i * n + k] * J[(size_t)k * n_in + c];
+  T[e] = acc;
+}
+
+// out = J^T T (n_in x n_in)
+__global__ void k_jt_t(int n, int n_in, const double* __restrict__ J, const double* __restrict__ T,
+                       double* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n_in * n_in) return;
+  const int a = (int)(e / n_in), b = (int)(e % n_in);
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += J[(size_t)i * n_in + a] * T[(size_t)i * n_in + b];
+  out[e] = acc;
+}
+
 }  // namespace
+
+void launch_jt_vec(hipStream_t st, int n, int n_in, const double* J, const double* a, double* out) {
+  hipLaunchKernelGGL(k_jt_vec, dim3((n_in + 127) / 128), dim3(128), 0, st, n, n_in, J, a, out);
+}
+void launch_j_vec(hipStream_t st, int n, int n_in, const double* J, const double* v, double* out) {
+  hipLaunchKernelGGL(k_j_vec, dim3((n + 127) / 128), dim3(128), 0, st, n, n_in, J, v, out);
+}
+void launch_jt_h_j(hipStream_t st, int n, int n_in, const double* J, const double* H, double* T,
+                   double* out) {
+  const size_t e1 = (size_t)n * n_in, e2 = (size_t)n_in * n_in;
+  hipLaunchKernelGGL(k_h_j, dim3((unsigned)((e1 + 127) / 128)), dim3(128), 0, st, n, n_in, J, H, T);
+  hipLaunchKernelGGL(k_jt_t, dim3((unsigned)((e2 + 127) / 128)), dim3(128), 0, st, n, n_in, J, T,
+                     out);
+}
 
 void launch_cg_init(hipStream_t st, int n, const double* g, double delta, int modified,
                     double eig_floor, double* r, double* p, double* d, CgState* cs) {

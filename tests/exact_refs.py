@@ -104,3 +104,20 @@ def disk_exact(theta, theta_star, r, W, H_, sigma, nodes=2048):
     g = (sgn[:, None] * gq).mean(0)
     Hm = (sgn[:, None, None] * Hq).mean(0)
     return F, g, 0.5 * (Hm + Hm.T)
+
+
+def corner_fr22_grad(theta, theta_star, W, H_, sigma):
+    """Gradient of the corner scene's loss smoothed along the differentiated
+    dimension only (the FR22 comparator): for d/dtheta_0 the y-edge stays a
+    step, E = T + (1 - 2T) Phi(a) [y_c < theta_1], and symmetrically."""
+    xc = (np.arange(W) + 0.5) / W
+    yc = (np.arange(H_) + 0.5) / H_
+    a = (theta[0] - xc[None, :]) / sigma
+    b = (theta[1] - yc[:, None]) / sigma
+    T = ((xc[None, :] < theta_star[0]) & (yc[:, None] < theta_star[1])).astype(float)
+    sgn = 1 - 2 * T
+    inx = (xc[None, :] < theta[0]).astype(float)
+    iny = (yc[:, None] < theta[1]).astype(float)
+    g0 = np.mean(sgn * stats.norm.pdf(a) / sigma * iny)
+    g1 = np.mean(sgn * inx * stats.norm.pdf(b) / sigma)
+    return np.array([g0, g1])

@@ -40,8 +40,8 @@ def ctx(P):
 
 
 # ------------------------------------------------------------------- draws
-@pytest.mark.parametrize("kind,sampler", [("grad", 0), ("grad", 1), ("grad", 2), ("hess", 0),
-                                          ("hess", 1), ("hess", 2)])
+@pytest.mark.parametrize("kind,sampler", [("grad", 0), ("grad", 1), ("grad", 2), ("grad", 3),
+                                          ("hess", 0), ("hess", 1), ("hess", 2)])
 def test_draws_match_oracle(P, ctx, kind, sampler):
     n = 4
     A = np.eye(n)
@@ -104,7 +104,7 @@ def one_disk(P, ctx):
 
 
 @pytest.mark.parametrize("kind,sampler", [("grad", 0), ("hess", 0), ("grad", 1), ("hess", 1),
-                                          ("grad", 2), ("hess", 2)])
+                                          ("grad", 2), ("hess", 2), ("grad", 3)])
 def test_one_disk_full_size_parity(P, one_disk, kind, sampler):
     """64x64 single disk, N = 4096 draws (the full one-disk workload)."""
     w, osc, gsc = one_disk
@@ -331,6 +331,20 @@ def test_newton_cg_negative_curvature_parity(P, ctx):
     assert rel_inf(got - th0, ref - th0) < 1e-8
 
 
+# ---------------------------------------------------------- grey-box
+@pytest.mark.parametrize("kind", ["grad", "hess", "hvp"])
+def test_greybox_parity(P, ctx, one_disk, kind):
+    """Composite derivatives through an inner Jacobian (2 scene parameters from
+    3 inner ones) on the one-disk scene."""
+    w, osc, gsc = one_disk
+    J = np.array([[1.0, 0.5, -0.2], [0.3, -1.0, 0.8]])
+    vx = np.array([0.4, 1.0, -0.5])
+    say(f"greybox {kind}")
+    ref = O.estimate_greybox(kind, osc, w.theta0, J, w.sigma, 2048, w.seed, vx=vx)
+    got = P.estimate_greybox(kind, gsc, w.theta0, J, w.sigma, 2048, w.seed, vx=vx)
+    assert rel_inf(got, ref) < TOL
+
+
 # ---------------------------------------------------------- device API
 def test_device_pointer_api_matches_host_api(P, ctx, disks32):
     w, _, gsc = disks32
@@ -365,6 +379,8 @@ def test_errors_and_edge_cases(P, ctx, quad_pair):
         P.estimate("hvp", gsc, th, 0.1, 10, 1, v=[np.inf, 0, 0])
     with pytest.raises(P.HrError, match="EUNSUPPORTED"):
         P.estimate("hvp_limit", gsc, th, 0.1, 10, 1, v=[1.0, 0, 0], sampler=1)
+    with pytest.raises(P.HrError, match="EUNSUPPORTED"):
+        P.estimate("hess", gsc, th, 0.1, 10, 1, sampler=3)
     assert np.array_equal(P.estimate("hvp", gsc, th, 0.1, 10, 1, v=np.zeros(3)), np.zeros(3))
     c2 = P.Context(0)
     try:
@@ -377,3 +393,12 @@ def test_errors_and_edge_cases(P, ctx, quad_pair):
         c2.close()
     with pytest.raises(P.HrError, match="EINVAL"):
         P.Scene.disks(ctx, 8, 8, 5, np.ones((1, 5)), np.zeros((8, 8, 5)))
+    # a scene outliving its context is orphaned: calls fail cleanly, and the
+    # next context's launches are unaffected
+    c3 = P.Context(0)
+    s3 = P.Scene.quad(c3, np.eye(3))
+    c3.close()
+    with pytest.raises(P.HrError, match="EINVAL"):
+        P.estimate("grad", s3, th, 0.1, 10, 1)
+    s3.close()
+    assert np.isfinite(P.estimate("grad", gsc, th, 0.1, 10, 1)).all()

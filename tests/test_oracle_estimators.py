@@ -339,3 +339,56 @@ def test_modified_cg_uses_all_products_and_descends(orc):
     F0, _, _ = E.neggauss_exact(th0, s1, sg)
     F1, _, _ = E.neggauss_exact(th, s1, sg)
     assert F1 < F0
+
+
+def test_greybox_linear_inner_map_quadratic(orc):
+    """Appendix "Grey-box differentials": for a linear inner map y = J x + c
+    the composition is exact, so the composite estimates are unbiased for
+    J^T (A y + b), J^T A J and J^T A J v."""
+    A = WL.quad_paper()
+    b = np.array([0.3, -0.2])
+    sc = orc.Scene.quad(A, b, 0.1)
+    J = np.array([[1.0, 0.5, -0.2], [0.3, -1.0, 0.8]])
+    x = np.array([0.2, -0.4, 0.7])
+    y = J @ x + np.array([0.05, -0.1])
+    vx = np.array([0.4, 1.0, -0.5])
+    m, se = seeds_mean_se(lambda s: orc.estimate_greybox("grad", sc, y, J, 0.4, 2000, s), 12)
+    assert_within(m, se, J.T @ (A @ y + b))
+    m, se = seeds_mean_se(lambda s: orc.estimate_greybox("hess", sc, y, J, 0.4, 2000, s), 12)
+    assert_within(m, se, J.T @ A @ J)
+    m, se = seeds_mean_se(lambda s: orc.estimate_greybox("hvp", sc, y, J, 0.4, 2000, s, vx=vx), 12)
+    assert_within(m, se, J.T @ A @ J @ vx)
+    # composition of the same draws: J^T applied to the plain estimate
+    g = orc.estimate("grad", sc, y, 0.4, 500, 3)
+    assert np.allclose(orc.estimate_greybox("grad", sc, y, J, 0.4, 500, 3), J.T @ g, rtol=1e-13)
+
+
+def test_fr22_comparator_pins(orc, quad):
+    """FR22 blurs only the differentiated dimension (appendix on the gradient
+    derivation).  Quadratic: that smoothing only adds a constant, so the
+    gradient is exact in expectation.  One dimension: it is the per-element IS
+    estimator, draw for draw.  Corner scene: the closed form of the 1-D-smoothed
+    derivative (the other edge stays a step)."""
+    sc, A, b = quad
+    th = np.array([0.4, -0.9])
+    g_ex, _ = E.quad_exact(A, b, th)
+    m, se = seeds_mean_se(lambda s: orc.estimate("grad", sc, th, 0.5, 2000, s, sampler=orc.FR22), 12)
+    assert_within(m, se, g_ex)
+    W = 64
+    xc = (np.arange(W) + 0.5) / W
+    edge = orc.Scene.edge(W, 1, 1, (xc < 0.5).astype(np.float32).reshape(1, W, 1))
+    a = orc.estimate("grad", edge, [0.43], 0.05, 777, 8, sampler=orc.FR22)
+    bb = orc.estimate("grad", edge, [0.43], 0.05, 777, 8, sampler=orc.IS)
+    assert np.array_equal(a, bb)
+    Wc = Hc = 32
+    ts = np.array([0.55, 0.45])
+    xc = (np.arange(Wc) + 0.5) / Wc
+    yc = (np.arange(Hc) + 0.5) / Hc
+    tgt = ((xc[None, :] < ts[0]) & (yc[:, None] < ts[1])).astype(np.float32)[..., None]
+    corner = orc.Scene.edge(Wc, Hc, 2, tgt)
+    thc = np.array([0.5, 0.52])
+    m, se = seeds_mean_se(lambda s: orc.estimate("grad", corner, thc, 0.06, 3000, s,
+                                                 sampler=orc.FR22), 10)
+    assert_within(m, se, E.corner_fr22_grad(thc, ts, Wc, Hc, 0.06))
+    with pytest.raises(ValueError):
+        orc.estimate("hess", sc, th, 0.5, 10, 1, sampler=orc.FR22)
