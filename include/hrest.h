@@ -182,6 +182,13 @@ hr_status hr_est_hvp(hr_scene* sc, const double* theta, double sigma, uint64_t N
 hr_status hr_est_hvp_limit(hr_scene* sc, const double* theta, double sigma, uint64_t N,
                            uint64_t seed, const double* v, const hr_opts* opts, double* Hv);
 
+/* Smoothed loss F(theta) = E f(theta - tau), tau ~ N(0, sigma^2 I) (section
+ * "Background"): mean of the renders over N plain Gaussian draws (antithetic
+ * pairs as set in opts; opts->sampler is ignored).  sigma = 0 returns the plain
+ * loss f(theta) of one render.  F: one double (host). */
+hr_status hr_est_loss(hr_scene* sc, const double* theta, double sigma, uint64_t N,
+                      uint64_t seed, const hr_opts* opts, double* F);
+
 /* ---- grey-box composition (appendix "Grey-box differentials") -----------
  * The scene's parameters y = g(x) come from a caller-side inner map with known
  * Jacobian J = dg/dx: n rows (scene parameters) x n_in columns, row-major,
@@ -249,6 +256,35 @@ hr_status hr_newton_cg_step(hr_scene* sc, double* theta, double sigma, uint64_t 
 hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uint64_t N,
                                 uint64_t seed, const hr_ncg_opts* ncg, const hr_opts* opts,
                                 hr_ncg_report* report);
+
+/* ---- optimiser loop (appendix "Hyperparameters") --------------------------
+ * sigma annealed linearly from sigma_start to sigma_end over the iterations;
+ * the step of each iteration comes from Newton-CG, modified Newton on the full
+ * estimated H, or gradient descent; an optional line search halves alpha from
+ * 1 up to ls_iters times until the smoothed loss (N_loss draws, the
+ * iteration's seed for every trial) drops by ls_tol |F|, else alpha = 0;
+ * "recompute" reads as the number of iterations an accepted alpha is reused
+ * before a fresh search.  Iteration t uses draws keyed by seed + t. */
+typedef enum { HR_OPT_NEWTON_CG = 0, HR_OPT_NEWTON_FULL = 1, HR_OPT_GD = 2 } hr_optim_method;
+
+typedef struct {
+  int iters;                       /* outer iterations (default 10)                    */
+  double sigma_start, sigma_end;   /* linear schedule (0.1 -> 0.01)                    */
+  int method;                      /* hr_optim_method (HR_OPT_NEWTON_CG)               */
+  double lr;                       /* gradient-descent step (0.1)                      */
+  int ls_iters;                    /* line-search halvings, 0 = none (0)               */
+  double ls_tol;                   /* relative decrease demanded (1e-3)                */
+  int recompute;                   /* iterations between fresh searches (1)            */
+  uint64_t N_loss;                 /* draws per smoothed-loss estimate (1024)          */
+  hr_ncg_opts ncg;                 /* inner Newton settings (hr_ncg_opts_default)      */
+} hr_optim_opts;
+
+void hr_optim_opts_default(hr_optim_opts* o);
+/* theta (host, n) updated in place.  trace: optional host buffer of iters x 5
+ * doubles -- sigma_t, alpha, |alpha d|, smoothed loss at the new theta
+ * (sigma_t, N_loss draws), plain loss at the new theta. */
+hr_status hr_optimize(hr_scene* sc, double* theta, uint64_t N, uint64_t seed,
+                      const hr_optim_opts* opts_optim, const hr_opts* opts, double* trace);
 
 #ifdef __cplusplus
 }

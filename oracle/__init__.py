@@ -41,6 +41,13 @@ class NcgOpts(C.Structure):
                 ("hvp_limit", C.c_int), ("modified", C.c_int)]
 
 
+class OptimOpts(C.Structure):
+    _fields_ = [("iters", C.c_int), ("sigma_start", C.c_double), ("sigma_end", C.c_double),
+                ("method", C.c_int), ("lr", C.c_double), ("ls_iters", C.c_int),
+                ("ls_tol", C.c_double), ("recompute", C.c_int), ("N_loss", C.c_uint64),
+                ("ncg", NcgOpts)]
+
+
 class NcgReport(C.Structure):
     _fields_ = [("iters_done", C.c_int), ("hit_trust", C.c_int), ("neg_curv", C.c_int),
                 ("step_norm", C.c_double), ("g_norm", C.c_double)]
@@ -81,6 +88,10 @@ def lib():
                                          C.POINTER(Opts), C.POINTER(NcgReport)]
         L.orc_newton_cg_step.restype = i
         L.orc_jacobi_eig.argtypes = [i, vp, vp, vp]; L.orc_jacobi_eig.restype = i
+        L.orc_est_loss.argtypes = [vp, vp, d, u64, u64, C.POINTER(Opts), vp]
+        L.orc_est_loss.restype = i
+        L.orc_optimize.argtypes = [vp, vp, u64, u64, C.POINTER(OptimOpts), C.POINTER(Opts), vp]
+        L.orc_optimize.restype = i
         for nm in ("orc_est_grad_greybox", "orc_est_hessian_greybox"):
             getattr(L, nm).argtypes = [vp, vp, vp, i, d, u64, u64, C.POINTER(Opts), vp]
             getattr(L, nm).restype = i
@@ -295,3 +306,37 @@ def estimate_greybox(kind, scene, y, J, sigma, N, seed, vx=None, sampler=AIS, an
     if st:
         raise ValueError(f"oracle grey-box {kind} failed ({st})")
     return out
+
+
+def est_loss(scene, theta, sigma, N, seed, antithetic=True, nthreads=1):
+    """Smoothed loss by Gaussian draws; sigma = 0 gives the plain loss."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    o = _opts(GAUSS, antithetic, 0.1, nthreads, 0, None)
+    F = C.c_double()
+    st = lib().orc_est_loss(scene.h, _p(th), float(sigma), int(N), int(seed), C.byref(o),
+                            C.byref(F))
+    if st:
+        raise ValueError(f"orc_est_loss failed ({st})")
+    return F.value
+
+
+METHODS = {"newton_cg": 0, "newton_full": 1, "gd": 2}
+
+
+def optimize(scene, theta, N, seed, iters, sigma_start, sigma_end, method="newton_cg", lr=0.1,
+             ls_iters=0, ls_tol=1e-3, recompute=1, N_loss=0, cg_iters=10, trust_radius=1.0,
+             eig_floor=1e-6, modified=False, hvp_limit=False, sampler=AIS, antithetic=True,
+             hvp_rel_step=0.1, nthreads=None):
+    th = np.array(theta, dtype=np.float64)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    o = _opts(sampler, antithetic, hvp_rel_step, nthreads, 0, None)
+    oo = OptimOpts(int(iters), float(sigma_start), float(sigma_end), METHODS[method], float(lr),
+                   int(ls_iters), float(ls_tol), int(recompute), int(N_loss),
+                   NcgOpts(int(cg_iters), float(trust_radius), 0, float(eig_floor),
+                           1 if hvp_limit else 0, 1 if modified else 0))
+    trace = np.zeros((iters, 5))
+    st = lib().orc_optimize(scene.h, _p(th), int(N), int(seed), C.byref(oo), C.byref(o), _p(trace))
+    if st:
+        raise ValueError(f"orc_optimize failed ({st})")
+    return th, trace

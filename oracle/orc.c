@@ -880,6 +880,40 @@ int orc_est_hvp_limit(const orc_scene* sc, const double* theta, double sigma, ui
 }
 
 /* ========================================================================= */
+/* Smoothed loss (section "Background"): F(theta) = E f(theta - tau) over
+ * Gaussian draws (the plain sampler's draws), antithetic pairs as set; the
+ * mean is summed in draw order.  sigma = 0: the plain loss.                   */
+/* ========================================================================= */
+int orc_est_loss(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
+                 uint64_t seed, const orc_opts* o, double* F) {
+  if (!sc || !theta || !F || !o) return -1;
+  int n = sc->n;
+  for (int j = 0; j < n; ++j) if (!isfinite(theta[j])) return -1;
+  if (sigma == 0.0) {
+    *F = orc_loss(sc, theta, seed, 0);
+    return 0;
+  }
+  if (!(sigma > 0) || !isfinite(sigma) || N == 0 || N >= 0xFFFFFFFFull) return -1;
+  int A = o->antithetic ? 2 : 1;
+  double* tau = (double*)malloc((size_t)n * sizeof(double));
+  double* p = (double*)malloc((size_t)n * sizeof(double));
+  nsum acc = {0.0, 0.0};
+  for (uint64_t s = 0; s < N; ++s) {
+    int e;
+    draw(0, n, sigma, seed, (uint32_t)s, ORC_GAUSS, 0, tau, &e);
+    for (int ai = 0; ai < A; ++ai) {
+      double a = ai == 0 ? 1.0 : -1.0;
+      for (int j = 0; j < n; ++j) p[j] = theta[j] - a * tau[j];
+      nsum_add(&acc, orc_loss(sc, p, seed, (uint32_t)s));
+    }
+  }
+  *F = (acc.s + acc.c) / ((double)A * (double)N);
+  free(tau);
+  free(p);
+  return 0;
+}
+
+/* ========================================================================= */
 /* Grey-box composition (appendix "Grey-box differentials"): gradient J^T g_y,
  * Hessian J^T H_y J, HVP J^T H_y J v, with the outer derivatives sampled.    */
 /* ========================================================================= */
@@ -1102,5 +1136,80 @@ int orc_newton_cg_step(const orc_scene* sc, double* theta, double sigma, uint64_
 done:
   if (rep) *rep = R;
   free(g); free(d); free(r); free(p); free(Hp);
+  return st;
+}
+
+/* ========================================================================= */
+/* Optimiser loop (appendix "Hyperparameters"; reading of "recompute" and of
+ * the line search stated in orc.h).                                          */
+/* ========================================================================= */
+int orc_optimize(const orc_scene* sc, double* theta, uint64_t N, uint64_t seed,
+                 const orc_optim_opts* oo, const orc_opts* o, double* trace) {
+  if (!sc || !theta || !oo || !o) return -1;
+  if (oo->iters < 1 || oo->recompute < 1 || oo->ls_iters < 0) return -1;
+  if (!(oo->sigma_start > 0) || !(oo->sigma_end > 0)) return -1;
+  if (oo->method < 0 || oo->method > 2) return -1;
+  if (oo->ls_iters > 0 && oo->N_loss == 0) return -1;
+  int n = sc->n;
+  double* d = (double*)malloc((size_t)n * sizeof(double));
+  double* trial = (double*)malloc((size_t)n * sizeof(double));
+  double alpha_keep = 1.0;
+  int st = 0;
+  for (int t = 0; t < oo->iters; ++t) {
+    double sg = oo->iters > 1
+                    ? oo->sigma_start + (oo->sigma_end - oo->sigma_start) * t / (double)(oo->iters - 1)
+                    : oo->sigma_start;
+    uint64_t sd = seed + (uint64_t)t;
+    if (oo->method == ORC_OPT_GD) {
+      st = orc_est_grad(sc, theta, sg, N, sd, o, d);
+      if (st) break;
+      for (int i = 0; i < n; ++i) d[i] = -oo->lr * d[i];
+    } else {
+      orc_ncg_opts no = oo->ncg;
+      no.use_full_hessian = oo->method == ORC_OPT_NEWTON_FULL;
+      for (int i = 0; i < n; ++i) trial[i] = theta[i];
+      st = orc_newton_cg_step(sc, trial, sg, N, sd, &no, o, NULL);
+      if (st) break;
+      for (int i = 0; i < n; ++i) d[i] = trial[i] - theta[i];
+    }
+    double alpha = 1.0;
+    if (oo->ls_iters > 0) {
+      if (t % oo->recompute == 0) {
+        double F0, F1;
+        st = orc_est_loss(sc, theta, sg, oo->N_loss, sd, o, &F0);
+        if (st) break;
+        alpha = 1.0;
+        int ok = 0;
+        for (int k = 0; k < oo->ls_iters; ++k) {
+          for (int i = 0; i < n; ++i) trial[i] = theta[i] + alpha * d[i];
+          st = orc_est_loss(sc, trial, sg, oo->N_loss, sd, o, &F1);
+          if (st) break;
+          if (F1 <= F0 - oo->ls_tol * fabs(F0)) { ok = 1; break; }
+          alpha *= 0.5;
+        }
+        if (st) break;
+        if (!ok) alpha = 0.0;   /* no decrease found: stay */
+        alpha_keep = alpha;
+      } else {
+        alpha = alpha_keep;
+      }
+    }
+    double sn = 0.0;
+    for (int i = 0; i < n; ++i) {
+      theta[i] += alpha * d[i];
+      sn += (alpha * d[i]) * (alpha * d[i]);
+    }
+    if (trace) {
+      double Fs = 0.0, f = 0.0;
+      uint64_t nl = oo->N_loss > 0 ? oo->N_loss : N;
+      st = orc_est_loss(sc, theta, sg, nl, sd, o, &Fs);
+      if (!st) st = orc_est_loss(sc, theta, 0.0, 1, sd, o, &f);
+      if (st) break;
+      double* row = trace + 5 * (size_t)t;
+      row[0] = sg; row[1] = alpha; row[2] = sqrt(sn); row[3] = Fs; row[4] = f;
+    }
+  }
+  free(d);
+  free(trial);
   return st;
 }

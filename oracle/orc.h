@@ -84,6 +84,19 @@ int orc_est_hvp(const orc_scene* sc, const double* theta, double sigma, uint64_t
 int orc_est_hvp_limit(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
                       uint64_t seed, const double* v, const orc_opts* o, double* Hv);
 
+/* ---- smoothed loss F(theta) = E f(theta - tau), tau ~ N(0, sigma^2 I)
+ * (section "Background"), as the mean over N Gaussian draws (antithetic
+ * pairs as configured); sigma = 0 gives the plain loss f(theta). ---- */
+int orc_est_loss(const orc_scene* sc, const double* theta, double sigma, uint64_t N,
+                 uint64_t seed, const orc_opts* o, double* F);
+
+/* ---- optimiser loop (appendix "Hyperparameters": sigma annealed linearly
+ * from a start to an end value; line search with a number of iterations and
+ * a tolerance; "recompute" = iterations between fresh line searches) ---- */
+#define ORC_OPT_NEWTON_CG 0
+#define ORC_OPT_NEWTON_FULL 1
+#define ORC_OPT_GD 2
+
 /* ---- grey-box composition (appendix "Grey-box differentials") ----
  * The scene's parameters y = g(x) come from an inner map with known Jacobian
  * J = dg/dx (n rows = scene parameters, n_in columns, row-major).  The outer
@@ -119,6 +132,27 @@ typedef struct {
 int orc_newton_cg_step(const orc_scene* sc, double* theta, double sigma, uint64_t N,
                        uint64_t seed, const orc_ncg_opts* no, const orc_opts* o,
                        orc_ncg_report* rep);
+
+typedef struct {
+  int iters;               /* outer iterations                                          */
+  double sigma_start, sigma_end;
+  int method;              /* ORC_OPT_NEWTON_CG / ORC_OPT_NEWTON_FULL / ORC_OPT_GD      */
+  double lr;               /* gradient-descent step                                     */
+  int ls_iters;            /* halvings tried by the line search (0: no line search)     */
+  double ls_tol;           /* accept alpha if F(theta + alpha d) <= F(theta) - tol |F|  */
+  int recompute;           /* a fresh search every `recompute` iterations (>= 1); the
+                              accepted alpha is reused in between                        */
+  uint64_t N_loss;         /* draws of the line search's smoothed-loss estimates        */
+  orc_ncg_opts ncg;        /* inner Newton settings (methods 0 and 1)                   */
+} orc_optim_opts;
+
+/* Iteration t (0-based): sigma_t on the linear schedule, draws keyed by
+ * seed + t; step d from the method; alpha from the line search (1 without);
+ * theta += alpha d.  trace (optional, iters x 5 doubles): sigma_t, alpha,
+ * |alpha d|, smoothed loss at the new theta (sigma_t, N_loss draws, seed + t),
+ * plain loss f at the new theta. */
+int orc_optimize(const orc_scene* sc, double* theta, uint64_t N, uint64_t seed,
+                 const orc_optim_opts* oo, const orc_opts* o, double* trace);
 int orc_jacobi_eig(int n, const double* A, double* evals, double* evecs);
 
 #ifdef __cplusplus

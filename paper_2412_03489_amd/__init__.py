@@ -30,6 +30,7 @@ EXPORTED = (
     "hr_est_hvp_limit", "hr_est_grad_dev", "hr_est_hessian_dev", "hr_est_hvp_dev",
     "hr_newton_cg_step", "hr_newton_cg_step_dev", "hr_dev_alloc", "hr_dev_free", "hr_memcpy",
     "hr_est_grad_greybox", "hr_est_hessian_greybox", "hr_est_hvp_greybox",
+    "hr_est_loss", "hr_optim_opts_default", "hr_optimize",
 )
 
 
@@ -49,6 +50,13 @@ class NcgOpts(C.Structure):
     _fields_ = [("cg_iters", C.c_int), ("trust_radius", C.c_double),
                 ("use_full_hessian", C.c_int), ("eig_floor", C.c_double), ("hvp_limit", C.c_int),
                 ("modified", C.c_int)]
+
+
+class OptimOpts(C.Structure):
+    _fields_ = [("iters", C.c_int), ("sigma_start", C.c_double), ("sigma_end", C.c_double),
+                ("method", C.c_int), ("lr", C.c_double), ("ls_iters", C.c_int),
+                ("ls_tol", C.c_double), ("recompute", C.c_int), ("N_loss", C.c_uint64),
+                ("ncg", NcgOpts)]
 
 
 class NcgReport(C.Structure):
@@ -100,6 +108,9 @@ def lib():
     for nm in ("hr_est_grad_greybox", "hr_est_hessian_greybox"):
         getattr(L, nm).argtypes = [vp, vp, vp, i, d, u64, u64, C.POINTER(Opts), vp]
     L.hr_est_hvp_greybox.argtypes = [vp, vp, vp, i, d, u64, u64, vp, C.POINTER(Opts), vp]
+    L.hr_est_loss.argtypes = [vp, vp, d, u64, u64, C.POINTER(Opts), vp]
+    L.hr_optim_opts_default.argtypes = [C.POINTER(OptimOpts)]
+    L.hr_optimize.argtypes = [vp, vp, u64, u64, C.POINTER(OptimOpts), C.POINTER(Opts), vp]
     _lib = L
     return L
 
@@ -377,3 +388,33 @@ def estimate_greybox(kind, scene, y, J, sigma, N, seed, vx=None, sampler=AIS, an
         raise ValueError(kind)
     _check(st)
     return out
+
+
+def est_loss(scene, theta, sigma, N, seed, antithetic=True):
+    """Smoothed loss (hr_est_loss); sigma = 0 gives the plain loss."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    o = make_opts(GAUSS, antithetic)
+    F = C.c_double()
+    _check(lib().hr_est_loss(scene.h, _p(th), float(sigma), int(N), int(seed), C.byref(o),
+                             C.byref(F)))
+    return F.value
+
+
+METHODS = {"newton_cg": 0, "newton_full": 1, "gd": 2}
+
+
+def optimize(scene, theta, N, seed, iters, sigma_start, sigma_end, method="newton_cg", lr=0.1,
+             ls_iters=0, ls_tol=1e-3, recompute=1, N_loss=0, cg_iters=10, trust_radius=1.0,
+             eig_floor=1e-6, modified=False, hvp_limit=False, sampler=AIS, antithetic=True,
+             hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0):
+    """Optimiser loop (hr_optimize); returns (theta, trace[iters, 5])."""
+    th = np.array(theta, dtype=np.float64)
+    o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block)
+    oo = OptimOpts(int(iters), float(sigma_start), float(sigma_end), METHODS[method], float(lr),
+                   int(ls_iters), float(ls_tol), int(recompute), int(N_loss),
+                   NcgOpts(int(cg_iters), float(trust_radius), 0, float(eig_floor),
+                           1 if hvp_limit else 0, 1 if modified else 0))
+    trace = np.zeros((iters, 5))
+    _check(lib().hr_optimize(scene.h, _p(th), int(N), int(seed), C.byref(oo), C.byref(o),
+                             _p(trace)))
+    return th, trace

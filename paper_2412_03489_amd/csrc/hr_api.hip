@@ -151,11 +151,21 @@ hr_opts resolve(const hr_opts* o) {
 
 // the estimator pipeline on device pointers
 hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, uint64_t N,
-                  uint64_t seed, const double* d_v, const hr_opts& o, double* d_out,
+                  uint64_t seed, const double* d_v, const hr_opts& o_in, double* d_out,
                   double* h_dbg, double* h_tau) {
   hr_ctx* ctx = sc->ctx;
   if (!ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
-  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(HR_EINVAL, "sigma must be positive and finite");
+  hr_opts o = o_in;
+  if (what == kLoss) {
+    // the smoothed loss uses the plain Gaussian draws; sigma = 0: one render at theta
+    o.sampler = kGauss;
+    if (sigma == 0.0) {
+      N = 1;
+      o.antithetic = 0;
+    }
+  }
+  if (!(what == kLoss && sigma == 0.0) && (!(sigma > 0.0) || !std::isfinite(sigma)))
+    return fail(HR_EINVAL, "sigma must be positive and finite");
   if (N == 0 || N >= 0xFFFFFFFFull) return fail(HR_EINVAL, "N must be in [1, 2^32 - 1)");
   if (o.sampler < 0 || o.sampler > 3) return fail(HR_EINVAL, "unknown sampler");
   if ((what == kHvp || what == kHvpLimit) && !d_v) return fail(HR_EINVAL, "v is NULL");
@@ -173,8 +183,8 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
   e.sampler = o.sampler;
   e.n = sc->n;
   e.hessk = (what == kHess || what == kHvpLimit) ? 1 : 0;
-  e.K = e.hessk ? e.n * (e.n + 1) / 2 : e.n;
-  e.nout = what == kHess ? e.K : e.n;
+  e.K = what == kLoss ? 1 : (e.hessk ? e.n * (e.n + 1) / 2 : e.n);
+  e.nout = what == kHess ? e.K : (what == kLoss ? 1 : e.n);
   e.N = N;
   e.streams = per_element(o.sampler) ? (uint64_t)e.K : 1;
   e.A = o.antithetic ? 2 : 1;
@@ -257,7 +267,7 @@ hr_status run_host(hr_scene* sc, int what, const double* theta, double sigma, ui
   hr_opts o = resolve(opts);
   hr_ctx* ctx = sc->ctx;
   HR_HIP(hipSetDevice(ctx->device));
-  const size_t nout = what == kHess ? (size_t)n * n : (size_t)n;
+  const size_t nout = what == kHess ? (size_t)n * n : (what == kLoss ? 1 : (size_t)n);
   if (what == kHvp || what == kHvpLimit) {
     bool zero = true;
     for (int i = 0; i < n; ++i) zero = zero && v[i] == 0.0;
@@ -609,6 +619,11 @@ hr_status hr_est_hvp_dev(hr_scene* sc, const double* d_theta, double sigma, uint
   return run_est(sc, kHvp, d_theta, sigma, N, seed, d_v, o, d_Hv, nullptr, nullptr);
 }
 
+hr_status hr_est_loss(hr_scene* sc, const double* theta, double sigma, uint64_t N, uint64_t seed,
+                      const hr_opts* opts, double* F) {
+  return run_host(sc, kLoss, theta, sigma, N, seed, nullptr, opts, F);
+}
+
 // ------------------------------------------------------------ grey-box
 static hr_status run_greybox(hr_scene* sc, int what, const double* y, const double* J, int n_in,
                              double sigma, uint64_t N, uint64_t seed, const double* vx,
@@ -734,6 +749,92 @@ hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uin
     report->neg_curv = h.neg_curv;
     report->step_norm = h.step_norm;
     report->g_norm = h.gnorm;
+  }
+  return HR_OK;
+}
+
+void hr_optim_opts_default(hr_optim_opts* o) {
+  if (!o) return;
+  o->iters = 10;
+  o->sigma_start = 0.1;
+  o->sigma_end = 0.01;
+  o->method = HR_OPT_NEWTON_CG;
+  o->lr = 0.1;
+  o->ls_iters = 0;
+  o->ls_tol = 1e-3;
+  o->recompute = 1;
+  o->N_loss = 1024;
+  hr_ncg_opts_default(&o->ncg);
+}
+
+// Outer loop of the optimiser.  Every estimate and Newton/CG solve runs in
+// the library's kernels; the O(n) update theta += alpha d is done here in FP64.
+hr_status hr_optimize(hr_scene* sc, double* theta, uint64_t N, uint64_t seed,
+                      const hr_optim_opts* oo_in, const hr_opts* opts, double* trace) {
+  if (!sc || !theta) return fail(HR_EINVAL, "NULL argument");
+  if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
+  hr_optim_opts oo;
+  hr_optim_opts_default(&oo);
+  if (oo_in) oo = *oo_in;
+  if (oo.iters < 1 || oo.recompute < 1 || oo.ls_iters < 0) return fail(HR_EINVAL, "bad iteration counts");
+  if (!(oo.sigma_start > 0.0) || !(oo.sigma_end > 0.0)) return fail(HR_EINVAL, "sigma schedule must be positive");
+  if (oo.method < 0 || oo.method > 2) return fail(HR_EINVAL, "unknown method");
+  if (oo.ls_iters > 0 && oo.N_loss == 0) return fail(HR_EINVAL, "N_loss must be positive");
+  const int n = sc->n;
+  if (!finite_all(theta, n)) return fail(HR_EINVAL, "theta has a non-finite entry");
+  std::vector<double> d(n), trial(n);
+  double alpha_keep = 1.0;
+  hr_status st = HR_OK;
+  for (int t = 0; t < oo.iters; ++t) {
+    const double sg = oo.iters > 1
+                          ? oo.sigma_start + (oo.sigma_end - oo.sigma_start) * t / (double)(oo.iters - 1)
+                          : oo.sigma_start;
+    const uint64_t sd = seed + (uint64_t)t;
+    if (oo.method == HR_OPT_GD) {
+      st = hr_est_grad(sc, theta, sg, N, sd, opts, d.data());
+      if (st) return st;
+      for (int i = 0; i < n; ++i) d[i] = -oo.lr * d[i];
+    } else {
+      hr_ncg_opts no = oo.ncg;
+      no.use_full_hessian = oo.method == HR_OPT_NEWTON_FULL;
+      trial.assign(theta, theta + n);
+      st = hr_newton_cg_step(sc, trial.data(), sg, N, sd, &no, opts, nullptr);
+      if (st) return st;
+      for (int i = 0; i < n; ++i) d[i] = trial[i] - theta[i];
+    }
+    double alpha = 1.0;
+    if (oo.ls_iters > 0) {
+      if (t % oo.recompute == 0) {
+        double F0, F1;
+        st = hr_est_loss(sc, theta, sg, oo.N_loss, sd, opts, &F0);
+        if (st) return st;
+        bool ok = false;
+        for (int k = 0; k < oo.ls_iters; ++k) {
+          for (int i = 0; i < n; ++i) trial[i] = theta[i] + alpha * d[i];
+          st = hr_est_loss(sc, trial.data(), sg, oo.N_loss, sd, opts, &F1);
+          if (st) return st;
+          if (F1 <= F0 - oo.ls_tol * std::fabs(F0)) { ok = true; break; }
+          alpha *= 0.5;
+        }
+        if (!ok) alpha = 0.0;   // no decrease found: stay
+        alpha_keep = alpha;
+      } else {
+        alpha = alpha_keep;
+      }
+    }
+    double sn = 0.0;
+    for (int i = 0; i < n; ++i) {
+      theta[i] += alpha * d[i];
+      sn += (alpha * d[i]) * (alpha * d[i]);
+    }
+    if (trace) {
+      double Fs = 0.0, f = 0.0;
+      st = hr_est_loss(sc, theta, sg, oo.N_loss > 0 ? oo.N_loss : N, sd, opts, &Fs);
+      if (!st) st = hr_est_loss(sc, theta, 0.0, 1, sd, opts, &f);
+      if (st) return st;
+      double* row = trace + 5 * (size_t)t;
+      row[0] = sg; row[1] = alpha; row[2] = std::sqrt(sn); row[3] = Fs; row[4] = f;
+    }
   }
   return HR_OK;
 }

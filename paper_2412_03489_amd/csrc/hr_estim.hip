@@ -142,7 +142,8 @@ __global__ void k_prep(EstShape e, const double* __restrict__ f, const double* _
       if (e.A == 2) F1 = f[r0 + 1];
     }
     double F = F0;
-    if (e.A == 2) F = e.hessk ? F0 + F1 : F0 - F1;
+    // even weights (Hessian kernel, plain loss) add the antithetic partner
+    if (e.A == 2) F = (e.hessk || e.what == kLoss) ? F0 + F1 : F0 - F1;
     const double* t = tau + sidx * (uint64_t)e.n;
     const double sg = e.sigma, s2 = sg * sg;
     if (e.sampler == kAIS) {
@@ -176,6 +177,7 @@ __global__ void k_prep(EstShape e, const double* __restrict__ f, const double* _
 // kernel factor d_m(tau) (output m; Hessian elements from (i, j))
 __device__ __forceinline__ double kfac(const EstShape& e, int m, int i, int j,
                                        const double* t, double vts, const double* v) {
+  if (e.what == kLoss) return 1.0;   // smoothed loss: plain mean of the renders
   const double s2 = e.sigma * e.sigma;
   if (e.what == kHvpLimit) return t[m] * vts / (s2 * s2) - v[m] / s2;
   if (!e.hessk) return -t[m] / s2;

@@ -8,7 +8,7 @@ namespace hr {
 
 inline __host__ __device__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
-enum What { kGrad = 0, kHess = 1, kHvp = 2, kHvpLimit = 3 };
+enum What { kGrad = 0, kHess = 1, kHvp = 2, kHvpLimit = 3, kLoss = 4 };
 enum Sampler { kAIS = 0, kIS = 1, kGauss = 2, kFR22 = 3 };
 // per-element streams (one stream of draws per estimated element)
 inline __host__ __device__ bool per_element(int sampler) { return sampler == kIS || sampler == kFR22; }

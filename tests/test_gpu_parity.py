@@ -331,6 +331,31 @@ def test_newton_cg_negative_curvature_parity(P, ctx):
     assert rel_inf(got - th0, ref - th0) < 1e-8
 
 
+# ---------------------------------------------------------- loss and optimiser
+def test_smoothed_loss_parity(P, one_disk, disks32, pt_small):
+    for (w, osc, gsc) in (one_disk, disks32, pt_small):
+        say(f"loss {w.name}")
+        for sg in (0.0, w.sigma):
+            ref = O.est_loss(osc, w.theta0, sg, 256, w.seed)
+            got = P.est_loss(gsc, w.theta0, sg, 256, w.seed)
+            assert abs(got - ref) <= 2e-5 * abs(ref) + 1e-12, (w.name, sg, got, ref)
+
+
+@pytest.mark.parametrize("method", ["newton_cg", "newton_full", "gd"])
+def test_optimiser_parity(P, one_disk, method):
+    """Three iterations of the optimiser loop with sigma annealing and line
+    search: the trajectory follows the oracle's."""
+    w, osc, gsc = one_disk
+    kw = dict(iters=3, sigma_start=0.1, sigma_end=0.05, method=method, lr=0.02, ls_iters=3,
+              ls_tol=1e-3, recompute=1, N_loss=256, cg_iters=2, trust_radius=0.1, eig_floor=1.0)
+    say(f"optimiser {method}")
+    ref, tr_r = O.optimize(osc, w.theta0, 1024, 1, **kw)
+    got, tr_g = P.optimize(gsc, w.theta0, 1024, 1, **kw)
+    assert np.array_equal(tr_g[:, 1], tr_r[:, 1])          # same line-search decisions
+    assert rel_inf(got - w.theta0, ref - w.theta0) < 1e-3
+    assert np.allclose(tr_g[:, 3], tr_r[:, 3], rtol=2e-5)
+
+
 # ---------------------------------------------------------- grey-box
 @pytest.mark.parametrize("kind", ["grad", "hess", "hvp"])
 def test_greybox_parity(P, ctx, one_disk, kind):

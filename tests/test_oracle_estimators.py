@@ -392,3 +392,53 @@ def test_fr22_comparator_pins(orc, quad):
     assert_within(m, se, E.corner_fr22_grad(thc, ts, Wc, Hc, 0.06))
     with pytest.raises(ValueError):
         orc.estimate("hess", sc, th, 0.5, 10, 1, sampler=orc.FR22)
+
+
+# ------------------------------------------------------ loss and optimiser
+def test_smoothed_loss_closed_forms(orc, quad):
+    """F(theta) = E f(theta - tau): quadratic f + sigma^2 tr(A)/2; negated
+    Gaussian -N(theta; 0, (s1^2 + sigma^2) I); half-plane erf sum; sigma = 0
+    is the plain loss."""
+    sc, A, b = quad
+    th = np.array([0.4, -0.9])
+    f0 = 0.5 * th @ A @ th + b @ th + 0.7
+    m, se = seeds_mean_se(lambda s: orc.est_loss(sc, th, 0.5, 4000, s), 10)
+    assert_within(m, se, f0 + 0.25 * np.trace(A) / 2)
+    assert orc.est_loss(sc, th, 0.0, 1, 0) == pytest.approx(f0, rel=1e-14)
+    ng = orc.Scene.neggauss(2, 1.0)
+    F, _, _ = E.neggauss_exact(th, 1.0, 0.5)
+    m, se = seeds_mean_se(lambda s: orc.est_loss(ng, th, 0.5, 4000, s), 10)
+    assert_within(m, se, F)
+    W = 64
+    xc = (np.arange(W) + 0.5) / W
+    edge = orc.Scene.edge(W, 1, 1, (xc < 0.5).astype(np.float32).reshape(1, W, 1))
+    F, _, _ = E.halfplane_exact(0.43, 0.5, W, 0.05)
+    m, se = seeds_mean_se(lambda s: orc.est_loss(edge, [0.43], 0.05, 4000, s), 10)
+    assert_within(m, se, F)
+
+
+def test_optimiser_schedule_and_second_order_advantage(orc, one_disk):
+    """Appendix "Hyperparameters": sigma annealed linearly; the second-order
+    methods reach the one-disk target far faster than gradient descent (the
+    paper's main claim, on its two-parameter plateau task with a disk)."""
+    w, sc, _ = one_disk
+    common = dict(iters=8, sigma_start=0.1, sigma_end=0.02, ls_iters=4, ls_tol=1e-3,
+                  recompute=1, N_loss=512)
+    th_n, tr_n = orc.optimize(sc, w.theta0, 1024, 1, method="newton_cg", cg_iters=2,
+                              trust_radius=0.1, **common)
+    th_g, tr_g = orc.optimize(sc, w.theta0, 1024, 1, method="gd", lr=0.02, **common)
+    assert np.allclose(tr_n[:, 0], np.linspace(0.1, 0.02, 8), rtol=1e-14)
+    assert np.linalg.norm(th_n - w.theta_star) < 0.01
+    assert np.linalg.norm(th_n - w.theta_star) < 0.2 * np.linalg.norm(th_g - w.theta_star)
+    # the line search only moves on a decrease of the smoothed loss: alpha in {0, 2^-k}
+    for a in tr_n[:, 1]:
+        assert a == 0.0 or np.log2(a) == np.round(np.log2(a))
+
+
+def test_optimiser_recompute_reuses_alpha(orc, quad):
+    sc, A, b = quad
+    th, tr = orc.optimize(sc, [2.0, -2.0], 2000, 4, iters=6, sigma_start=0.3, sigma_end=0.3,
+                          method="gd", lr=0.05, ls_iters=3, ls_tol=0.0, recompute=3,
+                          N_loss=2000)
+    assert tr[1, 1] == tr[0, 1] and tr[2, 1] == tr[0, 1]
+    assert tr[4, 1] == tr[3, 1] and tr[5, 1] == tr[3, 1]
