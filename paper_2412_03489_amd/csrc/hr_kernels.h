@@ -47,6 +47,19 @@ struct RasterExact {
   int n, ppd, A, NH;
   double h;
 };
+// One query's raster work: records of renders [0, R) (r_base = global index
+// of render 0 for the exact path), 32x32 tiles, S renders per work item.
+struct RasterQuery {
+  const float4* rec;
+  const float* target;
+  const float* colors;
+  float* partial;
+  int W, H, C, D, S, tiles_x, tiles, pad;
+  uint64_t R, r_base;
+  RasterExact ex;
+};
+size_t raster_lds_bytes(int D, int S);
+int raster_max_samples();
 void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
                     const double* tau, const double* u, float4* rec);
 // number of 32x32 tiles; partial[r * tiles + t]

@@ -121,25 +121,23 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// One block's work: renders [r0, r0 + nr) of one query on one 32x32 tile.
+// Shared by the per-query kernel and the persistent batch kernel, so a render's
+// tile partial is the same bits whichever launch computes it.
 template <int C, bool kOneGroup>
-__global__ __launch_bounds__(256) void k_raster_loss(
-    const float4* __restrict__ rec, const float* __restrict__ target,
-    const float* __restrict__ colors, int W, int H, int D, uint64_t R, int S, int tiles_x,
-    int tiles, uint64_t chunks, uint64_t r_base, RasterExact ex, float* __restrict__ partial) {
-  extern __shared__ float4 smem[];
+__device__ __forceinline__ void raster_block(const RasterQuery& a, int tile, uint64_t r0, int nr,
+                                             float4* smem) {
+  const int W = a.W, H = a.H, D = a.D, S = a.S, tiles_x = a.tiles_x, tiles = a.tiles;
+  const float4* __restrict__ rec = a.rec;
+  const float* __restrict__ target = a.target;
+  const float* __restrict__ colors = a.colors;
+  float* __restrict__ partial = a.partial;
+  const RasterExact& ex = a.ex;
+  const uint64_t r_base = a.r_base;
   float4* s_col = smem;                        // D + 1 colours, index 0 = background
   float* s_q = (float*)(smem + (D + 1));       // [S][4 waves][kQuadStride]
   float* s_cc = s_q + S * 4 * kQuadStride;     // D + 1 squared norms (C == 4)
-
-  // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
-  // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
-  const uint64_t b = blockIdx.x;
-  const uint64_t xcd = b & 7u, j = b >> 3;
-  const uint64_t chunk = (j / (uint64_t)tiles) * 8u + xcd;
-  const int tile = (int)(j % (uint64_t)tiles);
-  if (chunk >= chunks) return;
-  const uint64_t r0 = chunk * (uint64_t)S;
-  const int nr = (int)min((uint64_t)S, R - r0);
+  __syncthreads();   // the previous work item's readers of LDS are done
 
   // colour table: channels, and |c|^2 in .w (C <= 3) or in s_cc (C == 4)
   for (int k = threadIdx.x; k <= D; k += blockDim.x) {
@@ -297,6 +295,21 @@ __global__ __launch_bounds__(256) void k_raster_loss(
   }
 }
 
+template <int C, bool kOneGroup>
+__global__ __launch_bounds__(256) void k_raster_loss(RasterQuery a, uint64_t chunks) {
+  extern __shared__ float4 smem[];
+  // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
+  // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
+  const uint64_t b = blockIdx.x;
+  const uint64_t xcd = b & 7u, j = b >> 3;
+  const uint64_t chunk = (j / (uint64_t)a.tiles) * 8u + xcd;
+  const int tile = (int)(j % (uint64_t)a.tiles);
+  if (chunk >= chunks) return;
+  const uint64_t r0 = chunk * (uint64_t)a.S;
+  const int nr = (int)min((uint64_t)a.S, a.R - r0);
+  raster_block<C, kOneGroup>(a, tile, r0, nr, smem);
+}
+
 // one wave per render: fixed-order FP64 sum of the tile partials
 __global__ void k_tile_reduce(const float* __restrict__ partial, uint64_t R, int tiles,
                               double inv_count, double* __restrict__ f) {
@@ -341,14 +354,20 @@ void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const
 
 int raster_tiles(int W, int H) { return ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile); }
 
+size_t raster_lds_bytes(int D, int S) {
+  return (size_t)(D + 1) * sizeof(float4) + (size_t)S * 4 * kQuadStride * sizeof(float) +
+         (size_t)(D + 1) * sizeof(float);
+}
+
+int raster_max_samples() { return kMaxS; }
+
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
                         int S, const RasterExact& ex, float* partial) {
   if (S <= 0 || S > kMaxS) S = kMaxS;
   const int tiles_x = (s.W + kTile - 1) / kTile;
   const int tiles = raster_tiles(s.W, s.H);
   const uint64_t chunks = (R + S - 1) / S;
-  const size_t lds = (size_t)(s.D + 1) * sizeof(float4) + (size_t)S * 4 * kQuadStride * sizeof(float) +
-                    (size_t)(s.D + 1) * sizeof(float);
+  const size_t lds = raster_lds_bytes(s.D, S);
   // grid: 8 XCD lanes x tiles x ceil(chunks / 8); launched in slices that keep
   // the block count within the grid limit
   const uint64_t per_xcd = (chunks + 7) / 8;
@@ -357,14 +376,19 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
     const uint64_t rows = umin64(max_rows, per_xcd - row0);
     const uint64_t sub_chunks = umin64(chunks - row0 * 8, rows * 8);
     const uint64_t r_base = row0 * 8 * (uint64_t)S;
-    const uint64_t sub_R = umin64(R - r_base, sub_chunks * (uint64_t)S);
-    const float4* rec_s = rec + r_base * (uint64_t)s.D;
-    float* part_s = partial + r_base * (uint64_t)tiles;
+    RasterQuery a;
+    a.rec = rec + r_base * (uint64_t)s.D;
+    a.target = s.target;
+    a.colors = s.colors;
+    a.partial = partial + r_base * (uint64_t)tiles;
+    a.W = s.W; a.H = s.H; a.C = s.C; a.D = s.D; a.S = S;
+    a.tiles_x = tiles_x; a.tiles = tiles;
+    a.R = umin64(R - r_base, sub_chunks * (uint64_t)S);
+    a.r_base = r_base;
+    a.ex = ex;
     const dim3 grid((unsigned)(8 * tiles * rows));
-#define HR_RASTER(CC, ONE)                                                                \
-  hipLaunchKernelGGL((k_raster_loss<CC, ONE>), grid, dim3(256), lds, st, rec_s, s.target,   \
-                     s.colors, s.W, s.H, s.D, sub_R, S, tiles_x, tiles, sub_chunks, r_base, \
-                     ex, part_s)
+#define HR_RASTER(CC, ONE) \
+  hipLaunchKernelGGL((k_raster_loss<CC, ONE>), grid, dim3(256), lds, st, a, sub_chunks)
     const bool one = s.D <= 64;
     switch (s.C) {
       case 1: if (one) HR_RASTER(1, true); else HR_RASTER(1, false); break;
