@@ -56,6 +56,7 @@ typedef enum {
   HR_ENOMEM = -2,
   HR_EDEVICE = -3,
   HR_EUNSUPPORTED = -4,
+  HR_EBUSY = -5,          /* nothing completed within the wait's time limit */
 } hr_status;
 
 /* Sampler (section "Aggregate", table of evaluations per draw).
@@ -81,6 +82,10 @@ typedef struct {
   double hvp_rel_step;  /* HVP central-difference step h = hvp_rel_step * sigma (0.1) */
   int accum_fp64;       /* 0 (default): compensated-FP32 lobe sums; 1: FP64 sums        */
   int samples_per_block;/* renders per raster/path-tracer block; 0 = library choice     */
+  int raster_tile;      /* raster block of 16x16 wave tiles: 0 = library choice,
+                           1 = 32x32, 2 = 64x16, 3 = 16x64.  Neither this nor
+                           samples_per_block changes any result bit: every wave
+                           tile's loss partial is summed in a fixed order.          */
   double* dbg_loss;     /* optional host buffer receiving every render's loss, in the
                            order ((stream*N + s)*A + a)*S + shift, with a = 0 for
                            theta - tau, 1 for theta + tau, shift = 0 for +h, 1 for -h
@@ -285,6 +290,121 @@ void hr_optim_opts_default(hr_optim_opts* o);
  * (sigma_t, N_loss draws), plain loss at the new theta. */
 hr_status hr_optimize(hr_scene* sc, double* theta, uint64_t N, uint64_t seed,
                       const hr_optim_opts* opts_optim, const hr_opts* opts, double* trace);
+
+/* ---- batched queries ------------------------------------------------------
+ * Many independent estimator queries -- any scenes of one context, any kinds,
+ * image sizes, parameter counts and sample budgets -- run together: one
+ * launch per pipeline step over all queries, and one persistent launch each
+ * for the rasteriser and the path tracer that takes (query, chunk, tile) work
+ * items from per-XCD queues, longest items first.  The launch sequence is
+ * fixed (all per-batch data is in one device table), so it is captured once
+ * as a hipGraph and replayed for every later batch.  Each result is the same
+ * bits as the single-query entry point returns for the same query, whatever
+ * the batch around it and whatever samples_per_block / raster_tile. */
+typedef enum {
+  HR_QUERY_GRAD = 0,        /* out: n doubles                                   */
+  HR_QUERY_HESSIAN = 1,     /* out: n*n doubles                                 */
+  HR_QUERY_HVP = 2,         /* out: n doubles; v required                       */
+  HR_QUERY_HVP_LIMIT = 3,   /* out: n doubles; v required                       */
+  HR_QUERY_LOSS = 4         /* out: 1 double (smoothed loss; sigma = 0: plain)  */
+} hr_query_kind;
+
+typedef struct {
+  hr_scene* scene;
+  int kind;                 /* hr_query_kind                                    */
+  double sigma;
+  uint64_t N;               /* draws                                            */
+  uint64_t seed;
+  const double* theta;      /* host, n doubles; read during the call            */
+  const double* v;          /* host, n doubles (HVP kinds), else NULL           */
+  const hr_opts* opts;      /* NULL = defaults; dbg buffers must be NULL        */
+  double* out;              /* host result buffer (see hr_query_kind)           */
+} hr_query;
+
+typedef struct {
+  int use_graph;            /* 1 (default): replay the launches as a hipGraph   */
+  int autotune;             /* 1: before a batch, time samples-per-block and
+                               block shape for every not yet tuned class of
+                               disk scene (channels, disk count, image size
+                               buckets) and keep the fastest in the context;
+                               0 (default): 64 renders per 32x32 block        */
+} hr_batch_opts;
+
+typedef struct {
+  uint64_t queries;         /* queries in the last run                          */
+  uint64_t raster_items;    /* work items of the persistent rasteriser          */
+  uint64_t pt_items;        /* work items of the persistent path tracer         */
+  int raster_blocks;        /* persistent grid sizes                            */
+  int pt_blocks;
+  uint64_t workspace_bytes; /* device workspace of the batch                    */
+  uint64_t lds_bytes;       /* dynamic LDS of the persistent rasteriser         */
+  int graph;                /* 1 if the launches ran as a graph replay          */
+} hr_batch_report;
+
+typedef struct hr_batch hr_batch;
+void hr_batch_opts_default(hr_batch_opts* o);
+/* A batch executor of the context (own stream, table, workspace and graph). */
+hr_status hr_batch_create(hr_ctx* ctx, const hr_batch_opts* opts, hr_batch** out);
+void hr_batch_destroy(hr_batch* b);
+/* Runs `count` queries and returns when every out buffer is written.
+ * Errors: any query's validation error (HR_EINVAL / HR_EUNSUPPORTED, message
+ * names the query), HR_ENOMEM when the summed workspace exceeds the context's
+ * memory budget; no query is run then. */
+hr_status hr_batch_run(hr_batch* b, const hr_query* queries, int count);
+hr_status hr_batch_report_get(const hr_batch* b, hr_batch_report* out);
+/* The autotuner's choice for the scene's class (0, 0 if not tuned yet). */
+hr_status hr_batch_tuned(hr_ctx* ctx, const hr_scene* sc, int* samples_per_block,
+                         int* raster_tile);
+
+/* ---- serving: continuous batching ------------------------------------------
+ * A server owns a worker thread and `slots` batch executors, each with its own
+ * stream.  Queries are submitted asynchronously; whenever a slot is free the
+ * worker forms a batch from the waiting queries in arrival order, admitting a
+ * query only while the batch's workspace fits the slot's share of
+ * memory_bytes, and launches it at once -- so queries arriving while others
+ * are on the GPU start in the next free slot and their work overlaps with the
+ * batches in flight.  Results are the same bits as the single-query entry
+ * points give.  Scenes must outlive the queries submitted on them. */
+typedef struct {
+  int slots;                /* batches in flight (default 2)                    */
+  int max_batch;            /* queries per batch (default 64)                   */
+  uint64_t memory_bytes;    /* device workspace across all slots
+                               (default: the context's memory budget)           */
+  int use_graph;            /* as in hr_batch_opts (default 1)                  */
+  int autotune;             /* as in hr_batch_opts (default 0)                  */
+} hr_server_opts;
+
+typedef struct {
+  double submit_ms;         /* times since the server started                   */
+  double start_ms;          /* its batch was launched                           */
+  double end_ms;            /* its batch's results were on the host             */
+  int batch_size;           /* queries in its batch                             */
+  hr_status status;         /* HR_OK, or the error that failed its batch        */
+} hr_query_stats;
+
+typedef struct {
+  uint64_t submitted, completed, batches;
+  double mean_batch;        /* queries per batch                                */
+  double busy_ms;           /* wall time with at least one batch in flight      */
+} hr_server_stats;
+
+typedef struct hr_server hr_server;
+void hr_server_opts_default(hr_server_opts* o);
+hr_status hr_server_create(hr_ctx* ctx, const hr_server_opts* opts, hr_server** out);
+/* Waits for every submitted query, then stops the worker. */
+void hr_server_destroy(hr_server* s);
+/* Validates and enqueues a query; theta and v are copied, q->out is ignored
+ * (the result is returned by hr_wait).  Errors: validation errors as in
+ * hr_batch_run; HR_ENOMEM if the query alone exceeds a slot's workspace. */
+hr_status hr_submit(hr_server* s, const hr_query* q, uint64_t* ticket);
+/* Blocks until the query is done, copies its result to `out` (sized as in
+ * hr_query_kind) and its timings to `stats` (either may be NULL), and retires
+ * the ticket.  Returns the query's status; HR_EINVAL for unknown tickets. */
+hr_status hr_wait(hr_server* s, uint64_t ticket, double* out, hr_query_stats* stats);
+/* Waits up to timeout_ms (< 0: no limit) for any completed, not yet retired
+ * query and returns its ticket; HR_EBUSY if none completed in time. */
+hr_status hr_wait_any(hr_server* s, double timeout_ms, uint64_t* ticket);
+hr_status hr_server_stats_get(hr_server* s, hr_server_stats* out);
 
 #ifdef __cplusplus
 }

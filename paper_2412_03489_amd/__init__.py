@@ -19,7 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhrest.so")
 
 AIS, IS, GAUSS, FR22 = 0, 1, 2, 3
-STATUS = {0: "HR_OK", -1: "HR_EINVAL", -2: "HR_ENOMEM", -3: "HR_EDEVICE", -4: "HR_EUNSUPPORTED"}
+STATUS = {0: "HR_OK", -1: "HR_EINVAL", -2: "HR_ENOMEM", -3: "HR_EDEVICE", -4: "HR_EUNSUPPORTED",
+          -5: "HR_EBUSY"}
+KIND = {"grad": 0, "hess": 1, "hvp": 2, "hvp_limit": 3, "loss": 4}
 
 EXPORTED = (
     "hr_opts_default", "hr_ncg_opts_default", "hr_ctx_create", "hr_ctx_destroy",
@@ -31,6 +33,10 @@ EXPORTED = (
     "hr_newton_cg_step", "hr_newton_cg_step_dev", "hr_dev_alloc", "hr_dev_free", "hr_memcpy",
     "hr_est_grad_greybox", "hr_est_hessian_greybox", "hr_est_hvp_greybox",
     "hr_est_loss", "hr_optim_opts_default", "hr_optimize",
+    "hr_batch_opts_default", "hr_batch_create", "hr_batch_destroy", "hr_batch_run",
+    "hr_batch_report_get", "hr_batch_tuned",
+    "hr_server_opts_default", "hr_server_create", "hr_server_destroy", "hr_submit", "hr_wait",
+    "hr_wait_any", "hr_server_stats_get",
 )
 
 
@@ -43,7 +49,7 @@ class HrError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("sampler", C.c_int), ("antithetic", C.c_int), ("hvp_rel_step", C.c_double),
                 ("accum_fp64", C.c_int), ("samples_per_block", C.c_int),
-                ("dbg_loss", C.POINTER(C.c_double)), ("dbg_tau", C.POINTER(C.c_double))]
+                ("raster_tile", C.c_int), ("dbg_loss", C.POINTER(C.c_double)), ("dbg_tau", C.POINTER(C.c_double))]
 
 
 class NcgOpts(C.Structure):
@@ -57,6 +63,37 @@ class OptimOpts(C.Structure):
                 ("method", C.c_int), ("lr", C.c_double), ("ls_iters", C.c_int),
                 ("ls_tol", C.c_double), ("recompute", C.c_int), ("N_loss", C.c_uint64),
                 ("ncg", NcgOpts)]
+
+
+class Query(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("kind", C.c_int), ("sigma", C.c_double),
+                ("N", C.c_uint64), ("seed", C.c_uint64), ("theta", C.c_void_p),
+                ("v", C.c_void_p), ("opts", C.POINTER(Opts)), ("out", C.c_void_p)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("use_graph", C.c_int), ("autotune", C.c_int)]
+
+
+class BatchReport(C.Structure):
+    _fields_ = [("queries", C.c_uint64), ("raster_items", C.c_uint64), ("pt_items", C.c_uint64),
+                ("raster_blocks", C.c_int), ("pt_blocks", C.c_int),
+                ("workspace_bytes", C.c_uint64), ("lds_bytes", C.c_uint64), ("graph", C.c_int)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("slots", C.c_int), ("max_batch", C.c_int), ("memory_bytes", C.c_uint64),
+                ("use_graph", C.c_int), ("autotune", C.c_int)]
+
+
+class QueryStats(C.Structure):
+    _fields_ = [("submit_ms", C.c_double), ("start_ms", C.c_double), ("end_ms", C.c_double),
+                ("batch_size", C.c_int), ("status", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("batches", C.c_uint64),
+                ("mean_batch", C.c_double), ("busy_ms", C.c_double)]
 
 
 class NcgReport(C.Structure):
@@ -111,6 +148,19 @@ def lib():
     L.hr_est_loss.argtypes = [vp, vp, d, u64, u64, C.POINTER(Opts), vp]
     L.hr_optim_opts_default.argtypes = [C.POINTER(OptimOpts)]
     L.hr_optimize.argtypes = [vp, vp, u64, u64, C.POINTER(OptimOpts), C.POINTER(Opts), vp]
+    L.hr_batch_opts_default.argtypes = [C.POINTER(BatchOpts)]
+    L.hr_batch_create.argtypes = [vp, C.POINTER(BatchOpts), pv]
+    L.hr_batch_destroy.argtypes = [vp]
+    L.hr_batch_run.argtypes = [vp, C.POINTER(Query), i]
+    L.hr_batch_report_get.argtypes = [vp, C.POINTER(BatchReport)]
+    L.hr_batch_tuned.argtypes = [vp, vp, C.POINTER(i), C.POINTER(i)]
+    L.hr_server_opts_default.argtypes = [C.POINTER(ServerOpts)]
+    L.hr_server_create.argtypes = [vp, C.POINTER(ServerOpts), pv]
+    L.hr_server_destroy.argtypes = [vp]
+    L.hr_submit.argtypes = [vp, C.POINTER(Query), C.POINTER(u64)]
+    L.hr_wait.argtypes = [vp, u64, vp, C.POINTER(QueryStats)]
+    L.hr_wait_any.argtypes = [vp, d, C.POINTER(u64)]
+    L.hr_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
     _lib = L
     return L
 
@@ -125,7 +175,7 @@ def _p(a):
 
 
 def make_opts(sampler=AIS, antithetic=True, hvp_rel_step=0.1, accum_fp64=False,
-              samples_per_block=0, dbg=None, dbg_tau=None):
+              samples_per_block=0, dbg=None, dbg_tau=None, raster_tile=0):
     o = Opts()
     lib().hr_opts_default(C.byref(o))
     o.sampler = sampler
@@ -133,6 +183,7 @@ def make_opts(sampler=AIS, antithetic=True, hvp_rel_step=0.1, accum_fp64=False,
     o.hvp_rel_step = hvp_rel_step
     o.accum_fp64 = 1 if accum_fp64 else 0
     o.samples_per_block = samples_per_block
+    o.raster_tile = raster_tile
     o.dbg_loss = dbg.ctypes.data_as(C.POINTER(C.c_double)) if dbg is not None else None
     o.dbg_tau = dbg_tau.ctypes.data_as(C.POINTER(C.c_double)) if dbg_tau is not None else None
     return o
@@ -289,7 +340,7 @@ def n_streams(kind, n, sampler=AIS):
 
 def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic=True,
              hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0, return_losses=False,
-             return_draws=False):
+             return_draws=False, raster_tile=0):
     """kind in {'grad', 'hess', 'hvp', 'hvp_limit'} (host-pointer entry points).
     With return_losses / return_draws the per-render losses and the draws are
     returned as well (in that order)."""
@@ -297,7 +348,8 @@ def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic
     th = np.ascontiguousarray(theta, dtype=np.float64)
     dbg = np.zeros(n_renders(kind, n, N, sampler, antithetic)) if return_losses else None
     taus = np.zeros(n_streams(kind, n, sampler) * N * n) if return_draws else None
-    o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block, dbg, taus)
+    o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block, dbg, taus,
+                  raster_tile)
     L = lib()
     if kind == "grad":
         out = np.zeros(n)
@@ -418,3 +470,127 @@ def optimize(scene, theta, N, seed, iters, sigma_start, sigma_end, method="newto
     _check(lib().hr_optimize(scene.h, _p(th), int(N), int(seed), C.byref(oo), C.byref(o),
                              _p(trace)))
     return th, trace
+
+
+# ------------------------------------------------------------ batches, serving
+def out_shape(kind, n):
+    return (n, n) if kind == "hess" else ((1,) if kind == "loss" else (n,))
+
+
+_OPT_KEYS = ("sampler", "antithetic", "hvp_rel_step", "accum_fp64", "samples_per_block",
+             "raster_tile")
+
+
+def _query(scene, kind, theta, sigma, N, seed, v=None, out=None, **opt):
+    """Builds an hr_query; returns it with the arrays it points at (kept alive)."""
+    bad = set(opt) - set(_OPT_KEYS)
+    if bad:
+        raise TypeError(f"unknown query options {sorted(bad)}")
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
+    o = make_opts(opt.get("sampler", AIS), opt.get("antithetic", True),
+                  opt.get("hvp_rel_step", 0.1), opt.get("accum_fp64", False),
+                  opt.get("samples_per_block", 0), raster_tile=opt.get("raster_tile", 0))
+    q = Query(scene.h, KIND[kind], float(sigma), int(N), int(seed), _p(th),
+              None if vv is None else _p(vv), C.pointer(o), None if out is None else _p(out))
+    return q, (th, vv, o, out)
+
+
+class Batch:
+    """Batched executor (hr_batch): many uneven queries per launch sequence."""
+
+    def __init__(self, ctx, use_graph=True, autotune=False):
+        o = BatchOpts(1 if use_graph else 0, 1 if autotune else 0)
+        h = C.c_void_p()
+        _check(lib().hr_batch_create(ctx.h, C.byref(o), C.byref(h)))
+        self.ctx, self.h = ctx, h
+
+    def run(self, queries):
+        """queries: dicts with scene, kind, theta, sigma, N, seed[, v] and
+        optional estimator options; returns the results in order."""
+        outs, keep = [], []
+        arr = (Query * max(1, len(queries)))()
+        for k, q in enumerate(queries):
+            q = dict(q)
+            out = np.zeros(out_shape(q["kind"], q["scene"].n))
+            qq, alive = _query(out=out, **q)
+            arr[k] = qq
+            outs.append(out)
+            keep.append(alive)
+        _check(lib().hr_batch_run(self.h, arr, len(queries)))
+        return outs
+
+    def report(self):
+        r = BatchReport()
+        _check(lib().hr_batch_report_get(self.h, C.byref(r)))
+        return {f: getattr(r, f) for f, _ in BatchReport._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tuned(ctx, scene):
+    """The autotuner's (samples_per_block, raster_tile) for the scene's class."""
+    s, t = C.c_int(), C.c_int()
+    _check(lib().hr_batch_tuned(ctx.h, scene.h, C.byref(s), C.byref(t)))
+    return s.value, t.value
+
+
+class Server:
+    """Continuous-batching server (hr_server)."""
+
+    def __init__(self, ctx, slots=2, max_batch=64, memory_bytes=0, use_graph=True,
+                 autotune=False):
+        o = ServerOpts(int(slots), int(max_batch), int(memory_bytes), 1 if use_graph else 0,
+                       1 if autotune else 0)
+        h = C.c_void_p()
+        _check(lib().hr_server_create(ctx.h, C.byref(o), C.byref(h)))
+        self.ctx, self.h = ctx, h
+        self._kind = {}
+
+    def submit(self, scene, kind, theta, sigma, N, seed, v=None, **opt):
+        q, alive = _query(scene, kind, theta, sigma, N, seed, v, **opt)
+        t = C.c_uint64()
+        _check(lib().hr_submit(self.h, C.byref(q), C.byref(t)))
+        self._kind[t.value] = out_shape(kind, scene.n)
+        return t.value
+
+    def wait(self, ticket):
+        """(result, stats) of a ticket; retires it."""
+        out = np.zeros(self._kind.pop(ticket))
+        st = QueryStats()
+        _check(lib().hr_wait(self.h, int(ticket), _p(out), C.byref(st)))
+        return out, {f: getattr(st, f) for f, _ in QueryStats._fields_}
+
+    def wait_any(self, timeout_ms=-1.0):
+        """A completed ticket, or None on time-out."""
+        t = C.c_uint64()
+        st = lib().hr_wait_any(self.h, float(timeout_ms), C.byref(t))
+        if st == -5:
+            return None
+        _check(st)
+        return t.value
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().hr_server_stats_get(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hr_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,83 +8,27 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <map>
-#include <set>
 #include <string>
 #include <vector>
 
-#include "hrest.h"
-#include "hr_kernels.h"
+#include "hr_runtime.h"
 
 using namespace hr;
+using namespace hr::rt;
 
-namespace {
+namespace hr {
+namespace rt {
 
-thread_local std::string g_err;
-
-hr_status fail(hr_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
+std::string& error_slot() {
+  thread_local std::string err;
+  return err;
 }
 
-#define HR_HIP(call)                                                              \
-  do {                                                                            \
-    hipError_t e_ = (call);                                                       \
-    if (e_ != hipSuccess)                                                         \
-      return fail(HR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-}  // namespace
-
-struct hr_ctx {
-  int device = 0;
-  hipStream_t own = nullptr;
-  hipStream_t stream = nullptr;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  void* stage = nullptr;      // host-call staging: theta, v, outputs
-  size_t stage_bytes = 0;
-  void* cg = nullptr;         // Newton-CG vectors and state
-  size_t cg_bytes = 0;
-  uint64_t budget = 64ull << 30;
-  bool timing = false;
-  struct Pending { std::string name; hipEvent_t a, b; };
-  std::vector<Pending> pending;
-  std::map<std::string, std::pair<uint64_t, double>> stats;
-  std::set<hr_scene*> scenes;   // released (and orphaned) with the context
-};
-
-enum SceneKind { kDisks = 0, kPT = 1, kQuad = 2, kNegGauss = 3 };
-
-struct hr_scene {
-  hr_ctx* ctx = nullptr;
-  int kind = kDisks;
-  int n = 0;
-  int W = 0, H = 0, C = 0;
-  float* target = nullptr;
-  int D = 0, ppd = 0;
-  float* colors = nullptr;
-  float* radius = nullptr;
-  std::vector<float> hradius;
-  int spp = 0, nspheres = 0;
-  std::vector<float> pt_desc;   // FP32 description + derived camera basis
-  double* A = nullptr;
-  double* b = nullptr;
-  double c = 0.0, s1 = 1.0;
-};
-
-namespace {
-
-void release_scene_memory(hr_scene* sc) {
-  if (sc->target) (void)hipFree(sc->target);
-  if (sc->colors) (void)hipFree(sc->colors);
-  if (sc->radius) (void)hipFree(sc->radius);
-  if (sc->A) (void)hipFree(sc->A);
-  if (sc->b) (void)hipFree(sc->b);
-  sc->target = sc->colors = sc->radius = nullptr;
-  sc->A = sc->b = nullptr;
+hr_opts resolve(const hr_opts* o) {
+  hr_opts r;
+  hr_opts_default(&r);
+  if (o) r = *o;
+  return r;
 }
 
 hr_status ensure(hr_ctx* ctx, void** buf, size_t* have, size_t need) {
@@ -106,21 +50,6 @@ hr_status ensure(hr_ctx* ctx, void** buf, size_t* have, size_t need) {
   return HR_OK;
 }
 
-template <class F>
-void timed(hr_ctx* ctx, const char* name, F&& fn) {
-  if (!ctx->timing) {
-    fn();
-    return;
-  }
-  hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess) { fn(); return; }
-  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); fn(); return; }
-  (void)hipEventRecord(a, ctx->stream);
-  fn();
-  (void)hipEventRecord(b, ctx->stream);
-  ctx->pending.push_back({name, a, b});
-}
-
 hr_status drain_timers(hr_ctx* ctx) {
   for (auto& p : ctx->pending) {
     HR_HIP(hipEventSynchronize(p.b));
@@ -136,25 +65,11 @@ hr_status drain_timers(hr_ctx* ctx) {
   return HR_OK;
 }
 
-bool finite_all(const double* x, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(x[i])) return false;
-  return true;
-}
-
-hr_opts resolve(const hr_opts* o) {
-  hr_opts r;
-  hr_opts_default(&r);
-  if (o) r = *o;
-  return r;
-}
-
-// the estimator pipeline on device pointers
-hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, uint64_t N,
-                  uint64_t seed, const double* d_v, const hr_opts& o_in, double* d_out,
-                  double* h_dbg, double* h_tau) {
-  hr_ctx* ctx = sc->ctx;
-  if (!ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
+hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t seed, bool has_v,
+                     const hr_opts& o_in, QueryPlan* p) {
+  if (!sc) return fail(HR_EINVAL, "scene is NULL");
+  if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
+  if (what < kGrad || what > kLoss) return fail(HR_EINVAL, "unknown query kind");
   hr_opts o = o_in;
   if (what == kLoss) {
     // the smoothed loss uses the plain Gaussian draws; sigma = 0: one render at theta
@@ -168,17 +83,17 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
     return fail(HR_EINVAL, "sigma must be positive and finite");
   if (N == 0 || N >= 0xFFFFFFFFull) return fail(HR_EINVAL, "N must be in [1, 2^32 - 1)");
   if (o.sampler < 0 || o.sampler > 3) return fail(HR_EINVAL, "unknown sampler");
-  if ((what == kHvp || what == kHvpLimit) && !d_v) return fail(HR_EINVAL, "v is NULL");
+  if (o.raster_tile < 0 || o.raster_tile > 3) return fail(HR_EINVAL, "raster_tile must be in [0, 3]");
+  if ((what == kHvp || what == kHvpLimit) && !has_v) return fail(HR_EINVAL, "v is NULL");
   if (what == kHvpLimit && per_element(o.sampler))
     return fail(HR_EUNSUPPORTED, "the limit-kernel HVP supports the aggregate and Gaussian samplers");
   if (what == kHess && o.sampler == kFR22)
     return fail(HR_EUNSUPPORTED, "the FR22 comparator estimates gradients and HVPs only");
-  if (what == kHvp && !(o.hvp_rel_step > 0.0) ) return fail(HR_EINVAL, "hvp_rel_step must be positive");
+  if (what == kHvp && !(o.hvp_rel_step > 0.0)) return fail(HR_EINVAL, "hvp_rel_step must be positive");
   if (sc->n < 1 || sc->n > 6144) return fail(HR_EINVAL, "parameter count out of range");
-  HR_HIP(hipSetDevice(ctx->device));
-  (void)hipGetLastError();   // launch checks below report this call's errors only
 
-  EstShape e{};
+  EstShape& e = p->e;
+  e = EstShape{};
   e.what = what;
   e.sampler = o.sampler;
   e.n = sc->n;
@@ -194,36 +109,89 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
   e.h = what == kHvp ? o.hvp_rel_step * sigma : 0.0;
   e.seed = seed;
 
-  const int chunk = accum_chunk(e);
-  const uint64_t nchunks = (N + chunk - 1) / chunk;
-  const int tiles = sc->kind == kDisks ? raster_tiles(sc->W, sc->H)
-                    : sc->kind == kPT  ? pt_tiles(sc->W, sc->H)
-                                       : 0;
-  const size_t b_tau = align256(e.streams * N * (uint64_t)e.n * 8);
-  const size_t b_u = align256((size_t)e.n * 8 + 8);
-  const size_t b_rec = sc->kind == kDisks ? align256(e.R * (uint64_t)sc->D * 16) : 0;
-  const size_t b_part = tiles ? align256(e.R * (uint64_t)tiles * 4) : 0;
-  const size_t b_f = align256(e.R * 8);
-  const size_t b_Fq = align256(e.streams * N * 8);
-  const size_t b_vt = align256(N * 8);
-  const size_t b_acc = align256(nchunks * (uint64_t)e.nout * 16);
-  const size_t total = b_tau + b_u + b_rec + b_part + b_f + b_Fq + b_vt + b_acc;
-  if (total > ctx->budget)
-    return fail(HR_ENOMEM, "request needs " + std::to_string(total) + " bytes of workspace, budget is " +
-                               std::to_string(ctx->budget));
-  hr_status st = ensure(ctx, &ctx->ws, &ctx->ws_bytes, total);
+  p->sc = sc;
+  p->o = o;
+  p->chunk = accum_chunk(e);
+  p->nchunks = (N + p->chunk - 1) / p->chunk;
+  p->stride = sc->kind == kDisks ? raster_subtiles(sc->W, sc->H)
+              : sc->kind == kPT  ? pt_tiles(sc->W, sc->H)
+                                 : 0;
+  p->b_tau = align256(e.streams * N * (uint64_t)e.n * 8);
+  p->b_u = align256((size_t)e.n * 8 + 8);
+  p->b_rec = sc->kind == kDisks ? align256(e.R * (uint64_t)sc->D * 16) : 0;
+  p->b_part = p->stride ? align256(e.R * (uint64_t)p->stride * 4) : 0;
+  p->b_f = align256(e.R * 8);
+  p->b_Fq = align256(e.streams * N * 8);
+  p->b_vt = align256(N * 8);
+  p->b_acc = align256(p->nchunks * (uint64_t)e.nout * 16);
+  p->total = p->b_tau + p->b_u + p->b_rec + p->b_part + p->b_f + p->b_Fq + p->b_vt + p->b_acc;
+  p->nout = what == kHess ? (size_t)e.n * e.n : (what == kLoss ? 1 : (size_t)e.n);
+  return HR_OK;
+}
+
+QueryBufs carve(const QueryPlan& p, void* base) {
+  QueryBufs b;
+  char* c = (char*)base;
+  b.tau = (double*)c; c += p.b_tau;
+  b.u = (double*)c;
+  b.vnorm = b.u + p.e.n;
+  c += p.b_u;
+  b.rec = (float4*)c; c += p.b_rec;
+  b.partial = (float*)c; c += p.b_part;
+  b.f = (double*)c; c += p.b_f;
+  b.Fq = (double*)c; c += p.b_Fq;
+  b.vt = (double*)c; c += p.b_vt;
+  b.acc = (void*)c;
+  return b;
+}
+
+}  // namespace rt
+}  // namespace hr
+
+namespace {
+
+void release_scene_memory(hr_scene* sc) {
+  if (sc->target) (void)hipFree(sc->target);
+  if (sc->colors) (void)hipFree(sc->colors);
+  if (sc->radius) (void)hipFree(sc->radius);
+  if (sc->A) (void)hipFree(sc->A);
+  if (sc->b) (void)hipFree(sc->b);
+  if (sc->ptc) (void)hipFree(sc->ptc);
+  sc->target = sc->colors = sc->radius = nullptr;
+  sc->A = sc->b = nullptr;
+  sc->ptc = nullptr;
+}
+
+// the estimator pipeline on device pointers
+hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, uint64_t N,
+                  uint64_t seed, const double* d_v, const hr_opts& o_in, double* d_out,
+                  double* h_dbg, double* h_tau) {
+  QueryPlan pl;
+  hr_status st = plan_query(sc, what, sigma, N, seed, d_v != nullptr, o_in, &pl);
   if (st) return st;
-  char* p = (char*)ctx->ws;
-  double* tau = (double*)p; p += b_tau;
-  double* u = (double*)p;
-  double* vnorm = u + e.n;
-  p += b_u;
-  float4* rec = (float4*)p; p += b_rec;
-  float* partial = (float*)p; p += b_part;
-  double* f = (double*)p; p += b_f;
-  double* Fq = (double*)p; p += b_Fq;
-  double* vt = (double*)p; p += b_vt;
-  void* acc = (void*)p;
+  hr_ctx* ctx = sc->ctx;
+  const hr_opts& o = pl.o;
+  const EstShape& e = pl.e;
+  N = e.N;
+  const int chunk = pl.chunk;
+  const int tiles = pl.stride;
+  HR_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below report this call's errors only
+  if (pl.total > ctx->budget)
+    return fail(HR_ENOMEM, "request needs " + std::to_string(pl.total) +
+                               " bytes of workspace, budget is " + std::to_string(ctx->budget));
+  st = ensure(ctx, &ctx->ws, &ctx->ws_bytes, pl.total);
+  if (st) return st;
+  const QueryBufs qb = carve(pl, ctx->ws);
+  double* tau = qb.tau;
+  double* u = qb.u;
+  double* vnorm = qb.vnorm;
+  float4* rec = qb.rec;
+  float* partial = qb.partial;
+  double* f = qb.f;
+  double* Fq = qb.Fq;
+  double* vt = qb.vt;
+  void* acc = qb.acc;
 
   hipStream_t s = ctx->stream;
   if (what == kHvp || what == kHvpLimit) launch_vnorm(s, e.n, d_v, u, vnorm);
@@ -233,7 +201,7 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
     DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};
     timed(ctx, "records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
     RasterExact ex{d_theta, tau, u, sc->radius, e.n, sc->ppd, e.A, e.NH, e.h};
-    timed(ctx, "raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, ex, partial); });
+    timed(ctx, "raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, o.raster_tile, ex, partial); });
     launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
   } else if (sc->kind == kPT) {
     PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data()};
@@ -301,6 +269,7 @@ void hr_opts_default(hr_opts* o) {
   o->hvp_rel_step = 0.1;
   o->accum_fp64 = 0;
   o->samples_per_block = 0;
+  o->raster_tile = 0;
   o->dbg_loss = nullptr;
   o->dbg_tau = nullptr;
 }
@@ -315,7 +284,7 @@ void hr_ncg_opts_default(hr_ncg_opts* o) {
   o->modified = 0;
 }
 
-const char* hr_last_error(void) { return g_err.c_str(); }
+const char* hr_last_error(void) { return error_slot().c_str(); }
 
 hr_status hr_ctx_create(int device, hr_ctx** out) {
   if (!out) return fail(HR_EINVAL, "out is NULL");
@@ -496,6 +465,13 @@ hr_status hr_scene_pt(hr_ctx* ctx, int W, int H, int spp, int nspheres, const do
   d[22] = (float)th;
   for (int i = 0; i < 7 * nspheres; ++i) d[23 + i] = (float)desc[12 + i];
   hr_status st = upload(target, (size_t)W * H * 3 * 4, (void**)&sc->target);
+  if (!st) {
+    // the path tracer's constants, resident for the batch kernels
+    const PTScene ps{W, H, spp, nspheres, sc->target, d.data()};
+    std::vector<char> pc(pt_const_bytes());
+    pt_fill_const(ps, pc.data());
+    st = upload(pc.data(), pc.size(), &sc->ptc);
+  }
   if (st) { hr_scene_destroy(sc); return st; }
   ctx->scenes.insert(sc);
   *out = sc;

@@ -25,46 +25,53 @@ inline unsigned grid_for(uint64_t total, int block) {
   return (unsigned)(g > 65536u * 16u ? 65536u * 16u : (g == 0 ? 1 : g));
 }
 
+// draw component gid = (stream * N + s) * n + j
+__device__ __forceinline__ void sample_one(int n, int K, int hessk, int sampler, uint64_t N,
+                                           uint64_t seed, double sg, uint64_t gid,
+                                           double* __restrict__ tau) {
+  const int j = (int)(gid % (uint64_t)n);
+  const uint64_t sidx = gid / (uint64_t)n;
+  const uint32_t stream = (uint32_t)(sidx / N);
+  const uint32_t s = (uint32_t)(sidx % N);
+  const uint32_t tag = per_element(sampler) ? stream : (sampler == kAIS ? kTagAIS : kTagGauss);
+  const u32x4 w = philox_seeded(seed, s, (uint32_t)j, 0u, tag);
+  int m = -1;
+  if (per_element(sampler)) m = (int)stream;
+  if (sampler == kAIS) {
+    const u32x4 ws = philox_seeded(seed, s, kDimSelect, 0u, tag);
+    m = (int)(((uint64_t)ws.x * (uint64_t)K) >> 32);
+  }
+  bool lg = false, ld = false;
+  if (m >= 0) {
+    if (!hessk) {
+      lg = (j == m);
+    } else {
+      int i, jj;
+      tri_ij(n, m, i, jj);
+      if (i == jj) ld = (j == i);
+      else lg = (j == i || j == jj);
+    }
+  }
+  double t;
+  if (ld) t = hdiag_lobe(w.z, sg);
+  else if (lg) t = grad_lobe(w.z, sg);
+  else if (sampler == kFR22) t = 0.0;   // only the differentiated dimension is blurred
+  else t = sg * sqrt(-2.0 * log(u01_d(w.x))) * cos(2.0 * kPi * u01_d(w.y));
+  tau[gid] = t;
+}
+
 // one thread per (stream, draw, dimension)
 __global__ void k_sample(int n, int K, int hessk, int sampler, uint64_t N, uint64_t seed,
                          double sg, uint64_t total, double* __restrict__ tau) {
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
-       gid += (uint64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(gid % (uint64_t)n);
-    const uint64_t sidx = gid / (uint64_t)n;
-    const uint32_t stream = (uint32_t)(sidx / N);
-    const uint32_t s = (uint32_t)(sidx % N);
-    const uint32_t tag = per_element(sampler) ? stream : (sampler == kAIS ? kTagAIS : kTagGauss);
-    const u32x4 w = philox_seeded(seed, s, (uint32_t)j, 0u, tag);
-    int m = -1;
-    if (per_element(sampler)) m = (int)stream;
-    if (sampler == kAIS) {
-      const u32x4 ws = philox_seeded(seed, s, kDimSelect, 0u, tag);
-      m = (int)(((uint64_t)ws.x * (uint64_t)K) >> 32);
-    }
-    bool lg = false, ld = false;
-    if (m >= 0) {
-      if (!hessk) {
-        lg = (j == m);
-      } else {
-        int i, jj;
-        tri_ij(n, m, i, jj);
-        if (i == jj) ld = (j == i);
-        else lg = (j == i || j == jj);
-      }
-    }
-    double t;
-    if (ld) t = hdiag_lobe(w.z, sg);
-    else if (lg) t = grad_lobe(w.z, sg);
-    else if (sampler == kFR22) t = 0.0;   // only the differentiated dimension is blurred
-    else t = sg * sqrt(-2.0 * log(u01_d(w.x))) * cos(2.0 * kPi * u01_d(w.y));
-    tau[gid] = t;
-  }
+       gid += (uint64_t)gridDim.x * blockDim.x)
+    sample_one(n, K, hessk, sampler, N, seed, sg, gid, tau);
 }
 
-__global__ void k_vnorm(int n, const double* __restrict__ v, double* __restrict__ u,
-                        double* __restrict__ vnorm) {
-  __shared__ double s_acc[256];
+__device__ __forceinline__ void vnorm_block(int n, const double* __restrict__ v,
+                                            double* __restrict__ u, double* __restrict__ vnorm,
+                                            double* s_acc) {
+  __syncthreads();
   double acc = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) acc += v[j] * v[j];
   s_acc[threadIdx.x] = acc;
@@ -78,44 +85,58 @@ __global__ void k_vnorm(int n, const double* __restrict__ v, double* __restrict_
   if (threadIdx.x == 0) *vnorm = nv;
 }
 
-// analytic scenes: one thread per render, FP64
+__global__ __launch_bounds__(256) void k_vnorm(int n, const double* __restrict__ v,
+                                               double* __restrict__ u, double* __restrict__ vnorm) {
+  __shared__ double s_acc[256];
+  vnorm_block(n, v, u, vnorm, s_acc);
+}
+
+// analytic scenes: render r in FP64
+__device__ __forceinline__ void analytic_one(int kind, int n, const double* __restrict__ A,
+                                             const double* __restrict__ b, double c, double s1,
+                                             const double* __restrict__ theta,
+                                             const double* __restrict__ tau,
+                                             const double* __restrict__ u, int Aa, int NH,
+                                             double h, uint64_t r, double* __restrict__ f) {
+  const int sh = (int)(r % (uint64_t)NH);
+  const uint64_t rem = r / (uint64_t)NH;
+  const int ai = (int)(rem % (uint64_t)Aa);
+  const uint64_t sidx = rem / (uint64_t)Aa;
+  const double* t = tau + sidx * (uint64_t)n;
+  const double a = ai == 0 ? 1.0 : -1.0;
+  const double shift = sh == 0 ? h : -h;
+  auto P = [&](int j) {
+    double base = theta[j];
+    if (NH == 2) base = base + shift * u[j];
+    return base - a * t[j];
+  };
+  double val;
+  if (kind == 0) {
+    val = c;
+    for (int i = 0; i < n; ++i) {
+      const double pi = P(i);
+      val += b[i] * pi;
+      for (int j = 0; j < n; ++j) val += 0.5 * pi * A[i * n + j] * P(j);
+    }
+  } else {
+    double r2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double pi = P(i);
+      r2 += pi * pi;
+    }
+    val = -pow(2.0 * kPi * s1 * s1, -0.5 * n) * exp(-r2 / (2.0 * s1 * s1));
+  }
+  f[r] = val;
+}
+
 __global__ void k_analytic(int kind, int n, const double* __restrict__ A,
                            const double* __restrict__ b, double c, double s1,
                            const double* __restrict__ theta, const double* __restrict__ tau,
                            const double* __restrict__ u, int Aa, int NH, double h, uint64_t R,
                            double* __restrict__ f) {
   for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < R;
-       r += (uint64_t)gridDim.x * blockDim.x) {
-    const int sh = (int)(r % (uint64_t)NH);
-    const uint64_t rem = r / (uint64_t)NH;
-    const int ai = (int)(rem % (uint64_t)Aa);
-    const uint64_t sidx = rem / (uint64_t)Aa;
-    const double* t = tau + sidx * (uint64_t)n;
-    const double a = ai == 0 ? 1.0 : -1.0;
-    const double shift = sh == 0 ? h : -h;
-    auto P = [&](int j) {
-      double base = theta[j];
-      if (NH == 2) base = base + shift * u[j];
-      return base - a * t[j];
-    };
-    double val;
-    if (kind == 0) {
-      val = c;
-      for (int i = 0; i < n; ++i) {
-        const double pi = P(i);
-        val += b[i] * pi;
-        for (int j = 0; j < n; ++j) val += 0.5 * pi * A[i * n + j] * P(j);
-      }
-    } else {
-      double r2 = 0.0;
-      for (int i = 0; i < n; ++i) {
-        const double pi = P(i);
-        r2 += pi * pi;
-      }
-      val = -pow(2.0 * kPi * s1 * s1, -0.5 * n) * exp(-r2 / (2.0 * s1 * s1));
-    }
-    f[r] = val;
-  }
+       r += (uint64_t)gridDim.x * blockDim.x)
+    analytic_one(kind, n, A, b, c, s1, theta, tau, u, Aa, NH, h, r, f);
 }
 
 __device__ __forceinline__ double z_grad(double sg) { return sqrt(2.0 / kPi) / sg; }
@@ -125,12 +146,12 @@ __device__ __forceinline__ double z_diag(double sg) {
 
 // per draw: F_s (antithetic pair collapsed, HVP difference quotient applied),
 // divided by the aggregate mixture q(tau_s); v^T tau_s for the limit HVP
-__global__ void k_prep(EstShape e, const double* __restrict__ f, const double* __restrict__ tau,
-                       const double* __restrict__ vnorm, const double* __restrict__ v,
-                       double* __restrict__ Fq, double* __restrict__ vt) {
-  const uint64_t total = e.streams * e.N;
-  for (uint64_t sidx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; sidx < total;
-       sidx += (uint64_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void prep_one(const EstShape& e, const double* __restrict__ f,
+                                         const double* __restrict__ tau,
+                                         const double* __restrict__ vnorm,
+                                         const double* __restrict__ v, uint64_t sidx,
+                                         double* __restrict__ Fq, double* __restrict__ vt) {
+  {
     const uint64_t r0 = sidx * (uint64_t)(e.A * e.NH);
     double F0, F1 = 0.0;
     if (e.what == kHvp) {
@@ -174,6 +195,15 @@ __global__ void k_prep(EstShape e, const double* __restrict__ f, const double* _
   }
 }
 
+__global__ void k_prep(EstShape e, const double* __restrict__ f, const double* __restrict__ tau,
+                       const double* __restrict__ vnorm, const double* __restrict__ v,
+                       double* __restrict__ Fq, double* __restrict__ vt) {
+  const uint64_t total = e.streams * e.N;
+  for (uint64_t sidx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; sidx < total;
+       sidx += (uint64_t)gridDim.x * blockDim.x)
+    prep_one(e, f, tau, vnorm, v, sidx, Fq, vt);
+}
+
 // kernel factor d_m(tau) (output m; Hessian elements from (i, j))
 __device__ __forceinline__ double kfac(const EstShape& e, int m, int i, int j,
                                        const double* t, double vts, const double* v) {
@@ -190,15 +220,21 @@ struct Lobes32 { fsum2 pos, neg; };
 // aggregate / Gaussian / limit HVP: block = chunk of draws, threads = elements
 constexpr int kLdsDoubles = 6144;   // 48 KiB of draws per chunk
 
-__global__ __launch_bounds__(256) void k_accum(EstShape e, const double* __restrict__ tau,
-                                               const double* __restrict__ Fq,
-                                               const double* __restrict__ vt,
-                                               const double* __restrict__ v, int fp64,
-                                               int chunk, void* __restrict__ part) {
-  __shared__ double s_tau[kLdsDoubles];
-  __shared__ double s_F[256];
-  __shared__ double s_vt[256];
-  const uint64_t c = blockIdx.x;
+struct AccumLds {
+  double tau[kLdsDoubles];
+  double F[256];
+  double vt[256];
+};
+
+__device__ __forceinline__ void accum_block(const EstShape& e, const double* __restrict__ tau,
+                                            const double* __restrict__ Fq,
+                                            const double* __restrict__ vt,
+                                            const double* __restrict__ v, int fp64, int chunk,
+                                            uint64_t c, void* __restrict__ part, AccumLds& L_) {
+  double* s_tau = L_.tau;
+  double* s_F = L_.F;
+  double* s_vt = L_.vt;
+  __syncthreads();   // the previous task's readers of LDS are done
   const uint64_t s0 = c * (uint64_t)chunk;
   const int ns = (int)min((uint64_t)chunk, e.N - s0);
   for (int i = threadIdx.x; i < ns * e.n; i += blockDim.x) s_tau[i] = tau[s0 * e.n + i];
@@ -228,48 +264,62 @@ __global__ __launch_bounds__(256) void k_accum(EstShape e, const double* __restr
   }
 }
 
-// per-element IS: thread per (element, chunk), draws of that element's stream
+__global__ __launch_bounds__(256) void k_accum(EstShape e, const double* __restrict__ tau,
+                                               const double* __restrict__ Fq,
+                                               const double* __restrict__ vt,
+                                               const double* __restrict__ v, int fp64,
+                                               int chunk, void* __restrict__ part) {
+  __shared__ AccumLds lds;
+  accum_block(e, tau, Fq, vt, v, fp64, chunk, blockIdx.x, part, lds);
+}
+
+// per-element IS: (element, chunk) item gid, draws of that element's stream
+__device__ __forceinline__ void accum_is_one(const EstShape& e, const double* __restrict__ tau,
+                                             const double* __restrict__ Fq, int fp64, int chunk,
+                                             uint64_t gid, void* __restrict__ part) {
+  const int m = (int)(gid % (uint64_t)e.nout);
+  const uint64_t c = gid / (uint64_t)e.nout;
+  const uint64_t s0 = c * (uint64_t)chunk;
+  const int ns = (int)min((uint64_t)chunk, e.N - s0);
+  int i = m, j = m;
+  if (e.hessk) tri_ij(e.n, m, i, j);
+  const double zm = !e.hessk ? z_grad(e.sigma) : (i == j ? z_diag(e.sigma) : z_grad(e.sigma) * z_grad(e.sigma));
+  double pos64 = 0.0, neg64 = 0.0;
+  Lobes32 L = {{0.f, 0.f}, {0.f, 0.f}};
+  for (int s = 0; s < ns; ++s) {
+    const uint64_t sidx = (uint64_t)m * e.N + s0 + s;
+    const double* t = tau + sidx * (uint64_t)e.n;
+    const double d = kfac(e, m, i, j, t, 0.0, nullptr);
+    const double w = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) * zm;
+    const double cv = w * Fq[sidx];
+    if (fp64) {
+      if (cv >= 0.0) pos64 += cv; else neg64 -= cv;
+    } else {
+      const float cf = (float)cv;
+      if (cf >= 0.0f) two_sum_add(L.pos, cf); else two_sum_add(L.neg, -cf);
+    }
+  }
+  if (fp64) ((double2*)part)[c * (uint64_t)e.nout + m] = make_double2(pos64, neg64);
+  else ((float4*)part)[c * (uint64_t)e.nout + m] = make_float4(L.pos.hi, L.pos.lo, L.neg.hi, L.neg.lo);
+}
+
 __global__ void k_accum_is(EstShape e, const double* __restrict__ tau,
                            const double* __restrict__ Fq, int fp64, int chunk, uint64_t nchunks,
                            void* __restrict__ part) {
   const uint64_t total = nchunks * (uint64_t)e.nout;
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
-       gid += (uint64_t)gridDim.x * blockDim.x) {
-    const int m = (int)(gid % (uint64_t)e.nout);
-    const uint64_t c = gid / (uint64_t)e.nout;
-    const uint64_t s0 = c * (uint64_t)chunk;
-    const int ns = (int)min((uint64_t)chunk, e.N - s0);
-    int i = m, j = m;
-    if (e.hessk) tri_ij(e.n, m, i, j);
-    const double zm = !e.hessk ? z_grad(e.sigma) : (i == j ? z_diag(e.sigma) : z_grad(e.sigma) * z_grad(e.sigma));
-    double pos64 = 0.0, neg64 = 0.0;
-    Lobes32 L = {{0.f, 0.f}, {0.f, 0.f}};
-    for (int s = 0; s < ns; ++s) {
-      const uint64_t sidx = (uint64_t)m * e.N + s0 + s;
-      const double* t = tau + sidx * (uint64_t)e.n;
-      const double d = kfac(e, m, i, j, t, 0.0, nullptr);
-      const double w = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) * zm;
-      const double cv = w * Fq[sidx];
-      if (fp64) {
-        if (cv >= 0.0) pos64 += cv; else neg64 -= cv;
-      } else {
-        const float cf = (float)cv;
-        if (cf >= 0.0f) two_sum_add(L.pos, cf); else two_sum_add(L.neg, -cf);
-      }
-    }
-    if (fp64) ((double2*)part)[c * (uint64_t)e.nout + m] = make_double2(pos64, neg64);
-    else ((float4*)part)[c * (uint64_t)e.nout + m] = make_float4(L.pos.hi, L.pos.lo, L.neg.hi, L.neg.lo);
-  }
+       gid += (uint64_t)gridDim.x * blockDim.x)
+    accum_is_one(e, tau, Fq, fp64, chunk, gid, part);
 }
 
 // FP64 lobe difference over chunks in fixed order; Hessian mirrored.
 // One block per element: thread t sums chunks t, t + 256, ... and the 256
 // partial sums meet in a fixed pairing tree.
-__global__ __launch_bounds__(256) void k_finalize(EstShape e, const void* __restrict__ part,
-                                                  int fp64, uint64_t nchunks,
-                                                  double* __restrict__ out) {
-  __shared__ double s_pos[256], s_neg[256];
-  const int m = blockIdx.x;
+__device__ __forceinline__ void finalize_block(const EstShape& e, const void* __restrict__ part,
+                                               int fp64, uint64_t nchunks, int m,
+                                               double* __restrict__ out, double* s_pos,
+                                               double* s_neg) {
+  __syncthreads();   // the previous task's readers of LDS are done
   double pos = 0.0, neg = 0.0;
   for (uint64_t c = threadIdx.x; c < nchunks; c += blockDim.x) {
     if (fp64) {
@@ -301,6 +351,116 @@ __global__ __launch_bounds__(256) void k_finalize(EstShape e, const void* __rest
     out[j * e.n + i] = est;
   } else {
     out[m] = est;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(EstShape e, const void* __restrict__ part,
+                                                  int fp64, uint64_t nchunks,
+                                                  double* __restrict__ out) {
+  __shared__ double s_pos[256], s_neg[256];
+  finalize_block(e, part, fp64, nchunks, blockIdx.x, out, s_pos, s_neg);
+}
+
+// ---- batch phase kernels: the same bodies over the task lists ----
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// elements [t * kBatchElems, min(total, (t + 1) * kBatchElems)) of a step
+template <class F>
+__device__ __forceinline__ void elems_of_task(uint64_t t, uint64_t total, F&& fn) {
+  const uint64_t b = t * (uint64_t)kBatchElems;
+  const uint64_t e = umin64(total, b + kBatchElems);
+  for (uint64_t g = b + threadIdx.x; g < e; g += blockDim.x) fn(g);
+}
+
+__global__ __launch_bounds__(256) void k_batch_sample(const BatchTable* __restrict__ T) {
+  __shared__ double s_acc[256];
+  const int nq = T->nq;
+  const uint64_t* off = T->off + (uint64_t)kPhSample * (nq + 1);
+  // the render work queues start empty
+  if (blockIdx.x == 0 && threadIdx.x < 16) {
+    unsigned long long* c = threadIdx.x < 8 ? T->raster.ctr : T->pt.ctr;
+    c[threadIdx.x & 7] = 0ull;
+  }
+  const uint64_t total = off[nq];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = batch_find(off, nq, t);
+    const BatchQuery& Q = T->q[q];
+    uint64_t lt = t - off[q];
+    const bool hv = Q.e.what == kHvp || Q.e.what == kHvpLimit;
+    if (hv) {
+      if (lt == 0) {
+        vnorm_block(Q.e.n, Q.v, Q.u, Q.u + Q.e.n, s_acc);
+        continue;
+      }
+      lt -= 1;
+    }
+    const EstShape& e = Q.e;
+    elems_of_task(lt, e.streams * e.N * (uint64_t)e.n, [&](uint64_t g) {
+      sample_one(e.n, e.K, e.hessk, e.sampler, e.N, e.seed, e.sigma, g, Q.tau);
+    });
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_analytic(const BatchTable* __restrict__ T) {
+  const int nq = T->nq;
+  const uint64_t* off = T->off + (uint64_t)kPhAnalytic * (nq + 1);
+  const uint64_t total = off[nq];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = batch_find(off, nq, t);
+    const BatchQuery& Q = T->q[q];
+    const EstShape& e = Q.e;
+    const AnalyticScene& a = Q.as;
+    elems_of_task(t - off[q], e.R, [&](uint64_t r) {
+      analytic_one(a.kind, a.n, a.A, a.b, a.c, a.s1, Q.theta, Q.tau, Q.u, e.A, e.NH, e.h, r, Q.f);
+    });
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_prep(const BatchTable* __restrict__ T) {
+  const int nq = T->nq;
+  const uint64_t* off = T->off + (uint64_t)kPhPrep * (nq + 1);
+  const uint64_t total = off[nq];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = batch_find(off, nq, t);
+    const BatchQuery& Q = T->q[q];
+    elems_of_task(t - off[q], Q.e.streams * Q.e.N, [&](uint64_t sidx) {
+      prep_one(Q.e, Q.f, Q.tau, Q.u + Q.e.n, Q.v, sidx, Q.Fq, Q.vt);
+    });
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_accum(const BatchTable* __restrict__ T) {
+  __shared__ AccumLds lds;
+  const int nq = T->nq;
+  const uint64_t* off = T->off + (uint64_t)kPhAccum * (nq + 1);
+  const uint64_t total = off[nq];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = batch_find(off, nq, t);
+    const BatchQuery& Q = T->q[q];
+    const uint64_t lt = t - off[q];
+    if (per_element(Q.e.sampler)) {
+      // 256 (element, chunk) items per task, as 256-thread blocks
+      const uint64_t g = lt * 256u + threadIdx.x;
+      if (g < Q.nchunks * (uint64_t)Q.e.nout) accum_is_one(Q.e, Q.tau, Q.Fq, Q.fp64, Q.chunk, g, Q.acc);
+    } else {
+      accum_block(Q.e, Q.tau, Q.Fq, Q.vt, Q.v, Q.fp64, Q.chunk, lt, Q.acc, lds);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_finalize(const BatchTable* __restrict__ T) {
+  __shared__ double s_pos[256], s_neg[256];
+  const int nq = T->nq;
+  const uint64_t* off = T->off + (uint64_t)kPhFinalize * (nq + 1);
+  const uint64_t total = off[nq];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = batch_find(off, nq, t);
+    const BatchQuery& Q = T->q[q];
+    finalize_block(Q.e, Q.acc, Q.fp64, Q.nchunks, (int)(t - off[q]), Q.out, s_pos, s_neg);
   }
 }
 
@@ -353,6 +513,47 @@ void launch_finalize(hipStream_t st, const EstShape& e, const void* part, int fp
   const uint64_t nchunks = (e.N + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)e.nout), dim3(256), 0, st, e, part, fp64, nchunks,
                      out);
+}
+
+uint64_t batch_tasks(const BatchQuery& q, int phase) {
+  const EstShape& e = q.e;
+  auto ceil_div = [](uint64_t a, uint64_t b) { return (a + b - 1) / b; };
+  const bool render = q.scene == kDisks || q.scene == kPT;
+  switch (phase) {
+    case kPhSample:
+      return ((e.what == kHvp || e.what == kHvpLimit) ? 1 : 0) +
+             ceil_div(e.streams * e.N * (uint64_t)e.n, kBatchElems);
+    case kPhRecords:
+      return q.scene == kDisks ? ceil_div(e.R * (uint64_t)q.ds.D, kBatchElems) : 0;
+    case kPhAnalytic:
+      return render ? 0 : ceil_div(e.R, kBatchElems);
+    case kPhReduce:
+      return render ? ceil_div(e.R, kBatchRenders) : 0;
+    case kPhPrep:
+      return ceil_div(e.streams * e.N, kBatchElems);
+    case kPhAccum:
+      return per_element(e.sampler) ? ceil_div(q.nchunks * (uint64_t)e.nout, 256) : q.nchunks;
+    case kPhFinalize:
+      return (uint64_t)e.nout;
+    default:
+      return 0;
+  }
+}
+
+void launch_batch_sample(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_sample, dim3(blocks), dim3(256), 0, st, T);
+}
+void launch_batch_analytic(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_analytic, dim3(blocks), dim3(256), 0, st, T);
+}
+void launch_batch_prep(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_prep, dim3(blocks), dim3(256), 0, st, T);
+}
+void launch_batch_accum(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_accum, dim3(blocks), dim3(256), 0, st, T);
+}
+void launch_batch_finalize(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_finalize, dim3(blocks), dim3(256), 0, st, T);
 }
 
 }  // namespace hr

@@ -48,24 +48,35 @@ struct RasterExact {
   double h;
 };
 // One query's raster work: records of renders [0, R) (r_base = global index
-// of render 0 for the exact path), 32x32 tiles, S renders per work item.
+// of render 0 for the exact path).  A block covers bwx x bwy wave tiles of
+// 16x16 pixels and S renders per work item; the loss partial of every wave
+// tile is written to partial[r * subs + wave tile], so neither the block
+// shape nor S changes any result bit.
 struct RasterQuery {
   const float4* rec;
   const float* target;
   const float* colors;
   float* partial;
-  int W, H, C, D, S, tiles_x, tiles, pad;
+  int W, H, C, D, S;
+  int bwx, bwy;          // wave tiles per block along x and y (bwx * bwy == 4)
+  int tiles_x, tiles;    // blocks per row, per image
+  int subs_x, subs;      // wave tiles per row, per image
+  int pad;
   uint64_t R, r_base;
   RasterExact ex;
 };
+// block shapes: 0 or 1 = 32x32, 2 = 64x16, 3 = 16x64
+void raster_block_shape(int shape, int* bwx, int* bwy);
 size_t raster_lds_bytes(int D, int S);
 int raster_max_samples();
+// fills the geometry fields of a RasterQuery (W, H must be set)
+void raster_geometry(RasterQuery& a, int shape);
 void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
                     const double* tau, const double* u, float4* rec);
-// number of 32x32 tiles; partial[r * tiles + t]
-int raster_tiles(int W, int H);
+// number of 16x16 wave tiles of the image: the partial stride per render
+int raster_subtiles(int W, int H);
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
-                        int samples_per_block, const RasterExact& ex, float* partial);
+                        int samples_per_block, int shape, const RasterExact& ex, float* partial);
 void launch_tile_reduce(hipStream_t st, const float* partial, uint64_t R, int tiles,
                         double inv_count, double* f);
 void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& ex, float* image);
@@ -76,6 +87,8 @@ struct PTScene {
   const float* desc;     // FP32 copy of the scene description
 };
 int pt_tiles(int W, int H);
+int pt_tiles_x(int W);
+int pt_max_samples();
 void launch_pt_loss(hipStream_t st, const EstShape& e, const PTScene& s, const double* theta,
                     const double* tau, const double* u, int samples_per_block, float* partial);
 void launch_pt_render(hipStream_t st, const PTScene& s, const double* theta, uint64_t seed,
@@ -99,6 +112,103 @@ void launch_accum(hipStream_t st, const EstShape& e, const double* tau, const do
                   const double* vt, const double* v, int fp64, void* part, int chunk);
 void launch_finalize(hipStream_t st, const EstShape& e, const void* part, int fp64, int chunk,
                      double* out);
+
+// ---- batched execution ----
+// A batch runs many queries through one launch per phase.  Each phase kernel
+// walks a task list: the tasks of query q are [off[phase][q], off[phase][q+1]);
+// a task is either a run of kBatchElems consecutive elements of a per-element
+// step or one block of a per-block step, with the same arithmetic as the
+// single-query kernels (so every output is the same bits).  Renders come from
+// two persistent kernels that pull work items from eight queues, one per XCD.
+constexpr int kBatchElems = 2048;    // elements per task of an elementwise step
+constexpr int kBatchRenders = 64;    // renders per task of the tile reduction
+
+enum SceneKind { kDisks = 0, kPT = 1, kQuad = 2, kNegGauss = 3 };
+
+struct WorkSeg {           // one query's items in one work queue
+  uint64_t item0;          // first item of the segment within its queue
+  int q;                   // query
+  int c0;                  // first chunk; the segment holds chunks c0, c0 + 8, ...
+  int tiles;               // items per chunk (blocks of the image)
+  int pad;
+};
+struct WorkQueues {
+  const WorkSeg* seg;
+  unsigned long long* ctr;   // 8 item counters, zeroed by the sampling phase
+  uint64_t seg_off[9];       // queue x owns seg[seg_off[x] .. seg_off[x + 1])
+  uint64_t items[8];
+};
+struct BatchQuery {
+  EstShape e;
+  int scene, fp64, chunk, pt_S;
+  int pt_tiles_x, pt_tiles, part_stride, pad;
+  uint64_t nchunks;
+  double inv_count;          // 1 / (pixels * channels) of a render's loss
+  const double* theta;
+  const double* v;
+  double* out;
+  double* tau;
+  double* u;                 // n entries, then |v|
+  float4* rec;
+  float* partial;
+  double* f;
+  double* Fq;
+  double* vt;
+  void* acc;
+  DiskScene ds;
+  RasterQuery rq;
+  AnalyticScene as;
+  const void* ptc;           // device copy of the path tracer's constants
+  const float* pt_target;
+};
+enum BatchPhase { kPhSample = 0, kPhRecords, kPhAnalytic, kPhReduce, kPhPrep, kPhAccum,
+                  kPhFinalize, kNumPhases };
+struct BatchTable {
+  int nq, pad;
+  const BatchQuery* q;
+  const uint64_t* off;       // [kNumPhases][nq + 1]
+  WorkQueues raster, pt;
+};
+// device-side lookup: the query owning task t of a phase (t < off[nq])
+__device__ __forceinline__ int batch_find(const uint64_t* off, int nq, uint64_t t) {
+  int lo = 0, hi = nq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+// Copy of a small table entry whose address is the same for the whole block,
+// taken word by word through readfirstlane so that the compiler keeps it in
+// scalar registers (a plain load after the block's own stores would be a
+// vector load).
+template <class Ty>
+__device__ __forceinline__ Ty uniform_copy(const Ty* p) {
+  static_assert(sizeof(Ty) % 4 == 0, "word-sized table entries only");
+  Ty v;
+  const uint32_t* src = (const uint32_t*)p;
+  uint32_t* dst = (uint32_t*)&v;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(Ty) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return v;
+}
+// tasks per phase of one query (host planning)
+uint64_t batch_tasks(const BatchQuery& q, int phase);
+void launch_batch_sample(hipStream_t st, const BatchTable* T, int blocks);
+void launch_batch_records(hipStream_t st, const BatchTable* T, int blocks);
+void launch_batch_analytic(hipStream_t st, const BatchTable* T, int blocks);
+void launch_batch_raster(hipStream_t st, const BatchTable* T, int blocks, size_t lds);
+void launch_batch_pt(hipStream_t st, const BatchTable* T, int blocks);
+void launch_batch_reduce(hipStream_t st, const BatchTable* T, int blocks);
+void launch_batch_prep(hipStream_t st, const BatchTable* T, int blocks);
+void launch_batch_accum(hipStream_t st, const BatchTable* T, int blocks);
+void launch_batch_finalize(hipStream_t st, const BatchTable* T, int blocks);
+// occupancy of the persistent raster kernel (blocks per CU) for a given LDS size
+int batch_raster_blocks_per_cu(size_t lds);
+int batch_pt_blocks_per_cu();
+// path tracer constants for device-resident scenes
+size_t pt_const_bytes();
+void pt_fill_const(const PTScene& s, void* host_out);
 
 // ---- solver ----
 struct CgState {

@@ -13,6 +13,8 @@
 // words and the primary ray are generated once per (pixel, spp) and traced
 // against each render's light/sphere placement.  Loss partials per
 // (render, tile) as in the rasteriser.
+#include <cstring>
+
 #include "hr_device.h"
 #include "hr_kernels.h"
 
@@ -180,22 +182,16 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// One block's work: draws [d0, d0 + nd) of one query on one 16x16 tile,
+// all NR renders of each draw.  Shared by the per-query and the batch kernel.
 template <int NR>
-__global__ __launch_bounds__(256) void k_pt_loss(PTConst P, const double* __restrict__ theta,
-                                                 const double* __restrict__ tau,
-                                                 const double* __restrict__ u,
-                                                 const float* __restrict__ target, EstShape e,
-                                                 int S, int tiles_x, int tiles, uint64_t draw0,
-                                                 uint64_t chunks, float* __restrict__ partial) {
-  __shared__ float s_part[kPtMaxS * NR][4];
-  const uint64_t b = blockIdx.x;
-  const uint64_t xcd = b & 7u, j = b >> 3;
-  const uint64_t chunk = (j / (uint64_t)tiles) * 8u + xcd;
-  const int tile = (int)(j % (uint64_t)tiles);
-  if (chunk >= chunks) return;
-  const uint64_t total = e.streams * e.N;
-  const uint64_t d0 = draw0 + chunk * (uint64_t)S;
-  const int nd = (int)min((uint64_t)S, total - d0);
+__device__ __forceinline__ void pt_block(const PTConst& P, const double* __restrict__ theta,
+                                         const double* __restrict__ tau,
+                                         const double* __restrict__ u,
+                                         const float* __restrict__ target, const EstShape& e,
+                                         int tiles_x, int tiles, int tile, uint64_t d0, int nd,
+                                         float* __restrict__ partial, float (*s_part)[4]) {
+  __syncthreads();   // the previous work item's readers of LDS are done
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x = (tile % tiles_x) * kPtTile + (threadIdx.x & 15);
   const int y = (tile / tiles_x) * kPtTile + (threadIdx.x >> 4);
@@ -261,6 +257,73 @@ __global__ __launch_bounds__(256) void k_pt_loss(PTConst P, const double* __rest
   }
 }
 
+template <int NR>
+__global__ __launch_bounds__(256) void k_pt_loss(PTConst P, const double* __restrict__ theta,
+                                                 const double* __restrict__ tau,
+                                                 const double* __restrict__ u,
+                                                 const float* __restrict__ target, EstShape e,
+                                                 int S, int tiles_x, int tiles, uint64_t draw0,
+                                                 uint64_t chunks, float* __restrict__ partial) {
+  __shared__ float s_part[kPtMaxS * NR][4];
+  // XCD-aware order as in the rasteriser
+  const uint64_t b = blockIdx.x;
+  const uint64_t xcd = b & 7u, j = b >> 3;
+  const uint64_t chunk = (j / (uint64_t)tiles) * 8u + xcd;
+  const int tile = (int)(j % (uint64_t)tiles);
+  if (chunk >= chunks) return;
+  const uint64_t total = e.streams * e.N;
+  const uint64_t d0 = draw0 + chunk * (uint64_t)S;
+  const int nd = (int)min((uint64_t)S, total - d0);
+  pt_block<NR>(P, theta, tau, u, target, e, tiles_x, tiles, tile, d0, nd, partial, s_part);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Persistent path tracer over its eight work queues (same scheme as the
+// persistent rasteriser: item = (query, chunk of S draws, 16x16 tile)).
+__global__ __launch_bounds__(256) void k_batch_pt(const BatchTable* __restrict__ T) {
+  __shared__ float s_part[kPtMaxS * 4][4];
+  __shared__ unsigned long long s_item;
+  const WorkQueues& W = T->pt;
+  const int home = blockIdx.x & 7;
+  for (int k = 0; k < 8; ++k) {
+    const int x = (home + k) & 7;
+    const uint64_t nitems = W.items[x];
+    const uint64_t sb = W.seg_off[x], se = W.seg_off[x + 1];
+    for (;;) {
+      if (threadIdx.x == 0) s_item = atomicAdd(&W.ctr[x], 1ull);
+      __syncthreads();
+      const uint64_t it = uniform64(s_item);
+      __syncthreads();
+      if (it >= nitems) break;
+      uint64_t lo = sb, hi = se - 1;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (W.seg[mid].item0 <= it) lo = mid; else hi = mid - 1;
+      }
+      const WorkSeg sg = W.seg[lo];
+      const BatchQuery& Q = T->q[sg.q];
+      const PTConst& P = *(const PTConst*)Q.ptc;
+      const uint64_t l = it - sg.item0;
+      const uint64_t chunk = (uint64_t)sg.c0 + 8u * (l / (uint64_t)sg.tiles);
+      const int tile = (int)(l % (uint64_t)sg.tiles);
+      const uint64_t d0 = chunk * (uint64_t)Q.pt_S;
+      const int nd = (int)min((uint64_t)Q.pt_S, Q.e.streams * Q.e.N - d0);
+      const int nr = Q.e.A * Q.e.NH;
+      if (nr == 1)
+        pt_block<1>(P, Q.theta, Q.tau, Q.u, Q.pt_target, Q.e, Q.pt_tiles_x, Q.pt_tiles, tile, d0, nd, Q.partial, s_part);
+      else if (nr == 2)
+        pt_block<2>(P, Q.theta, Q.tau, Q.u, Q.pt_target, Q.e, Q.pt_tiles_x, Q.pt_tiles, tile, d0, nd, Q.partial, s_part);
+      else
+        pt_block<4>(P, Q.theta, Q.tau, Q.u, Q.pt_target, Q.e, Q.pt_tiles_x, Q.pt_tiles, tile, d0, nd, Q.partial, s_part);
+    }
+  }
+}
+
 __global__ void k_pt_render(PTConst P, Placement pl, uint64_t seed, uint32_t s, int spp,
                             float* __restrict__ image) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
@@ -302,6 +365,7 @@ PTConst make_const(const PTScene& s, int spp) {
 }  // namespace
 
 int pt_tiles(int W, int H) { return ((W + kPtTile - 1) / kPtTile) * ((H + kPtTile - 1) / kPtTile); }
+int pt_tiles_x(int W) { return (W + kPtTile - 1) / kPtTile; }
 
 void launch_pt_loss(hipStream_t st, const EstShape& e, const PTScene& s, const double* theta,
                     const double* tau, const double* u, int S, float* partial) {
@@ -337,5 +401,24 @@ void launch_pt_render(hipStream_t st, const PTScene& s, const double* theta, uin
   hipLaunchKernelGGL(k_pt_render, dim3((s.W + 63) / 64, s.H), dim3(64), 0, st, P, pl, seed, sidx,
                      spp, image);
 }
+
+size_t pt_const_bytes() { return sizeof(PTConst); }
+
+void pt_fill_const(const PTScene& s, void* host_out) {
+  const PTConst P = make_const(s, s.spp);
+  memcpy(host_out, &P, sizeof(PTConst));
+}
+
+void launch_batch_pt(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_pt, dim3(blocks), dim3(256), 0, st, T);
+}
+
+int batch_pt_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pt, 256, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+int pt_max_samples() { return kPtMaxS; }
 
 }  // namespace hr

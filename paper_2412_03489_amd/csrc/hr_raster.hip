@@ -3,9 +3,9 @@
 // One render = the disk scene at theta_r = theta (+- h u) - a tau_s.  The
 // loss of a render is the mean over H*W*C of (I - T)^2 (the image loss of the
 // paper's tasks, section "Methods").  Work decomposition:
-//   block (256 threads = 4 wave64) = one 32x32 pixel tile x S consecutive
-//   renders; each wave owns a 16x16 sub-tile, each lane one pixel column of 4
-//   rows.  The target tile lives in registers for all S renders.  Per render a
+//   block (256 threads = 4 wave64) = four 16x16 wave tiles (arranged 2x2,
+//   4x1 or 1x4) x S consecutive renders; each lane owns one pixel column of 4
+//   rows of its wave tile.  The target tile lives in registers for all S renders.  Per render a
 //   wave loads the disk records (one disk per lane, the next render's records
 //   already in flight), culls them against its sub-tile with a conservative
 //   circle/rectangle test, and walks the surviving disks in painter's order as
@@ -21,8 +21,9 @@
 // A sub-tile that no disk reaches renders as background; its loss is the
 // sub-tile's sum of T^2, computed once per block with the same arithmetic.
 // Per render each wave folds its lanes in quads (two DPP adds) and parks 16
-// partials in LDS; after the S renders the block sums them in a fixed order,
-// giving one FP32 partial per (render, tile).
+// partials in LDS; after the S renders the block sums each wave's 16 in a
+// fixed order, giving one FP32 partial per (render, wave tile) -- the same
+// bits for any block shape and any S.
 #include "hr_device.h"
 #include "hr_kernels.h"
 
@@ -30,8 +31,7 @@ namespace hr {
 
 namespace {
 
-constexpr int kTile = 32;        // block tile side (pixels)
-constexpr int kSub = 16;         // wave sub-tile side
+constexpr int kSub = 16;         // wave tile side (pixels)
 constexpr int kRows = 4;         // rows per lane
 constexpr int kMaxS = 64;        // renders per block (upper bound)
 constexpr int kQuadStride = 17;  // 16 quad partials per wave-render, padded
@@ -47,40 +47,48 @@ __host__ __device__ inline double ambiguity_band(double cx, double cy, double r)
 }
 
 // record: (cx, cy, (r^2 + band)(1 + 1e-5), r^2 - band) in FP32; r <= 0: never covered
+__device__ __forceinline__ void record_one(const double* __restrict__ theta,
+                                           const double* __restrict__ tau,
+                                           const double* __restrict__ u,
+                                           const float* __restrict__ radius, int n, int D, int ppd,
+                                           int A, int NH, double h, uint64_t gid,
+                                           float4* __restrict__ rec) {
+  const int k = (int)(gid % (uint64_t)D);
+  const uint64_t r = gid / (uint64_t)D;
+  const int sh = (int)(r % (uint64_t)NH);
+  const uint64_t rem = r / (uint64_t)NH;
+  const int ai = (int)(rem % (uint64_t)A);
+  const uint64_t sidx = rem / (uint64_t)A;
+  const double* t = tau + sidx * (uint64_t)n;
+  const double a = ai == 0 ? 1.0 : -1.0;
+  const double shift = sh == 0 ? h : -h;
+  double p[3];
+  for (int q = 0; q < ppd; ++q) {
+    const int j = k * ppd + q;
+    double base = theta[j];
+    if (NH == 2) base = base + shift * u[j];
+    p[q] = base - a * t[j];
+  }
+  const double rad = ppd == 3 ? p[2] : (double)radius[k];
+  float4 out = make_float4((float)p[0], (float)p[1], -1.0f, -1.0f);
+  if (rad > 0.0) {
+    // r^2 +- band; the upper value is also the cull radius, widened by a
+    // further 1e-5 relative so that culling stays conservative in FP32
+    const double r2 = (double)(float)(rad * rad);
+    const double band = ambiguity_band(p[0], p[1], rad);
+    out.z = (float)((r2 + band) * 1.00001);
+    out.w = (float)(r2 - band);
+  }
+  rec[gid] = out;
+}
+
 __global__ void k_records(const double* __restrict__ theta, const double* __restrict__ tau,
                           const double* __restrict__ u, const float* __restrict__ radius,
                           int n, int D, int ppd, int A, int NH, double h, uint64_t total,
                           float4* __restrict__ rec) {
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
-       gid += (uint64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(gid % (uint64_t)D);
-    const uint64_t r = gid / (uint64_t)D;
-    const int sh = (int)(r % (uint64_t)NH);
-    const uint64_t rem = r / (uint64_t)NH;
-    const int ai = (int)(rem % (uint64_t)A);
-    const uint64_t sidx = rem / (uint64_t)A;
-    const double* t = tau + sidx * (uint64_t)n;
-    const double a = ai == 0 ? 1.0 : -1.0;
-    const double shift = sh == 0 ? h : -h;
-    double p[3];
-    for (int q = 0; q < ppd; ++q) {
-      const int j = k * ppd + q;
-      double base = theta[j];
-      if (NH == 2) base = base + shift * u[j];
-      p[q] = base - a * t[j];
-    }
-    const double rad = ppd == 3 ? p[2] : (double)radius[k];
-    float4 out = make_float4((float)p[0], (float)p[1], -1.0f, -1.0f);
-    if (rad > 0.0) {
-      // r^2 +- band; the upper value is also the cull radius, widened by a
-      // further 1e-5 relative so that culling stays conservative in FP32
-      const double r2 = (double)(float)(rad * rad);
-      const double band = ambiguity_band(p[0], p[1], rad);
-      out.z = (float)((r2 + band) * 1.00001);
-      out.w = (float)(r2 - band);
-    }
-    rec[gid] = out;
-  }
+       gid += (uint64_t)gridDim.x * blockDim.x)
+    record_one(theta, tau, u, radius, n, D, ppd, A, NH, h, gid, rec);
 }
 
 // Exact coverage of pixel (x, y) by disk k of render r, in FP64 from the
@@ -124,15 +132,17 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
 // One block's work: renders [r0, r0 + nr) of one query on one 32x32 tile.
 // Shared by the per-query kernel and the persistent batch kernel, so a render's
 // tile partial is the same bits whichever launch computes it.
-template <int C, bool kOneGroup>
-__device__ __forceinline__ void raster_block(const RasterQuery& a, int tile, uint64_t r0, int nr,
+template <int C, bool kOneGroup, class Query>
+__device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t r0, int nr,
                                              float4* smem) {
-  const int W = a.W, H = a.H, D = a.D, S = a.S, tiles_x = a.tiles_x, tiles = a.tiles;
+  const int W = a.W, H = a.H, D = a.D, S = a.S, tiles_x = a.tiles_x, bwx = a.bwx;
+  const int subs_x = a.subs_x;
+  const uint64_t subs = (uint64_t)a.subs;
   const float4* __restrict__ rec = a.rec;
   const float* __restrict__ target = a.target;
   const float* __restrict__ colors = a.colors;
   float* __restrict__ partial = a.partial;
-  const RasterExact& ex = a.ex;
+  auto& ex = a.ex;
   const uint64_t r_base = a.r_base;
   float4* s_col = smem;                        // D + 1 colours, index 0 = background
   float* s_q = (float*)(smem + (D + 1));       // [S][4 waves][kQuadStride]
@@ -151,8 +161,11 @@ __device__ __forceinline__ void raster_block(const RasterQuery& a, int tile, uin
   }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tx0 = (tile % tiles_x) * kTile + (wave & 1) * kSub;
-  const int ty0 = (tile / tiles_x) * kTile + (wave >> 1) * kSub;
+  const int bx0 = (tile % tiles_x) * (kSub * bwx), by0 = (tile / tiles_x) * (kSub * a.bwy);
+  const int tx0 = bx0 + (wave % bwx) * kSub;
+  const int ty0 = by0 + (wave / bwx) * kSub;
+  // a wave tile wholly outside the image renders nothing and writes no partial
+  const bool live = tx0 < W && ty0 < H;
   const int x = tx0 + (lane & 15);
   const int yb = ty0 + (lane >> 4) * kRows;
   const float invW = 1.0f / (float)W, invH = 1.0f / (float)H;
@@ -188,7 +201,8 @@ __device__ __forceinline__ void raster_block(const RasterQuery& a, int tile, uin
   // loaded while this render is processed (clamped on the last render)
   const int lane_d = lane < D ? lane : D - 1;
   float4 q_next = rp0[lane_d];
-  for (int rr = 0; rr < nr; ++rr) {
+  const int nr_wave = live ? nr : 0;
+  for (int rr = 0; rr < nr_wave; ++rr) {
     const float4* rp = rp0 + (uint64_t)rr * D;
     int idx[kRows];
 #pragma unroll
@@ -281,17 +295,15 @@ __device__ __forceinline__ void raster_block(const RasterQuery& a, int tile, uin
     if ((lane & 3) == 0) s_q[(rr * 4 + wave) * kQuadStride + (lane >> 2)] = e;
   }
   __syncthreads();
-  // fixed-order sums: 16 quads per wave, then the 4 waves
+  // fixed-order sum of each wave's 16 quad partials: one partial per wave tile
   for (int t = threadIdx.x; t < nr * 4; t += blockDim.x) {
+    const int w = t & 3;
+    const int wx0 = bx0 + (w % bwx) * kSub, wy0 = by0 + (w / bwx) * kSub;
+    if (wx0 >= W || wy0 >= H) continue;
     float acc = 0.0f;
     for (int qd = 0; qd < 16; ++qd) acc += s_q[t * kQuadStride + qd];
-    s_q[t * kQuadStride + 16] = acc;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nr; t += blockDim.x) {
-    const float* w4 = s_q + (t * 4) * kQuadStride + 16;
-    const float v = ((w4[0] + w4[kQuadStride]) + w4[2 * kQuadStride]) + w4[3 * kQuadStride];
-    partial[(r0 + (uint64_t)t) * (uint64_t)tiles + tile] = v;
+    const uint64_t sub = (uint64_t)(wy0 / kSub) * (uint64_t)subs_x + (uint64_t)(wx0 / kSub);
+    partial[(r0 + (uint64_t)(t >> 2)) * subs + sub] = acc;
   }
 }
 
@@ -307,22 +319,28 @@ __global__ __launch_bounds__(256) void k_raster_loss(RasterQuery a, uint64_t chu
   if (chunk >= chunks) return;
   const uint64_t r0 = chunk * (uint64_t)a.S;
   const int nr = (int)min((uint64_t)a.S, a.R - r0);
-  raster_block<C, kOneGroup>(a, tile, r0, nr, smem);
+  raster_block<C, kOneGroup, RasterQuery>(a, tile, r0, nr, smem);
 }
 
-// one wave per render: fixed-order FP64 sum of the tile partials
+// fixed-order FP64 sum of the tile partials of render r, by one wave
+__device__ __forceinline__ void reduce_render(const float* __restrict__ partial, int tiles,
+                                              double inv_count, uint64_t r,
+                                              double* __restrict__ f) {
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  for (int t = lane; t < tiles; t += 64) acc += (double)partial[r * (uint64_t)tiles + t];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) f[r] = acc * inv_count;
+}
+
+// one wave per render
 __global__ void k_tile_reduce(const float* __restrict__ partial, uint64_t R, int tiles,
                               double inv_count, double* __restrict__ f) {
-  const int lane = threadIdx.x & 63;
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t r = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < R;
-       r += waves) {
-    double acc = 0.0;
-    for (int t = lane; t < tiles; t += 64) acc += (double)partial[r * (uint64_t)tiles + t];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) f[r] = acc * inv_count;
-  }
+       r += waves)
+    reduce_render(partial, tiles, inv_count, r, f);
 }
 
 // single render at theta, coverage in FP64 (the definition)
@@ -336,6 +354,96 @@ __global__ void k_render_disks(RasterExact ex, const float* __restrict__ colors,
     if (cover_fp64(ex, 0, k, x, y, W, H)) top = k;
   for (int c = 0; c < C; ++c)
     image[((size_t)y * W + x) * C + c] = top >= 0 ? colors[(size_t)top * C + c] : 0.0f;
+}
+
+// ---- batch kernels ----
+typedef const RasterQuery __attribute__((address_space(4))) ConstRasterQuery;
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(256) void k_batch_records(const BatchTable* __restrict__ T) {
+  const int nq = T->nq;
+  const uint64_t* off = T->off + (uint64_t)kPhRecords * (nq + 1);
+  const uint64_t total = off[nq];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = batch_find(off, nq, t);
+    const BatchQuery& Q = T->q[q];
+    const EstShape& e = Q.e;
+    const uint64_t b = (t - off[q]) * (uint64_t)kBatchElems;
+    const uint64_t end = umin64(e.R * (uint64_t)Q.ds.D, b + kBatchElems);
+    for (uint64_t g = b + threadIdx.x; g < end; g += blockDim.x)
+      record_one(Q.theta, Q.tau, Q.u, Q.ds.radius, e.n, Q.ds.D, Q.ds.ppd, e.A, e.NH, e.h, g, Q.rec);
+  }
+}
+
+// Persistent raster over the eight work queues.  Queue x holds the chunks of
+// S renders whose position in the batch's chunk sequence is x mod 8, each
+// chunk as one item per block of its image; blocks start on the queue of
+// their XCD (block id mod 8), so the records of a chunk are read by one XCD,
+// and move on to the other queues when theirs is empty.  Every item is
+// claimed by exactly one atomic increment; a block leaves after seeing all
+// eight queues exhausted.
+__global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restrict__ T) {
+  extern __shared__ float4 smem[];
+  __shared__ unsigned long long s_item;
+  const WorkQueues& W = T->raster;
+  const int home = blockIdx.x & 7;
+  for (int k = 0; k < 8; ++k) {
+    const int x = (home + k) & 7;
+    const uint64_t nitems = W.items[x];
+    const uint64_t sb = W.seg_off[x], se = W.seg_off[x + 1];
+    for (;;) {
+      if (threadIdx.x == 0) s_item = atomicAdd(&W.ctr[x], 1ull);
+      __syncthreads();
+      const uint64_t it = uniform64(s_item);
+      __syncthreads();   // every thread has read s_item before it is reused
+      if (it >= nitems) break;
+      // segment of the item: largest s in [sb, se) with seg[s].item0 <= it
+      uint64_t lo = sb, hi = se - 1;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (uniform64(W.seg[mid].item0) <= it) lo = mid; else hi = mid - 1;
+      }
+      const WorkSeg sg = uniform_copy(&W.seg[lo]);
+      // the query descriptor is read through the constant address space: the
+      // batch never writes it, so its fields come in by scalar loads on use
+      const ConstRasterQuery& a = *(const ConstRasterQuery*)(&T->q[sg.q].rq);
+      const uint64_t l = it - sg.item0;
+      const uint64_t chunk = (uint64_t)sg.c0 + 8u * (l / (uint64_t)sg.tiles);
+      const int tile = (int)(l % (uint64_t)sg.tiles);
+      const uint64_t r0 = chunk * (uint64_t)a.S;
+      const int nr = (int)min((uint64_t)a.S, a.R - r0);
+      const bool one = a.D <= 64;
+      switch (a.C) {
+        case 1: if (one) raster_block<1, true, ConstRasterQuery>(a, tile, r0, nr, smem);
+                else raster_block<1, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+        case 2: if (one) raster_block<2, true, ConstRasterQuery>(a, tile, r0, nr, smem);
+                else raster_block<2, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+        case 3: if (one) raster_block<3, true, ConstRasterQuery>(a, tile, r0, nr, smem);
+                else raster_block<3, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+        default: if (one) raster_block<4, true, ConstRasterQuery>(a, tile, r0, nr, smem);
+                 else raster_block<4, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+      }
+    }
+  }
+}
+
+// tile partials -> per-render loss for raster and path-traced queries
+__global__ __launch_bounds__(256) void k_batch_reduce(const BatchTable* __restrict__ T) {
+  const int nq = T->nq;
+  const uint64_t* off = T->off + (uint64_t)kPhReduce * (nq + 1);
+  const uint64_t total = off[nq];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = batch_find(off, nq, t);
+    const BatchQuery& Q = T->q[q];
+    const uint64_t b = (t - off[q]) * (uint64_t)kBatchRenders;
+    const uint64_t end = umin64(Q.e.R, b + kBatchRenders);
+    for (uint64_t r = b + (threadIdx.x >> 6); r < end; r += (blockDim.x >> 6))
+      reduce_render(Q.partial, Q.part_stride, Q.inv_count, r, Q.f);
+  }
 }
 
 inline unsigned grid_for(uint64_t total, int block) {
@@ -352,7 +460,21 @@ void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const
                      s.radius, e.n, s.D, s.ppd, e.A, e.NH, e.h, total, rec);
 }
 
-int raster_tiles(int W, int H) { return ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile); }
+int raster_subtiles(int W, int H) { return ((W + kSub - 1) / kSub) * ((H + kSub - 1) / kSub); }
+
+void raster_block_shape(int shape, int* bwx, int* bwy) {
+  *bwx = shape == 2 ? 4 : (shape == 3 ? 1 : 2);
+  *bwy = 4 / *bwx;
+}
+
+void raster_geometry(RasterQuery& a, int shape) {
+  raster_block_shape(shape, &a.bwx, &a.bwy);
+  a.tiles_x = (a.W + kSub * a.bwx - 1) / (kSub * a.bwx);
+  a.tiles = a.tiles_x * ((a.H + kSub * a.bwy - 1) / (kSub * a.bwy));
+  a.subs_x = (a.W + kSub - 1) / kSub;
+  a.subs = raster_subtiles(a.W, a.H);
+  a.pad = 0;
+}
 
 size_t raster_lds_bytes(int D, int S) {
   return (size_t)(D + 1) * sizeof(float4) + (size_t)S * 4 * kQuadStride * sizeof(float) +
@@ -362,10 +484,12 @@ size_t raster_lds_bytes(int D, int S) {
 int raster_max_samples() { return kMaxS; }
 
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
-                        int S, const RasterExact& ex, float* partial) {
+                        int S, int shape, const RasterExact& ex, float* partial) {
   if (S <= 0 || S > kMaxS) S = kMaxS;
-  const int tiles_x = (s.W + kTile - 1) / kTile;
-  const int tiles = raster_tiles(s.W, s.H);
+  RasterQuery a;
+  a.W = s.W; a.H = s.H; a.C = s.C; a.D = s.D; a.S = S;
+  raster_geometry(a, shape);
+  const int tiles = a.tiles;
   const uint64_t chunks = (R + S - 1) / S;
   const size_t lds = raster_lds_bytes(s.D, S);
   // grid: 8 XCD lanes x tiles x ceil(chunks / 8); launched in slices that keep
@@ -376,13 +500,10 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
     const uint64_t rows = umin64(max_rows, per_xcd - row0);
     const uint64_t sub_chunks = umin64(chunks - row0 * 8, rows * 8);
     const uint64_t r_base = row0 * 8 * (uint64_t)S;
-    RasterQuery a;
     a.rec = rec + r_base * (uint64_t)s.D;
     a.target = s.target;
     a.colors = s.colors;
-    a.partial = partial + r_base * (uint64_t)tiles;
-    a.W = s.W; a.H = s.H; a.C = s.C; a.D = s.D; a.S = S;
-    a.tiles_x = tiles_x; a.tiles = tiles;
+    a.partial = partial + r_base * (uint64_t)a.subs;
     a.R = umin64(R - r_base, sub_chunks * (uint64_t)S);
     a.r_base = r_base;
     a.ex = ex;
@@ -410,6 +531,22 @@ void launch_tile_reduce(hipStream_t st, const float* partial, uint64_t R, int ti
 void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& ex, float* image) {
   hipLaunchKernelGGL(k_render_disks, dim3((s.W + 63) / 64, s.H), dim3(64), 0, st, ex, s.colors,
                      s.W, s.H, s.C, s.D, image);
+}
+
+void launch_batch_records(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_records, dim3(blocks), dim3(256), 0, st, T);
+}
+void launch_batch_raster(hipStream_t st, const BatchTable* T, int blocks, size_t lds) {
+  hipLaunchKernelGGL(k_batch_raster, dim3(blocks), dim3(256), lds, st, T);
+}
+void launch_batch_reduce(hipStream_t st, const BatchTable* T, int blocks) {
+  hipLaunchKernelGGL(k_batch_reduce, dim3(blocks), dim3(256), 0, st, T);
+}
+int batch_raster_blocks_per_cu(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_raster, 256, lds) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
 }
 
 }  // namespace hr
