@@ -83,6 +83,104 @@ def cpu_baseline(w, draws):
                       f"({renders} renders of 256x256x3), {dt:.2f} s wall"}
 
 
+def rel_inf(x, ref):
+    x = np.ravel(np.asarray(x, float))
+    ref = np.ravel(np.asarray(ref, float))
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def uneven_section(P, ctx, reps):
+    """64 uneven disk instances at their full sample budgets: plain per-query
+    calls one after another vs one batch (persistent launches, graph replay,
+    autotuned raster configuration)."""
+    import workloads as WL
+    ws = WL.uneven(64)
+    scenes, qs = [], []
+    renders = pixels = 0
+    for w in ws:
+        sc = P.Scene.disks(ctx, w.W, w.H, w.C, w.colors, render_target_on_gpu(P, ctx, w),
+                           radius=w.radius, ppd=w.ppd)
+        scenes.append(sc)
+        kind = w.kinds[0]
+        q = dict(scene=sc, kind=kind, theta=w.theta0, sigma=w.sigma, N=w.N, seed=w.seed)
+        if kind == "hvp":
+            q["v"] = w.v
+        qs.append(q)
+        R = P.n_renders(kind, w.n, w.N)
+        renders += R
+        pixels += R * w.pixels
+
+    def plain():
+        return [P.estimate(q["kind"], q["scene"], q["theta"], q["sigma"], q["N"], q["seed"],
+                           v=q.get("v")) for q in qs]
+
+    log("bench: uneven batch, plain per-query calls")
+    ref = plain()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain()
+    t_plain = (time.perf_counter() - t0) / reps
+    log("bench: uneven batch, batched (autotune on the first run)")
+    b = P.Batch(ctx, use_graph=True, autotune=True)
+    got = b.run(qs)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got = b.run(qs)
+    t_batch = (time.perf_counter() - t0) / reps
+    rep = b.report()
+    identical = all(np.array_equal(x, y) for x, y in zip(got, ref))
+    # precision plan: compensated-FP32 lobe sums against FP64 accumulation
+    fp64 = P.Batch(ctx, use_graph=False).run([dict(q, accum_fp64=True) for q in qs])
+    err = max(rel_inf(x, y) for x, y in zip(got, fp64))
+    b.close()
+    for sc in scenes:
+        sc.close()
+    return {"instances": len(qs), "renders": renders, "perturbed_Mpix": round(pixels / 1e6, 1),
+            "plain": {"ms": round(t_plain * 1e3, 3), "queries_per_s": round(len(qs) / t_plain, 1),
+                      "Mpix_per_s": round(pixels / t_plain / 1e6, 1)},
+            "batched": {"ms": round(t_batch * 1e3, 3),
+                        "queries_per_s": round(len(qs) / t_batch, 1),
+                        "Mpix_per_s": round(pixels / t_batch / 1e6, 1),
+                        "graph": bool(rep["graph"]), "raster_items": rep["raster_items"],
+                        "raster_blocks": rep["raster_blocks"]},
+            "speedup": round(t_plain / t_batch, 3), "identical_to_plain": identical,
+            "comp_fp32_vs_fp64_accum_max_rel": err, "reps": reps}
+
+
+def serving_section(P, ctx, args):
+    """Newton optimisations arriving as a Poisson stream over the raster and
+    path-traced scenes: continuous-batching server vs plain per-query calls."""
+    import workloads as WL
+    from paper_2412_03489_amd import serving as SV
+    wr = WL.disks32()
+    wp = WL.pt_spheres()
+    sr = P.Scene.disks(ctx, wr.W, wr.H, wr.C, wr.colors, render_target_on_gpu(P, ctx, wr),
+                       radius=wr.radius, ppd=wr.ppd)
+    s0 = P.Scene.pt(ctx, wp.W, wp.H, wp.spp, wp.desc, np.zeros((wp.H, wp.W, 3), np.float32))
+    tp = s0.render(wp.theta_star, seed=wp.target_seed, s=0, spp=wp.target_spp)
+    s0.close()
+    sp = P.Scene.pt(ctx, wp.W, wp.H, wp.spp, wp.desc, tp)
+    scenes = {"raster": sr, "pt": sp}
+    sigma = {"raster": wr.sigma, "pt": wp.sigma}
+    N = {"raster": args.serving_n_raster, "pt": args.serving_n_pt}
+    specs = WL.serving_clients(args.serving_clients, rate=args.serving_rate)
+    # warm both paths
+    warm = WL.serving_clients(4, rate=1e6, base_seed=99)
+    SV.run_plain(ctx, SV.make_clients(warm, scenes, sigma, N, args.serving_cg))
+    SV.run_served(ctx, SV.make_clients(warm, scenes, sigma, N, args.serving_cg))
+    log(f"bench: serving {len(specs)} clients, plain")
+    plain = SV.run_plain(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
+    log("bench: serving, continuous batching")
+    served = SV.run_served(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
+    sr.close()
+    sp.close()
+    rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+    return {"clients": len(specs), "arrival_rate_per_s": args.serving_rate,
+            "draws": {"raster_hvp_grad": N["raster"], "pt_grad_hess": N["pt"]},
+            "cg_iters": args.serving_cg, "plain": rnd(plain), "served": rnd(served),
+            "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +193,14 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB "
                          "(a kernel of known traffic for scaling memory counters)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
+    ap.add_argument("--uneven-reps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serving-clients", type=int, default=256)
+    ap.add_argument("--serving-rate", type=float, default=512.0)
+    ap.add_argument("--serving-n-raster", type=int, default=16384)
+    ap.add_argument("--serving-n-pt", type=int, default=2048)
+    ap.add_argument("--serving-cg", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -201,6 +307,10 @@ def main():
     for b in (th0, th, v, out):
         b.free()
     sc.close()
+    if not args.no_uneven:
+        line["uneven_batch"] = uneven_section(P, ctx, args.uneven_reps)
+    if not args.no_serving:
+        line["serving"] = serving_section(P, ctx, args)
     ctx.close()
     if not args.no_cpu:
         log(f"bench: CPU oracle baseline at N={args.cpu_draws}")

@@ -204,7 +204,7 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
     timed(ctx, "raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, o.raster_tile, ex, partial); });
     launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
   } else if (sc->kind == kPT) {
-    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data()};
+    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
     timed(ctx, "pt_loss", [&] { launch_pt_loss(s, e, ps, d_theta, tau, u, spb, partial); });
     launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f);
   } else {
@@ -467,7 +467,7 @@ hr_status hr_scene_pt(hr_ctx* ctx, int W, int H, int spp, int nspheres, const do
   hr_status st = upload(target, (size_t)W * H * 3 * 4, (void**)&sc->target);
   if (!st) {
     // the path tracer's constants, resident for the batch kernels
-    const PTScene ps{W, H, spp, nspheres, sc->target, d.data()};
+    const PTScene ps{W, H, spp, nspheres, sc->target, d.data(), nullptr};
     std::vector<char> pc(pt_const_bytes());
     pt_fill_const(ps, pc.data());
     st = upload(pc.data(), pc.size(), &sc->ptc);
@@ -543,7 +543,7 @@ hr_status hr_render(hr_scene* sc, const double* theta, uint64_t seed, uint32_t s
     RasterExact ex{d_theta, nullptr, nullptr, sc->radius, sc->n, sc->ppd, 1, 1, 0.0};
     launch_render_disks(ctx->stream, ds, ex, d_img);
   } else {
-    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data()};
+    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
     launch_pt_render(ctx->stream, ps, theta, seed, s, spp > 0 ? spp : sc->spp, d_img);
   }
   HR_HIP(hipGetLastError());

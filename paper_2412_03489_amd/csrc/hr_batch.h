@@ -24,7 +24,8 @@ struct BatchSlot {
   hr_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  int cus = 1, phase_blocks = 1, raster_blocks = 1, pt_blocks = 1;
+  int cus = 1, phase_blocks = 1, raster_blocks = 1;
+  int pt_blocks[3] = {1, 1, 1};    // per renders-per-draw class (1, 2, 4)
   void* dev = nullptr;             // device table: header, queries, task lists,
   void* host = nullptr;            //   queue segments, counters, theta/v, outputs
   size_t table_bytes = 0;          //   (pinned host mirror of the same layout)

@@ -52,7 +52,7 @@ hr_status BatchSlot::init(hr_ctx* c) {
   HR_HIP(hipGetDeviceProperties(&prop, ctx->device));
   cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
   phase_blocks = cus * kPhaseBlocksPerCU;
-  pt_blocks = cus * batch_pt_blocks_per_cu();
+  for (int c = 0; c < 3; ++c) pt_blocks[c] = cus * batch_pt_blocks_per_cu(1 << c);
   return HR_OK;
 }
 
@@ -171,8 +171,8 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
 
   struct Q8 { std::vector<WorkSeg> seg[8]; uint64_t items[8] = {0, 0, 0, 0, 0, 0, 0, 0}; };
-  Q8 rq, pq;
-  uint64_t rchunks = 0, pchunks = 0;
+  Q8 rq, pq[3];   // path-traced queues by renders per draw (1, 2, 4)
+  uint64_t rchunks = 0, pchunks[3] = {0, 0, 0};
   auto add_segments = [](Q8& Qs, uint64_t& cbase, int q, uint64_t chunks, int tiles) {
     for (int x = 0; x < 8; ++x) {
       const int c0 = (int)(((uint64_t)x + 8u - (cbase & 7u)) & 7u);
@@ -198,18 +198,23 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       add_segments(rq, rchunks, q, (p.e.R + qS[q] - 1) / qS[q], a.tiles);
     } else if (sc->kind == kPT) {
       const uint64_t draws = p.e.streams * p.e.N;
-      add_segments(pq, pchunks, q, (draws + qS[q] - 1) / qS[q], pt_tiles(sc->W, sc->H));
+      const int nr = p.e.A * p.e.NH;
+      const int c = nr == 1 ? 0 : (nr == 2 ? 1 : 2);
+      add_segments(pq[c], pchunks[c], q, (draws + qS[q] - 1) / qS[q], pt_tiles(sc->W, sc->H));
     }
   }
   raster_items_ = pt_items_ = 0;
   for (int x = 0; x < 8; ++x) {
     raster_items_ += rq.items[x];
-    pt_items_ += pq.items[x];
+    for (int c = 0; c < 3; ++c) pt_items_ += pq[c].items[x];
   }
 
   // table layout
-  size_t nrs = 0, nps = 0, nin = 0, nout = 0;
-  for (int x = 0; x < 8; ++x) { nrs += rq.seg[x].size(); nps += pq.seg[x].size(); }
+  size_t nrs = 0, nps[3] = {0, 0, 0}, nin = 0, nout = 0;
+  for (int x = 0; x < 8; ++x) {
+    nrs += rq.seg[x].size();
+    for (int c = 0; c < 3; ++c) nps[c] += pq[c].seg[x].size();
+  }
   for (auto& it : items) {
     nin += (size_t)it.plan.e.n * (it.v ? 2 : 1);
     nout += it.plan.nout;
@@ -220,8 +225,9 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   const size_t o_q = take((size_t)nq * sizeof(BatchQuery));
   const size_t o_off = take((size_t)kNumPhases * (nq + 1) * 8);
   const size_t o_rs = take(std::max<size_t>(nrs, 1) * sizeof(WorkSeg));
-  const size_t o_ps = take(std::max<size_t>(nps, 1) * sizeof(WorkSeg));
-  const size_t o_ctr = take(16 * 8);
+  size_t o_ps[3];
+  for (int c = 0; c < 3; ++c) o_ps[c] = take(std::max<size_t>(nps[c], 1) * sizeof(WorkSeg));
+  const size_t o_ctr = take(32 * 8);
   const size_t o_in = take(nin * 8);
   upload_bytes_ = off;
   const size_t o_out = take(nout * 8);
@@ -250,7 +256,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
     W.ctr = (unsigned long long*)(Dv + o_ctr) + ctr_index;
   };
   fill_queues(T->raster, rq, o_rs, 0);
-  fill_queues(T->pt, pq, o_ps, 8);
+  for (int c = 0; c < 3; ++c) fill_queues(T->pt[c], pq[c], o_ps[c], 8 + 8 * c);
 
   BatchQuery* HQ = (BatchQuery*)(H + o_q);
   double* hin = (double*)(H + o_in);
@@ -344,7 +350,9 @@ void BatchSlot::launches(hipStream_t st, bool time_phases) {
   run("batch_records", [&] { launch_batch_records(st, T, phase_blocks); });
   run("batch_analytic", [&] { launch_batch_analytic(st, T, phase_blocks); });
   run("batch_raster", [&] { launch_batch_raster(st, T, raster_blocks, lds); });
-  run("batch_pt", [&] { launch_batch_pt(st, T, pt_blocks); });
+  run("batch_pt", [&] {
+    for (int c = 0; c < 3; ++c) launch_batch_pt(st, T, 1 << c, pt_blocks[c]);
+  });
   run("batch_reduce", [&] { launch_batch_reduce(st, T, phase_blocks); });
   run("batch_prep", [&] { launch_batch_prep(st, T, phase_blocks); });
   run("batch_accum", [&] { launch_batch_accum(st, T, phase_blocks); });
@@ -587,7 +595,7 @@ hr_status hr_batch_run(hr_batch* b, const hr_query* queries, int count) {
   b->last.raster_items = b->slot.raster_items_;
   b->last.pt_items = b->slot.pt_items_;
   b->last.raster_blocks = b->slot.raster_blocks;
-  b->last.pt_blocks = b->slot.pt_blocks;
+  b->last.pt_blocks = b->slot.pt_blocks[0];
   b->last.workspace_bytes = ws;
   b->last.graph = b->slot.graph_used ? 1 : 0;
   b->last.lds_bytes = (uint64_t)b->slot.lds;

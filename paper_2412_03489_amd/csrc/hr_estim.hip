@@ -381,8 +381,9 @@ __global__ __launch_bounds__(256) void k_batch_sample(const BatchTable* __restri
   const int nq = T->nq;
   const uint64_t* off = T->off + (uint64_t)kPhSample * (nq + 1);
   // the render work queues start empty
-  if (blockIdx.x == 0 && threadIdx.x < 16) {
-    unsigned long long* c = threadIdx.x < 8 ? T->raster.ctr : T->pt.ctr;
+  if (blockIdx.x == 0 && threadIdx.x < 32) {
+    const int set = threadIdx.x >> 3;
+    unsigned long long* c = set == 0 ? T->raster.ctr : T->pt[set - 1].ctr;
     c[threadIdx.x & 7] = 0ull;
   }
   const uint64_t total = off[nq];

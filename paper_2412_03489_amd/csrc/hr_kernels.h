@@ -84,7 +84,8 @@ void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& 
 struct PTScene {
   int W, H, spp, nspheres;
   const float* target;   // H*W*3
-  const float* desc;     // FP32 copy of the scene description
+  const float* desc;     // FP32 copy of the scene description (host)
+  const void* ptc;       // device copy of the tracer's constants (pt_fill_const)
 };
 int pt_tiles(int W, int H);
 int pt_tiles_x(int W);
@@ -167,7 +168,8 @@ struct BatchTable {
   int nq, pad;
   const BatchQuery* q;
   const uint64_t* off;       // [kNumPhases][nq + 1]
-  WorkQueues raster, pt;
+  WorkQueues raster;
+  WorkQueues pt[3];          // path-traced items by renders per draw: 1, 2, 4
 };
 // device-side lookup: the query owning task t of a phase (t < off[nq])
 __device__ __forceinline__ int batch_find(const uint64_t* off, int nq, uint64_t t) {
@@ -198,14 +200,15 @@ void launch_batch_sample(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_records(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_analytic(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_raster(hipStream_t st, const BatchTable* T, int blocks, size_t lds);
-void launch_batch_pt(hipStream_t st, const BatchTable* T, int blocks);
+// path-traced items with nr renders per draw (1, 2 or 4)
+void launch_batch_pt(hipStream_t st, const BatchTable* T, int nr, int blocks);
 void launch_batch_reduce(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_prep(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_accum(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_finalize(hipStream_t st, const BatchTable* T, int blocks);
 // occupancy of the persistent raster kernel (blocks per CU) for a given LDS size
 int batch_raster_blocks_per_cu(size_t lds);
-int batch_pt_blocks_per_cu();
+int batch_pt_blocks_per_cu(int nr);
 // path tracer constants for device-resident scenes
 size_t pt_const_bytes();
 void pt_fill_const(const PTScene& s, void* host_out);

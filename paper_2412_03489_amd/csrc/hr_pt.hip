@@ -46,7 +46,8 @@ __device__ __forceinline__ float dot3(V3 a, V3 b) { return fmaf(a.x, b.x, fmaf(a
 
 struct Placement { V3 light, s0; };
 
-__device__ __forceinline__ V3 sph_c(const PTConst& P, const Placement& pl, int i) {
+template <class Consts>
+__device__ __forceinline__ V3 sph_c(const Consts& P, const Placement& pl, int i) {
   return i == 0 ? pl.s0 : v3(P.sph[i][0], P.sph[i][1], P.sph[i][2]);
 }
 
@@ -65,7 +66,8 @@ __device__ __forceinline__ float hit_sphere(V3 o, V3 d, V3 c, float r) {
 }
 
 // closest hit: -1 none, 0..ns-1 sphere, ns plane, ns+1 light
-__device__ int intersect(const PTConst& P, const Placement& pl, V3 o, V3 d, float& tb) {
+template <class Consts>
+__device__ int intersect(const Consts& P, const Placement& pl, V3 o, V3 d, float& tb) {
   int id = -1;
   float best = 3.0e38f;
   for (int i = 0; i < P.ns; ++i) {
@@ -86,7 +88,8 @@ __device__ int intersect(const PTConst& P, const Placement& pl, V3 o, V3 d, floa
   return id;
 }
 
-__device__ bool occluded(const PTConst& P, const Placement& pl, V3 o, V3 d, float dist) {
+template <class Consts>
+__device__ bool occluded(const Consts& P, const Placement& pl, V3 o, V3 d, float dist) {
   const float tmax = dist - kEps;
   for (int i = 0; i < P.ns; ++i) {
     const float t = hit_sphere(o, d, sph_c(P, pl, i), P.sph[i][3]);
@@ -100,7 +103,8 @@ __device__ bool occluded(const PTConst& P, const Placement& pl, V3 o, V3 d, floa
 }
 
 // Le cos_x cos_l A / (pi d^2) for a uniform light point, visibility included
-__device__ float nee(const PTConst& P, const Placement& pl, V3 o, V3 n, float u1, float u2) {
+template <class Consts>
+__device__ float nee(const Consts& P, const Placement& pl, V3 o, V3 n, float u1, float u2) {
   const V3 y = v3(pl.light.x + (u1 - 0.5f) * P.side, pl.light.y, pl.light.z + (u2 - 0.5f) * P.side);
   const V3 wv = y - o;
   const float d2 = dot3(wv, wv);
@@ -112,7 +116,8 @@ __device__ float nee(const PTConst& P, const Placement& pl, V3 o, V3 n, float u1
   return P.Le * cx * cl * P.side * P.side / d2 / kPiF;
 }
 
-__device__ __forceinline__ void surface(const PTConst& P, const Placement& pl, int id, V3 x, V3& n,
+template <class Consts>
+__device__ __forceinline__ void surface(const Consts& P, const Placement& pl, int id, V3 x, V3& n,
                                         V3& alb) {
   if (id < P.ns) {
     n = (x - sph_c(P, pl, id)) * (1.0f / P.sph[id][3]);
@@ -125,7 +130,8 @@ __device__ __forceinline__ void surface(const PTConst& P, const Placement& pl, i
 
 // radiance of one path; u[0..1] jitter (used by the caller), u[2..3] light
 // sample at hit 1, u[4..5] bounce, u[6..7] light sample at hit 2
-__device__ V3 radiance(const PTConst& P, const Placement& pl, V3 eye, V3 d, const float* u) {
+template <class Consts>
+__device__ V3 radiance(const Consts& P, const Placement& pl, V3 eye, V3 d, const float* u) {
   float t;
   const int id = intersect(P, pl, eye, d, t);
   if (id < 0) return v3(0.f, 0.f, 0.f);
@@ -166,7 +172,8 @@ __device__ __forceinline__ void path_uniforms(uint64_t seed, uint32_t s, uint32_
   u[4] = u01_f(wb.x); u[5] = u01_f(wb.y); u[6] = u01_f(wb.z); u[7] = u01_f(wb.w);
 }
 
-__device__ __forceinline__ V3 camera_dir(const PTConst& P, int x, int y, float jx, float jy) {
+template <class Consts>
+__device__ __forceinline__ V3 camera_dir(const Consts& P, int x, int y, float jx, float jy) {
   const float sx = (2.0f * ((float)x + jx) / (float)P.W - 1.0f) * P.sx_scale;
   const float sy = (1.0f - 2.0f * ((float)y + jy) / (float)P.H) * P.sy_scale;
   const V3 f = v3(P.fwd[0], P.fwd[1], P.fwd[2]);
@@ -184,8 +191,8 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 // One block's work: draws [d0, d0 + nd) of one query on one 16x16 tile,
 // all NR renders of each draw.  Shared by the per-query and the batch kernel.
-template <int NR>
-__device__ __forceinline__ void pt_block(const PTConst& P, const double* __restrict__ theta,
+template <int NR, class Consts>
+__device__ __forceinline__ void pt_block(const Consts& P, const double* __restrict__ theta,
                                          const double* __restrict__ tau,
                                          const double* __restrict__ u,
                                          const float* __restrict__ target, const EstShape& e,
@@ -257,8 +264,14 @@ __device__ __forceinline__ void pt_block(const PTConst& P, const double* __restr
   }
 }
 
+typedef const PTConst __attribute__((address_space(4))) ConstPT;
+
+// The scene's constants are read from device memory through the constant
+// address space: scalar loads on use, and no private copy (a by-value
+// argument passed by reference to the tracing routines would be copied to
+// scratch).
 template <int NR>
-__global__ __launch_bounds__(256) void k_pt_loss(PTConst P, const double* __restrict__ theta,
+__global__ __launch_bounds__(256) void k_pt_loss(const PTConst* ptc, const double* __restrict__ theta,
                                                  const double* __restrict__ tau,
                                                  const double* __restrict__ u,
                                                  const float* __restrict__ target, EstShape e,
@@ -274,6 +287,7 @@ __global__ __launch_bounds__(256) void k_pt_loss(PTConst P, const double* __rest
   const uint64_t total = e.streams * e.N;
   const uint64_t d0 = draw0 + chunk * (uint64_t)S;
   const int nd = (int)min((uint64_t)S, total - d0);
+  ConstPT& P = *(ConstPT*)ptc;
   pt_block<NR>(P, theta, tau, u, target, e, tiles_x, tiles, tile, d0, nd, partial, s_part);
 }
 
@@ -283,13 +297,22 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Persistent path tracer over its eight work queues (same scheme as the
-// persistent rasteriser: item = (query, chunk of S draws, 16x16 tile)).
+// Persistent path tracer over eight work queues (same scheme as the
+// persistent rasteriser: item = (query, chunk of S draws, 16x16 tile)); one
+// kernel per number of renders per draw, so each keeps the register budget of
+// the per-query kernel.  Query constants are read through the constant
+// address space (the batch never writes them), as kernel arguments are.
+typedef const PTConst __attribute__((address_space(4))) ConstPT;
+
+template <int NR>
 __global__ __launch_bounds__(256) void k_batch_pt(const BatchTable* __restrict__ T) {
-  __shared__ float s_part[kPtMaxS * 4][4];
+  __shared__ float s_part[kPtMaxS * NR][4];
   __shared__ unsigned long long s_item;
-  const WorkQueues& W = T->pt;
+  const WorkQueues& W = T->pt[NR == 1 ? 0 : (NR == 2 ? 1 : 2)];
   const int home = blockIdx.x & 7;
+  uint64_t all = 0;
+  for (int x = 0; x < 8; ++x) all += W.items[x];
+  if (all == 0) return;   // nothing of this kind in the batch
   for (int k = 0; k < 8; ++k) {
     const int x = (home + k) & 7;
     const uint64_t nitems = W.items[x];
@@ -303,23 +326,25 @@ __global__ __launch_bounds__(256) void k_batch_pt(const BatchTable* __restrict__
       uint64_t lo = sb, hi = se - 1;
       while (lo < hi) {
         const uint64_t mid = (lo + hi + 1) >> 1;
-        if (W.seg[mid].item0 <= it) lo = mid; else hi = mid - 1;
+        if (uniform64(W.seg[mid].item0) <= it) lo = mid; else hi = mid - 1;
       }
-      const WorkSeg sg = W.seg[lo];
+      const WorkSeg sg = uniform_copy(&W.seg[lo]);
       const BatchQuery& Q = T->q[sg.q];
-      const PTConst& P = *(const PTConst*)Q.ptc;
+      const EstShape e = uniform_copy(&Q.e);
+      const uint64_t qp[4] = {uniform64((uint64_t)Q.theta), uniform64((uint64_t)Q.tau),
+                              uniform64((uint64_t)Q.u), uniform64((uint64_t)Q.pt_target)};
+      float* partial = (float*)uniform64((uint64_t)Q.partial);
+      const int S = __builtin_amdgcn_readfirstlane(Q.pt_S);
+      const int tiles_x = __builtin_amdgcn_readfirstlane(Q.pt_tiles_x);
+      const int tiles = __builtin_amdgcn_readfirstlane(Q.pt_tiles);
+      ConstPT& P = *(ConstPT*)uniform64((uint64_t)Q.ptc);
       const uint64_t l = it - sg.item0;
       const uint64_t chunk = (uint64_t)sg.c0 + 8u * (l / (uint64_t)sg.tiles);
       const int tile = (int)(l % (uint64_t)sg.tiles);
-      const uint64_t d0 = chunk * (uint64_t)Q.pt_S;
-      const int nd = (int)min((uint64_t)Q.pt_S, Q.e.streams * Q.e.N - d0);
-      const int nr = Q.e.A * Q.e.NH;
-      if (nr == 1)
-        pt_block<1>(P, Q.theta, Q.tau, Q.u, Q.pt_target, Q.e, Q.pt_tiles_x, Q.pt_tiles, tile, d0, nd, Q.partial, s_part);
-      else if (nr == 2)
-        pt_block<2>(P, Q.theta, Q.tau, Q.u, Q.pt_target, Q.e, Q.pt_tiles_x, Q.pt_tiles, tile, d0, nd, Q.partial, s_part);
-      else
-        pt_block<4>(P, Q.theta, Q.tau, Q.u, Q.pt_target, Q.e, Q.pt_tiles_x, Q.pt_tiles, tile, d0, nd, Q.partial, s_part);
+      const uint64_t d0 = chunk * (uint64_t)S;
+      const int nd = (int)min((uint64_t)S, e.streams * e.N - d0);
+      pt_block<NR>(P, (const double*)qp[0], (const double*)qp[1], (const double*)qp[2],
+                   (const float*)qp[3], e, tiles_x, tiles, tile, d0, nd, partial, s_part);
     }
   }
 }
@@ -370,7 +395,7 @@ int pt_tiles_x(int W) { return (W + kPtTile - 1) / kPtTile; }
 void launch_pt_loss(hipStream_t st, const EstShape& e, const PTScene& s, const double* theta,
                     const double* tau, const double* u, int S, float* partial) {
   if (S <= 0 || S > kPtMaxS) S = 8;
-  const PTConst P = make_const(s, s.spp);
+  const PTConst* P = (const PTConst*)s.ptc;
   const int tiles_x = (s.W + kPtTile - 1) / kPtTile;
   const int tiles = pt_tiles(s.W, s.H);
   const uint64_t draws = e.streams * e.N;
@@ -409,13 +434,18 @@ void pt_fill_const(const PTScene& s, void* host_out) {
   memcpy(host_out, &P, sizeof(PTConst));
 }
 
-void launch_batch_pt(hipStream_t st, const BatchTable* T, int blocks) {
-  hipLaunchKernelGGL(k_batch_pt, dim3(blocks), dim3(256), 0, st, T);
+void launch_batch_pt(hipStream_t st, const BatchTable* T, int nr, int blocks) {
+  if (nr == 1) hipLaunchKernelGGL(k_batch_pt<1>, dim3(blocks), dim3(256), 0, st, T);
+  else if (nr == 2) hipLaunchKernelGGL(k_batch_pt<2>, dim3(blocks), dim3(256), 0, st, T);
+  else hipLaunchKernelGGL(k_batch_pt<4>, dim3(blocks), dim3(256), 0, st, T);
 }
 
-int batch_pt_blocks_per_cu() {
+int batch_pt_blocks_per_cu(int nr) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pt, 256, 0) != hipSuccess) return 1;
+  hipError_t e = nr == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pt<1>, 256, 0)
+                 : nr == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pt<2>, 256, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pt<4>, 256, 0);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 

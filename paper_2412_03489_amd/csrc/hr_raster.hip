@@ -391,6 +391,9 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restri
   __shared__ unsigned long long s_item;
   const WorkQueues& W = T->raster;
   const int home = blockIdx.x & 7;
+  uint64_t all = 0;
+  for (int x = 0; x < 8; ++x) all += W.items[x];
+  if (all == 0) return;   // nothing of this kind in the batch
   for (int k = 0; k < 8; ++k) {
     const int x = (home + k) & 7;
     const uint64_t nitems = W.items[x];

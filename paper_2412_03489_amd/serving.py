@@ -1,0 +1,196 @@
+"""Serving load: Newton optimisations arriving as a Poisson stream, each a
+closed loop of estimator queries, run either through the continuous-batching
+server (hr_server) or as plain per-query calls served one at a time in
+arrival order.  Both modes issue the same queries (results are the same bits
+either way, so every client follows the same trajectory) and report queries
+per second over the run with p50 / p99 query latency (submission to result
+on the host).
+
+Client step (the Newton step of section "Newton's method"):
+  raster (96 params): gradient, then `cg_iters` HVPs of a conjugate-gradient
+    solve with the Hessian-modification rule (curvature max(|p^T Hp|,
+    floor |p|^2)), step clipped to the trust radius;
+  path-traced (6 params): gradient and full Hessian, eigenvalue-clamped
+    Newton step clipped to the trust radius.
+"""
+from __future__ import annotations
+
+import collections
+import heapq
+import time
+
+import numpy as np
+
+from . import Server, estimate
+
+TRUST = 0.05
+EIG_FLOOR = 1e-3
+
+
+class NewtonClient:
+    """Application-side state of one Newton step (numpy, FP64)."""
+
+    def __init__(self, spec, scene, sigma, N, cg_iters, steps=1):
+        self.spec, self.scene, self.sigma, self.N = spec, scene, sigma, N
+        self.cg_iters, self.steps = cg_iters, steps
+        self.theta = np.array(spec.theta0, dtype=np.float64)
+        self.queries = 0
+        self.step = 0
+        self._start_step()
+
+    def _seed(self):
+        return self.spec.seed * 1000 + self.step
+
+    def _start_step(self):
+        self.g = None
+        self.H = None
+        self.next = ("grad", None)
+
+    def query(self):
+        kind, v = self.next
+        q = dict(scene=self.scene, kind=kind, theta=self.theta, sigma=self.sigma, N=self.N,
+                 seed=self._seed())
+        if v is not None:
+            q["v"] = v
+        return q
+
+    def on_result(self, out):
+        """Consumes a result; returns False when the client is finished."""
+        self.queries += 1
+        kind, _ = self.next
+        if kind == "grad":
+            self.g = np.array(out, dtype=np.float64)
+            if self.spec.scene == "pt":
+                self.next = ("hess", None)
+                return True
+            # conjugate gradients on H d = -g from d = 0
+            self.d = np.zeros_like(self.g)
+            self.r = -self.g
+            self.p = self.r.copy()
+            self.it = 0
+            self.next = ("hvp", self.p.copy())
+            return True
+        if kind == "hess":
+            H = 0.5 * (out + out.T)
+            lam, V = np.linalg.eigh(H)
+            lam = np.maximum(np.abs(lam), EIG_FLOOR)
+            d = -V @ ((V.T @ self.g) / lam)
+            return self._apply(d)
+        # hvp
+        Hp = np.array(out, dtype=np.float64)
+        pp = float(self.p @ self.p)
+        kappa = max(abs(float(self.p @ Hp)), EIG_FLOOR * pp)
+        rr = float(self.r @ self.r)
+        alpha = rr / kappa
+        self.d = self.d + alpha * self.p
+        self.r = self.r - alpha * Hp
+        self.it += 1
+        rr_new = float(self.r @ self.r)
+        if self.it >= self.cg_iters or np.linalg.norm(self.d) >= TRUST or rr_new == 0.0:
+            return self._apply(self.d)
+        self.p = self.r + (rr_new / rr) * self.p
+        self.next = ("hvp", self.p.copy())
+        return True
+
+    def _apply(self, d):
+        nd = np.linalg.norm(d)
+        if nd > TRUST:
+            d = d * (TRUST / nd)
+        self.theta = self.theta + d
+        self.step += 1
+        if self.step >= self.steps:
+            return False
+        self._start_step()
+        return True
+
+
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else float("nan")
+
+
+def _summary(lat_ms, t_total, nq, extra=None):
+    out = {"queries": nq, "seconds": t_total, "queries_per_s": nq / t_total,
+           "p50_ms": _pct(lat_ms, 50), "p99_ms": _pct(lat_ms, 99),
+           "mean_ms": float(np.mean(lat_ms)) if lat_ms else float("nan")}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def make_clients(specs, scenes, sigma, N, cg_iters, steps=1):
+    return [NewtonClient(s, scenes[s.scene], sigma[s.scene], N[s.scene], cg_iters, steps)
+            for s in specs]
+
+
+def run_served(ctx, clients, slots=2, max_batch=64, memory_bytes=16 << 30, use_graph=True):
+    """All clients through one continuous-batching server."""
+    srv = Server(ctx, slots=slots, max_batch=max_batch, memory_bytes=memory_bytes,
+                 use_graph=use_graph)
+    arrivals = collections.deque(sorted(clients, key=lambda c: c.spec.arrival))
+    live = {}
+    lat = []
+    sizes = []
+    t0 = time.perf_counter()
+
+    def submit(c, ts):
+        q = c.query()
+        t = srv.submit(q.pop("scene"), q.pop("kind"), q.pop("theta"), q.pop("sigma"),
+                       q.pop("N"), q.pop("seed"), v=q.pop("v", None))
+        live[t] = (c, ts)
+
+    while arrivals or live:
+        now = time.perf_counter() - t0
+        while arrivals and arrivals[0].spec.arrival <= now:
+            c = arrivals.popleft()
+            submit(c, t0 + c.spec.arrival)
+        wait = -1.0 if not arrivals else max(0.0, (arrivals[0].spec.arrival - now) * 1e3)
+        if not live:
+            time.sleep(wait / 1e3)
+            continue
+        t = srv.wait_any(timeout_ms=wait)
+        if t is None:
+            continue
+        out, st = srv.wait(t)
+        c, ts = live.pop(t)
+        tn = time.perf_counter()
+        lat.append((tn - ts) * 1e3)
+        sizes.append(st["batch_size"])
+        if c.on_result(out):
+            submit(c, tn)
+    total = time.perf_counter() - t0
+    s = srv.stats()
+    srv.close()
+    return _summary(lat, total, len(lat), {"batches": s["batches"],
+                                           "mean_batch": s["mean_batch"],
+                                           "slots": slots, "max_batch": max_batch})
+
+
+def run_plain(ctx, clients):
+    """The same clients, each query a plain single-query call, served one at a
+    time in arrival order."""
+    arrivals = collections.deque(sorted(clients, key=lambda c: c.spec.arrival))
+    queue = []   # (submission time, order, client): served oldest first
+    order = 0
+    lat = []
+    t0 = time.perf_counter()
+    while arrivals or queue:
+        now = time.perf_counter() - t0
+        while arrivals and arrivals[0].spec.arrival <= now:
+            c = arrivals.popleft()
+            heapq.heappush(queue, (t0 + c.spec.arrival, order, c))
+            order += 1
+        if not queue:
+            time.sleep(max(0.0, arrivals[0].spec.arrival - now))
+            continue
+        ts, _, c = heapq.heappop(queue)
+        q = c.query()
+        kind = q.pop("kind")
+        out = estimate(kind, q.pop("scene"), q.pop("theta"), q.pop("sigma"), q.pop("N"),
+                       q.pop("seed"), v=q.pop("v", None))
+        tn = time.perf_counter()
+        lat.append((tn - ts) * 1e3)
+        if c.on_result(out):
+            heapq.heappush(queue, (tn, order, c))
+            order += 1
+    total = time.perf_counter() - t0
+    return _summary(lat, total, len(lat))

@@ -21,6 +21,8 @@ light scene):
                       square light), 4 spp, theta = (light xyz, sphere-0 xyz),
                       sigma 0.05, N 8192, full 6x6 Hessian.
 * ``uneven``       -- 64 independent disk scenes of uneven size and sample budget.
+* ``serving_clients`` -- Poisson arrivals of Newton optimisations over a 50/50 mix of
+                      the ``disks32`` and ``pt_spheres`` scenes.
 """
 from __future__ import annotations
 
@@ -174,3 +176,35 @@ def uneven(count: int = 64, base_seed: int = 1000):
             theta_star=_f32(ts), theta0=_f32(t0.reshape(-1)), sigma=0.02, N=N,
             seed=base_seed + i, v=_f32(v), kinds=(kind,)))
     return out
+
+
+@dataclass
+class ServingClient:
+    """One Newton optimisation arriving at a server: which scene, where it
+    starts, its draws' seed and its arrival time (seconds after the start)."""
+    scene: str               # "raster" (disks32, 96 params) or "pt" (pt_spheres, 6 params)
+    theta0: np.ndarray
+    seed: int
+    arrival: float
+
+
+def serving_clients(count: int = 256, rate: float = 512.0, base_seed: int = 2000):
+    """Poisson arrivals (rate per second) of `count` Newton optimisations over a
+    50/50 mix of the 96-parameter raster scene and the 6-parameter path-traced
+    scene; each starts at a random perturbation of its scene's initial theta."""
+    g = np.random.default_rng(base_seed)
+    gaps = g.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    r0 = disks32().theta0.astype(np.float64)
+    p0 = pt_spheres().theta0.astype(np.float64)
+    out = []
+    for i in range(count):
+        if i % 2 == 0:
+            th = r0 + g.uniform(-0.01, 0.01, size=r0.shape)
+            th[2::3] = np.maximum(th[2::3], 0.03)
+            out.append(ServingClient("raster", th, base_seed + i, float(t[i])))
+        else:
+            out.append(ServingClient("pt", p0 + g.normal(0.0, 0.05, size=6), base_seed + i,
+                                     float(t[i])))
+    return out
+
