@@ -163,22 +163,25 @@ def serving_section(P, ctx, args):
     scenes = {"raster": sr, "pt": sp}
     sigma = {"raster": wr.sigma, "pt": wp.sigma}
     N = {"raster": args.serving_n_raster, "pt": args.serving_n_pt}
-    specs = WL.serving_clients(args.serving_clients, rate=args.serving_rate)
     # warm both paths
     warm = WL.serving_clients(4, rate=1e6, base_seed=99)
     SV.run_plain(ctx, SV.make_clients(warm, scenes, sigma, N, args.serving_cg))
     SV.run_served(ctx, SV.make_clients(warm, scenes, sigma, N, args.serving_cg))
-    log(f"bench: serving {len(specs)} clients, plain")
-    plain = SV.run_plain(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
-    log("bench: serving, continuous batching")
-    served = SV.run_served(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
+    rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+    out = {"clients": args.serving_clients,
+           "draws": {"raster_grad_hvp": N["raster"], "pt_grad_hess": N["pt"]},
+           "cg_iters": args.serving_cg}
+    for label, rate in (("saturated", args.serving_rate), ("moderate", args.serving_rate_low)):
+        specs = WL.serving_clients(args.serving_clients, rate=rate)
+        log(f"bench: serving {len(specs)} clients at {rate}/s, plain")
+        plain = SV.run_plain(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
+        log(f"bench: serving {len(specs)} clients at {rate}/s, continuous batching")
+        served = SV.run_served(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
+        out[label] = {"arrival_rate_per_s": rate, "plain": rnd(plain), "served": rnd(served),
+                      "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
     sr.close()
     sp.close()
-    rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
-    return {"clients": len(specs), "arrival_rate_per_s": args.serving_rate,
-            "draws": {"raster_hvp_grad": N["raster"], "pt_grad_hess": N["pt"]},
-            "cg_iters": args.serving_cg, "plain": rnd(plain), "served": rnd(served),
-            "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
+    return out
 
 
 def main():
@@ -198,6 +201,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serving-clients", type=int, default=256)
     ap.add_argument("--serving-rate", type=float, default=512.0)
+    ap.add_argument("--serving-rate-low", type=float, default=96.0)
     ap.add_argument("--serving-n-raster", type=int, default=16384)
     ap.add_argument("--serving-n-pt", type=int, default=2048)
     ap.add_argument("--serving-cg", type=int, default=4)

@@ -82,8 +82,8 @@ class BatchReport(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("slots", C.c_int), ("max_batch", C.c_int), ("memory_bytes", C.c_uint64),
-                ("use_graph", C.c_int), ("autotune", C.c_int)]
+    _fields_ = [("slots", C.c_int), ("max_batch", C.c_int), ("max_batch_ms", C.c_double),
+                ("memory_bytes", C.c_uint64), ("use_graph", C.c_int), ("autotune", C.c_int)]
 
 
 class QueryStats(C.Structure):
@@ -547,10 +547,10 @@ def tuned(ctx, scene):
 class Server:
     """Continuous-batching server (hr_server)."""
 
-    def __init__(self, ctx, slots=2, max_batch=64, memory_bytes=0, use_graph=True,
-                 autotune=False):
-        o = ServerOpts(int(slots), int(max_batch), int(memory_bytes), 1 if use_graph else 0,
-                       1 if autotune else 0)
+    def __init__(self, ctx, slots=4, max_batch=64, max_batch_ms=4.0, memory_bytes=0,
+                 use_graph=True, autotune=False):
+        o = ServerOpts(int(slots), int(max_batch), float(max_batch_ms), int(memory_bytes),
+                       1 if use_graph else 0, 1 if autotune else 0)
         h = C.c_void_p()
         _check(lib().hr_server_create(ctx.h, C.byref(o), C.byref(h)))
         self.ctx, self.h = ctx, h

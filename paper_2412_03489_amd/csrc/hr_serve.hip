@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -31,9 +32,25 @@ namespace {
 constexpr uint64_t kDefaultServerMemory = 8ull << 30;
 constexpr size_t kTableReserve = 4u << 20;
 
+// Predicted device milliseconds of one query (batch formation only; results
+// never depend on it): rasterised pixel-renders at ~2 per ps, path-traced
+// pixel samples at ~60 per ns, lobe-sum terms at ~200 per ns, plus a fixed
+// 20 us of small launches.
+double predict_ms(const QueryPlan& p) {
+  const hr_scene* sc = p.sc;
+  const double R = (double)p.e.R;
+  double ms = 0.02;
+  if (sc->kind == kDisks) ms += R * sc->W * sc->H / 2.0e9;
+  else if (sc->kind == kPT) ms += R * sc->W * sc->H * sc->spp / 6.0e7;
+  else ms += R * p.e.n * p.e.n / 1.0e9;
+  ms += (double)p.e.streams * (double)p.e.N * (double)p.e.nout / 2.0e8;
+  return ms;
+}
+
 struct Ticket {
   uint64_t id = 0;
   BatchItem item;
+  double cost_ms = 0.0;   // predicted device time
   std::vector<double> theta, v, result;
   hr_query_stats stats{};
   int state = 0;   // 0 waiting, 1 on the device, 2 done
@@ -92,12 +109,15 @@ struct hr_server {
   void launch(int i) {
     Flight& f = flights[i];
     size_t ws = 0;
+    double work = 0.0;
+    const double cap = opts.max_batch_ms > 0.0 ? opts.max_batch_ms : 1e300;
     while (!waiting.empty() && (int)f.items.size() < opts.max_batch) {
       Ticket* t = waiting.front();
       const size_t need = align256(t->item.plan.total);
-      if (!f.items.empty() && ws + need > capacity) break;
+      if (!f.items.empty() && (ws + need > capacity || work + t->cost_ms > cap)) break;
       waiting.pop_front();
       ws += need;
+      work += t->cost_ms;
       f.items.push_back(t->item);
       f.tickets.push_back(t);
     }
@@ -155,8 +175,9 @@ extern "C" {
 
 void hr_server_opts_default(hr_server_opts* o) {
   if (!o) return;
-  o->slots = 2;
+  o->slots = 4;
   o->max_batch = 64;
+  o->max_batch_ms = 4.0;
   o->memory_bytes = 0;
   o->use_graph = 1;
   o->autotune = 0;
@@ -169,6 +190,7 @@ hr_status hr_server_create(hr_ctx* ctx, const hr_server_opts* opts, hr_server** 
   if (opts) o = *opts;
   if (o.slots < 1 || o.slots > 8) return fail(HR_EINVAL, "slots must be 1..8");
   if (o.max_batch < 1 || o.max_batch > 4096) return fail(HR_EINVAL, "max_batch must be 1..4096");
+  if (std::isnan(o.max_batch_ms)) return fail(HR_EINVAL, "max_batch_ms is NaN");
   uint64_t mem = o.memory_bytes ? o.memory_bytes : kDefaultServerMemory;
   if (mem > ctx->budget) mem = ctx->budget;
   auto s = std::make_unique<hr_server>();
@@ -228,6 +250,7 @@ hr_status hr_submit(hr_server* s, const hr_query* q, uint64_t* ticket) {
   }
   t->result.assign(t->item.plan.nout, 0.0);
   t->item.out = t->result.data();
+  t->cost_ms = predict_ms(t->item.plan);
   std::lock_guard<std::mutex> lk(s->mu);
   t->id = s->next_id++;
   t->item.ticket = t->id;

@@ -122,10 +122,11 @@ def make_clients(specs, scenes, sigma, N, cg_iters, steps=1):
             for s in specs]
 
 
-def run_served(ctx, clients, slots=2, max_batch=64, memory_bytes=16 << 30, use_graph=True):
+def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_bytes=16 << 30,
+               use_graph=True):
     """All clients through one continuous-batching server."""
-    srv = Server(ctx, slots=slots, max_batch=max_batch, memory_bytes=memory_bytes,
-                 use_graph=use_graph)
+    srv = Server(ctx, slots=slots, max_batch=max_batch, max_batch_ms=max_batch_ms,
+                 memory_bytes=memory_bytes, use_graph=use_graph)
     arrivals = collections.deque(sorted(clients, key=lambda c: c.spec.arrival))
     live = {}
     lat = []
@@ -162,7 +163,8 @@ def run_served(ctx, clients, slots=2, max_batch=64, memory_bytes=16 << 30, use_g
     srv.close()
     return _summary(lat, total, len(lat), {"batches": s["batches"],
                                            "mean_batch": s["mean_batch"],
-                                           "slots": slots, "max_batch": max_batch})
+                                           "slots": slots, "max_batch": max_batch,
+                                           "max_batch_ms": max_batch_ms})
 
 
 def run_plain(ctx, clients):

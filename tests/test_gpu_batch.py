@@ -259,3 +259,8 @@ def test_server_admission_by_memory(P, ctx, scenes):
     ref = P.estimate("grad", sc, w.theta0, w.sigma, 3000, 103)
     assert np.array_equal(outs[3][0], ref)
     srv.close()
+    # a predicted-time cap below any query's cost: one query per batch
+    srv = P.Server(ctx, slots=2, max_batch=64, max_batch_ms=1e-9, memory_bytes=64 << 20)
+    ts = [srv.submit(sc, "grad", w.theta0, w.sigma, 64, 200 + i) for i in range(5)]
+    assert all(srv.wait(t)[1]["batch_size"] == 1 for t in ts)
+    srv.close()
