@@ -39,8 +39,8 @@ FLOP_PER_PIXEL = 12.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this SHA-256; reported as null once the source has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 274287888
-TRAFFIC_SOURCE_SHA256 = "26c254cacdec508817dc37aac572635f4b81768273be7dee047f97ac7e5a374f"
+TRAFFIC_BYTES_PER_LAUNCH = 466549068
+TRAFFIC_SOURCE_SHA256 = "7d2adf4e67afb8c8adbd1a5182293aad9c1ac6b50491cea15e076696938a6c54"
 
 
 def raster_traffic():
@@ -184,38 +184,11 @@ def serving_section(P, ctx, args):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--hvp-queries", type=int, default=30)
-    ap.add_argument("--cpu-draws", type=int, default=24576)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--samples-per-block", type=int, default=0)
-    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
-                    help="after the run, one device-to-device copy of this many MiB "
-                         "(a kernel of known traffic for scaling memory counters)")
-    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
-    ap.add_argument("--uneven-reps", type=int, default=3)
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
-    ap.add_argument("--serving-clients", type=int, default=256)
-    ap.add_argument("--serving-rate", type=float, default=512.0)
-    ap.add_argument("--serving-rate-low", type=float, default=96.0)
-    ap.add_argument("--serving-n-raster", type=int, default=16384)
-    ap.add_argument("--serving-n-pt", type=int, default=2048)
-    ap.add_argument("--serving-cg", type=int, default=4)
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
-    import paper_2412_03489_amd as P
+def main_section(P, ctx, args):
+    """The headline workload: Newton-CG steps of the 32-disk scene, single-HVP
+    latency and the raster kernel's roofline."""
     import workloads as WL
-
     w = WL.disks32()
-    ctx = P.Context(0)
     tgt = render_target_on_gpu(P, ctx, w)
     sc = P.Scene.disks(ctx, w.W, w.H, w.C, w.colors, tgt, radius=w.radius, ppd=w.ppd)
     th0 = ctx.alloc(8 * w.n)
@@ -311,14 +284,60 @@ def main():
     for b in (th0, th, v, out):
         b.free()
     sc.close()
-    if not args.no_uneven:
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--hvp-queries", type=int, default=30)
+    ap.add_argument("--cpu-draws", type=int, default=24576)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--samples-per-block", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="after the run, one device-to-device copy of this many MiB "
+                         "(a kernel of known traffic for scaling memory counters)")
+    ap.add_argument("--sections", default="main,uneven,serving",
+                    help="comma list of main, uneven, serving (default: all)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
+    ap.add_argument("--uneven-reps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serving-clients", type=int, default=256)
+    ap.add_argument("--serving-rate", type=float, default=512.0)
+    ap.add_argument("--serving-rate-low", type=float, default=96.0)
+    ap.add_argument("--serving-n-raster", type=int, default=16384)
+    ap.add_argument("--serving-n-pt", type=int, default=2048)
+    ap.add_argument("--serving-cg", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_2412_03489_amd as P
+    import workloads as WL
+
+    sections = set(args.sections.split(","))
+    if args.no_uneven:
+        sections.discard("uneven")
+    if args.no_serving:
+        sections.discard("serving")
+    ctx = P.Context(0)
+    if "main" in sections:
+        line = main_section(P, ctx, args)
+    else:   # a diagnostic run of the other sections only (for profiling)
+        line = {"metric": METRIC, "value": None, "unit": "Mpix/s", "n_gpus": 1,
+                "note": "headline section skipped (--sections)"}
+    if "uneven" in sections:
         line["uneven_batch"] = uneven_section(P, ctx, args.uneven_reps)
-    if not args.no_serving:
+    if "serving" in sections:
         line["serving"] = serving_section(P, ctx, args)
     ctx.close()
-    if not args.no_cpu:
+    if not args.no_cpu and "main" in sections:
         log(f"bench: CPU oracle baseline at N={args.cpu_draws}")
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_draws)
+        line["cpu_baseline"] = cpu_baseline(WL.disks32(), args.cpu_draws)
     print(json.dumps(line), flush=True)
 
 
