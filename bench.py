@@ -12,9 +12,12 @@ Newton step).  A step = hr_newton_cg_step_dev on device-resident theta:
 metric: perturbed Mpix/s = (renders actually made) * 65536 pixels / time.
 Also reported: p50/p99 latency of single HVP queries, the roofline of the
 dominant kernel (raster + MSE) from HIP events on its stream, and the CPU
-oracle on a bounded sample of the same workload.
+oracle on a bounded sample of the same workload; then, on the same line,
+`other_workloads` (one-disk gradient + Hessian, path-traced 6x6 Hessian),
+`uneven_batch` (64 uneven instances: plain calls vs one batch) and `serving`
+(Poisson-arriving Newton optimisations: server vs plain calls).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections ...]
 """
 from __future__ import annotations
 
@@ -287,6 +290,47 @@ def main_section(P, ctx, args):
     return line
 
 
+def configs_section(P, ctx, reps):
+    """The other workloads of the estimator: the one-disk gradient + Hessian
+    (64x64, N = 4096) and the path-traced full 6x6 Hessian (128x128, 4 spp,
+    N = 8192), each timed as host call to result."""
+    import workloads as WL
+    out = {}
+    w = WL.one_disk()
+    sc = P.Scene.disks(ctx, w.W, w.H, w.C, w.colors, render_target_on_gpu(P, ctx, w),
+                       radius=w.radius, ppd=w.ppd)
+
+    def one_disk():
+        P.estimate("grad", sc, w.theta0, w.sigma, w.N, w.seed)
+        P.estimate("hess", sc, w.theta0, w.sigma, w.N, w.seed)
+
+    one_disk()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one_disk()
+    dt = (time.perf_counter() - t0) / reps
+    renders = 2 * P.n_renders("grad", w.n, w.N)
+    out["one_disk_grad_hess"] = {"ms": round(dt * 1e3, 3), "renders": renders,
+                                 "Mpix_per_s": round(renders * w.pixels / dt / 1e6, 1)}
+    sc.close()
+    wp = WL.pt_spheres()
+    s0 = P.Scene.pt(ctx, wp.W, wp.H, wp.spp, wp.desc, np.zeros((wp.H, wp.W, 3), np.float32))
+    tp = s0.render(wp.theta_star, seed=wp.target_seed, s=0, spp=wp.target_spp)
+    s0.close()
+    sp = P.Scene.pt(ctx, wp.W, wp.H, wp.spp, wp.desc, tp)
+    P.estimate("hess", sp, wp.theta0, wp.sigma, wp.N, wp.seed)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.estimate("hess", sp, wp.theta0, wp.sigma, wp.N, wp.seed)
+    dt = (time.perf_counter() - t0) / reps
+    renders = P.n_renders("hess", wp.n, wp.N)
+    out["pt_spheres_hessian"] = {"ms": round(dt * 1e3, 3), "renders": renders,
+                                 "Mpix_per_s": round(renders * wp.pixels / dt / 1e6, 1),
+                                 "paths_per_s": round(renders * wp.pixels * wp.spp / dt, 1)}
+    sp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,8 +343,8 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB "
                          "(a kernel of known traffic for scaling memory counters)")
-    ap.add_argument("--sections", default="main,uneven,serving",
-                    help="comma list of main, uneven, serving (default: all)")
+    ap.add_argument("--sections", default="main,configs,uneven,serving",
+                    help="comma list of main, configs, uneven, serving (default: all)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--uneven-reps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
@@ -330,6 +374,8 @@ def main():
     else:   # a diagnostic run of the other sections only (for profiling)
         line = {"metric": METRIC, "value": None, "unit": "Mpix/s", "n_gpus": 1,
                 "note": "headline section skipped (--sections)"}
+    if "configs" in sections:
+        line["other_workloads"] = configs_section(P, ctx, 5)
     if "uneven" in sections:
         line["uneven_batch"] = uneven_section(P, ctx, args.uneven_reps)
     if "serving" in sections:
