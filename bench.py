@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Hessian-estimator throughput (perturbed Mpix/s) + p50/p99 HVP-query latency"
 PEAK_FP32_TFLOPS = 157.3          # MI355X fp32 vector (published)
+PEAK_HBM_GBS = 8000.0             # MI355X HBM3E (published)
 # algorithmic work per perturbed pixel of the bbox-culled rasteriser + loss:
 # 9 FLOP for the 3-channel squared error, 5 FLOP per disk test times the
 # 0.593 disks whose bounding box holds an average pixel (32 disks, E[r^2]).
@@ -42,8 +43,8 @@ FLOP_PER_PIXEL = 12.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this SHA-256; reported as null once the source has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 466549068
-TRAFFIC_SOURCE_SHA256 = "7d2adf4e67afb8c8adbd1a5182293aad9c1ac6b50491cea15e076696938a6c54"
+TRAFFIC_BYTES_PER_LAUNCH = 467317673
+TRAFFIC_SOURCE_SHA256 = "9c7a39411d12847040118d0ae4fc7e90c958e2a41b12641c7924c7d5e0350f01"
 
 
 def raster_traffic():
@@ -225,6 +226,7 @@ def main_section(P, ctx, args):
     ctx.synchronize()
     dt = time.perf_counter() - t0
     launches, raster_ms = ctx.kernel_stats("raster_loss")
+    red_launches, red_ms = ctx.kernel_stats("tile_reduce")
     ctx.enable_timing(False)
     log(f"bench: {args.steps} steps in {dt:.3f} s, raster launches {launches}")
 
@@ -284,6 +286,18 @@ def main_section(P, ctx, args):
                      "flop_per_pixel": FLOP_PER_PIXEL},
         "cpu_baseline": None,
     }
+    # the loss pass: per render, its wave-tile partials are read (4 B each)
+    # and one FP64 loss written -- HBM-bound, against the 8 TB/s peak
+    subs = ((w.W + 15) // 16) * ((w.H + 15) // 16)
+    red_bytes = renders * (subs * 4 + 8)
+    red_gbs = red_bytes / (red_ms * 1e-3) / 1e9 if red_ms > 0 else None
+    line["loss_pass"] = {"bound": "hbm", "kernel": "k_tile_reduce",
+                         "achieved": round(red_gbs, 1) if red_gbs else None,
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(red_gbs / PEAK_HBM_GBS, 4) if red_gbs else None,
+                         "avg_launch_ms": round(red_ms / max(red_launches, 1), 4),
+                         "launches": int(red_launches),
+                         "bytes_per_render": subs * 4 + 8}
     for b in (th0, th, v, out):
         b.free()
     sc.close()

@@ -112,7 +112,9 @@ hr_status hr_ctx_synchronize(hr_ctx* ctx);
 /* Kernel timing: when enabled, HIP events bracket every launch of the named
  * kernel on the stream it is launched on; stats report launch count and the
  * summed event time in milliseconds.  Names: "raster_loss", "pt_loss",
- * "sample", "records", "accumulate". */
+ * "tile_reduce", "sample", "records", "accumulate"; batches (eager runs):
+ * "batch_sample", "batch_records", "batch_analytic", "batch_raster",
+ * "batch_pt", "batch_reduce", "batch_prep", "batch_accum", "batch_finalize". */
 hr_status hr_ctx_enable_timing(hr_ctx* ctx, int enable);
 hr_status hr_ctx_kernel_stats(hr_ctx* ctx, const char* name, uint64_t* launches,
                               double* total_ms);

@@ -202,11 +202,15 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
     timed(ctx, "records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
     RasterExact ex{d_theta, tau, u, sc->radius, e.n, sc->ppd, e.A, e.NH, e.h};
     timed(ctx, "raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, o.raster_tile, ex, partial); });
-    launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
+    timed(ctx, "tile_reduce", [&] {
+      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
+    });
   } else if (sc->kind == kPT) {
     PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
     timed(ctx, "pt_loss", [&] { launch_pt_loss(s, e, ps, d_theta, tau, u, spb, partial); });
-    launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f);
+    timed(ctx, "tile_reduce", [&] {
+      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f);
+    });
   } else {
     AnalyticScene as{sc->kind == kQuad ? 0 : 1, sc->n, sc->A, sc->b, sc->c, sc->s1};
     launch_analytic(s, e, as, d_theta, tau, u, f);

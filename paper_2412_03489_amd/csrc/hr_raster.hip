@@ -322,27 +322,6 @@ __global__ __launch_bounds__(256) void k_raster_loss(RasterQuery a, uint64_t chu
   raster_block<C, kOneGroup, RasterQuery>(a, tile, r0, nr, smem);
 }
 
-// fixed-order FP64 sum of the tile partials of render r, by one wave
-__device__ __forceinline__ void reduce_render(const float* __restrict__ partial, int tiles,
-                                              double inv_count, uint64_t r,
-                                              double* __restrict__ f) {
-  const int lane = threadIdx.x & 63;
-  double acc = 0.0;
-  for (int t = lane; t < tiles; t += 64) acc += (double)partial[r * (uint64_t)tiles + t];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) f[r] = acc * inv_count;
-}
-
-// one wave per render
-__global__ void k_tile_reduce(const float* __restrict__ partial, uint64_t R, int tiles,
-                              double inv_count, double* __restrict__ f) {
-  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  for (uint64_t r = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < R;
-       r += waves)
-    reduce_render(partial, tiles, inv_count, r, f);
-}
-
 // single render at theta, coverage in FP64 (the definition)
 __global__ void k_render_disks(RasterExact ex, const float* __restrict__ colors, int W, int H,
                                int C, int D, float* __restrict__ image) {
@@ -434,21 +413,6 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restri
   }
 }
 
-// tile partials -> per-render loss for raster and path-traced queries
-__global__ __launch_bounds__(256) void k_batch_reduce(const BatchTable* __restrict__ T) {
-  const int nq = T->nq;
-  const uint64_t* off = T->off + (uint64_t)kPhReduce * (nq + 1);
-  const uint64_t total = off[nq];
-  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int q = batch_find(off, nq, t);
-    const BatchQuery& Q = T->q[q];
-    const uint64_t b = (t - off[q]) * (uint64_t)kBatchRenders;
-    const uint64_t end = umin64(Q.e.R, b + kBatchRenders);
-    for (uint64_t r = b + (threadIdx.x >> 6); r < end; r += (blockDim.x >> 6))
-      reduce_render(Q.partial, Q.part_stride, Q.inv_count, r, Q.f);
-  }
-}
-
 inline unsigned grid_for(uint64_t total, int block) {
   uint64_t g = (total + block - 1) / block;
   return (unsigned)(g > 65536u * 16u ? 65536u * 16u : (g == 0 ? 1 : g));
@@ -524,13 +488,6 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
   }
 }
 
-void launch_tile_reduce(hipStream_t st, const float* partial, uint64_t R, int tiles,
-                        double inv_count, double* f) {
-  const uint64_t blocks = (R + 3) / 4;
-  hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)umin64(blocks, 1u << 20)), dim3(256), 0, st,
-                     partial, R, tiles, inv_count, f);
-}
-
 void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& ex, float* image) {
   hipLaunchKernelGGL(k_render_disks, dim3((s.W + 63) / 64, s.H), dim3(64), 0, st, ex, s.colors,
                      s.W, s.H, s.C, s.D, image);
@@ -541,9 +498,6 @@ void launch_batch_records(hipStream_t st, const BatchTable* T, int blocks) {
 }
 void launch_batch_raster(hipStream_t st, const BatchTable* T, int blocks, size_t lds) {
   hipLaunchKernelGGL(k_batch_raster, dim3(blocks), dim3(256), lds, st, T);
-}
-void launch_batch_reduce(hipStream_t st, const BatchTable* T, int blocks) {
-  hipLaunchKernelGGL(k_batch_reduce, dim3(blocks), dim3(256), 0, st, T);
 }
 int batch_raster_blocks_per_cu(size_t lds) {
   int nb = 0;
