@@ -71,6 +71,18 @@ def corner_exact(theta, theta_star, W, H_, sigma):
 
 
 # ----------------------------------------------------------------- one disk
+def disk_coverage_prob(theta, r, W, H_, sigma):
+    """q_p = P(|c_p - tau| < r), c_p = theta - x_p, for every pixel centre x_p
+    (row-major): a noncentral chi-square CDF with 2 degrees of freedom."""
+    theta = np.asarray(theta, float)
+    xs = (np.arange(W) + 0.5) / W
+    ys = (np.arange(H_) + 0.5) / H_
+    X, Y = np.meshgrid(xs, ys)
+    cx = (theta[0] - X).ravel()
+    cy = (theta[1] - Y).ravel()
+    return stats.ncx2.cdf(r * r / sigma**2, 2, (cx * cx + cy * cy) / sigma**2)
+
+
 def disk_exact(theta, theta_star, r, W, H_, sigma, nodes=2048):
     """One white disk of radius r on black, single channel.  Pixel p is covered
     iff tau lies in the disk B(c_p, r), c_p = theta - x_p, so

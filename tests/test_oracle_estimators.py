@@ -442,3 +442,53 @@ def test_optimiser_recompute_reuses_alpha(orc, quad):
                           N_loss=2000)
     assert tr[1, 1] == tr[0, 1] and tr[2, 1] == tr[0, 1]
     assert tr[4, 1] == tr[3, 1] and tr[5, 1] == tr[3, 1]
+
+
+# ------------------------------------- the exact references, pinned twice
+def test_disk_coverage_by_dense_quadrature():
+    """The one-disk reference's coverage probabilities (noncentral chi-square)
+    against direct 2-D quadrature of the Gaussian over the disk, at pixels
+    inside, on and outside the disk's edge."""
+    from scipy import integrate
+    w = WL.one_disk()
+    th, r, sg = w.theta0, 0.2, w.sigma
+    q = E.disk_coverage_prob(th, r, w.W, w.H, sg)
+    g = np.random.default_rng(4)
+    picks = g.choice(w.W * w.H, size=24, replace=False)
+    for p in picks:
+        y, x = divmod(int(p), w.W)
+        c = np.array([th[0] - (x + 0.5) / w.W, th[1] - (y + 0.5) / w.H])
+        dens = lambda b, a: np.exp(-((c[0] - a) ** 2 + (c[1] - b) ** 2) / (2 * sg * sg)) / (2 * math.pi * sg * sg)
+        val, err = integrate.dblquad(dens, -r, r, lambda a: -math.sqrt(r * r - a * a),
+                                     lambda a: math.sqrt(r * r - a * a), epsabs=1e-12, epsrel=1e-10)
+        assert abs(val - q[p]) < 1e-8 + 1e-7 * abs(val), (x, y, val, q[p])
+
+
+@pytest.mark.parametrize("scene", ["disk", "corner"])
+def test_exact_derivatives_match_finite_differences(scene):
+    """The analytic gradient and Hessian of each 2-parameter reference (contour
+    integrals for the disk, Gaussian CDF products for the corner) against
+    central finite differences of its smoothed loss F."""
+    if scene == "disk":
+        w = WL.one_disk()
+        th0 = np.array(w.theta0)
+        Ff = lambda t: E.disk_exact(t, w.theta_star, 0.2, w.W, w.H, w.sigma)
+        d = 1e-4
+    else:
+        th0 = np.array([0.5, 0.52])
+        Ff = lambda t: E.corner_exact(t, np.array([0.55, 0.45]), 32, 32, 0.06)
+        d = 1e-4
+    F0, g, H = Ff(th0)
+    e = np.eye(2)
+    gfd = np.array([(Ff(th0 + d * e[i])[0] - Ff(th0 - d * e[i])[0]) / (2 * d) for i in range(2)])
+    Hfd = np.zeros((2, 2))
+    for i in range(2):
+        for j in range(2):
+            Hfd[i, j] = (Ff(th0 + d * e[i] + d * e[j])[0] - Ff(th0 + d * e[i] - d * e[j])[0]
+                         - Ff(th0 - d * e[i] + d * e[j])[0] + Ff(th0 - d * e[i] - d * e[j])[0]) / (4 * d * d)
+    # gradients of the FD of F against the analytic derivatives
+    np.testing.assert_allclose(gfd, g, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(Hfd, H, rtol=2e-4, atol=1e-4 * np.abs(H).max())
+    # and the gradient's own differences against the Hessian
+    Hg = np.array([(Ff(th0 + d * e[i])[1] - Ff(th0 - d * e[i])[1]) / (2 * d) for i in range(2)])
+    np.testing.assert_allclose(0.5 * (Hg + Hg.T), H, rtol=1e-5, atol=1e-6 * np.abs(H).max())
