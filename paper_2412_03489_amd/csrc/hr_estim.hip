@@ -139,6 +139,16 @@ __global__ void k_analytic(int kind, int n, const double* __restrict__ A,
     analytic_one(kind, n, A, b, c, s1, theta, tau, u, Aa, NH, h, r, f);
 }
 
+// 1/sigma^2 and 1/sigma^4, formed once per thread: the kernel factors and mixture densities
+// multiply by them instead of dividing in the per-contribution loops
+struct InvSigma {
+  double is2, is4;
+  __device__ __forceinline__ explicit InvSigma(double sigma) {
+    is2 = 1.0 / (sigma * sigma);
+    is4 = is2 * is2;
+  }
+};
+
 __device__ __forceinline__ double z_grad(double sg) { return sqrt(2.0 / kPi) / sg; }
 __device__ __forceinline__ double z_diag(double sg) {
   return 4.0 * exp(-0.5) / (sg * sg * sqrt(2.0 * kPi));
@@ -166,22 +176,24 @@ __device__ __forceinline__ void prep_one(const EstShape& e, const double* __rest
     // even weights (Hessian kernel, plain loss) add the antithetic partner
     if (e.A == 2) F = (e.hessk || e.what == kLoss) ? F0 + F1 : F0 - F1;
     const double* t = tau + sidx * (uint64_t)e.n;
-    const double sg = e.sigma, s2 = sg * sg;
+    const double sg = e.sigma;
+    const InvSigma iv(sg);
     if (e.sampler == kAIS) {
       double q = 0.0;
       if (!e.hessk) {
-        const double zg = z_grad(sg);
-        for (int k = 0; k < e.n; ++k) q += (fabs(t[k]) / s2) / zg;
+        // q = 1/K sum_k |d_k| / Z_G with |d_k| = |t_k| / sigma^2
+        const double c = iv.is2 / z_grad(sg);
+        for (int k = 0; k < e.n; ++k) q += fabs(t[k]) * c;
       } else {
-        const double zd = z_diag(sg), zo = z_grad(sg) * z_grad(sg);
+        const double izd = 1.0 / z_diag(sg), izo = 1.0 / (z_grad(sg) * z_grad(sg));
         double l1 = 0.0, l2 = 0.0, qd = 0.0;
         for (int k = 0; k < e.n; ++k) {
-          qd += fabs(t[k] * t[k] / (s2 * s2) - 1.0 / s2) / zd;
+          qd += fabs(t[k] * t[k] * iv.is4 - iv.is2) * izd;
           l1 += fabs(t[k]);
           l2 += t[k] * t[k];
         }
         // sum_{i<j} |t_i t_j| = ((sum |t_i|)^2 - sum t_i^2) / 2
-        q = qd + 0.5 * (l1 * l1 - l2) / (s2 * s2) / zo;
+        q = qd + 0.5 * (l1 * l1 - l2) * iv.is4 * izo;
       }
       q /= (double)e.K;
       F /= q;
@@ -205,14 +217,13 @@ __global__ void k_prep(EstShape e, const double* __restrict__ f, const double* _
 }
 
 // kernel factor d_m(tau) (output m; Hessian elements from (i, j))
-__device__ __forceinline__ double kfac(const EstShape& e, int m, int i, int j,
+__device__ __forceinline__ double kfac(const EstShape& e, const InvSigma& iv, int m, int i, int j,
                                        const double* t, double vts, const double* v) {
   if (e.what == kLoss) return 1.0;   // smoothed loss: plain mean of the renders
-  const double s2 = e.sigma * e.sigma;
-  if (e.what == kHvpLimit) return t[m] * vts / (s2 * s2) - v[m] / s2;
-  if (!e.hessk) return -t[m] / s2;
-  if (i == j) return t[i] * t[i] / (s2 * s2) - 1.0 / s2;
-  return t[i] * t[j] / (s2 * s2);
+  if (e.what == kHvpLimit) return t[m] * vts * iv.is4 - v[m] * iv.is2;
+  if (!e.hessk) return -t[m] * iv.is2;
+  if (i == j) return t[i] * t[i] * iv.is4 - iv.is2;
+  return t[i] * t[j] * iv.is4;
 }
 
 struct Lobes32 { fsum2 pos, neg; };
@@ -243,20 +254,21 @@ __device__ __forceinline__ void accum_block(const EstShape& e, const double* __r
     s_vt[i] = e.what == kHvpLimit ? vt[s0 + i] : 0.0;
   }
   __syncthreads();
+  const InvSigma iv(e.sigma);
   for (int m = threadIdx.x; m < e.nout; m += blockDim.x) {
     int i = 0, j = 0;
     if (e.hessk && e.what == kHess) tri_ij(e.n, m, i, j);
     if (fp64) {
       double pos = 0.0, neg = 0.0;
       for (int s = 0; s < ns; ++s) {
-        const double cv = kfac(e, m, i, j, s_tau + s * e.n, s_vt[s], v) * s_F[s];
+        const double cv = kfac(e, iv, m, i, j, s_tau + s * e.n, s_vt[s], v) * s_F[s];
         if (cv >= 0.0) pos += cv; else neg -= cv;
       }
       ((double2*)part)[c * (uint64_t)e.nout + m] = make_double2(pos, neg);
     } else {
       Lobes32 L = {{0.f, 0.f}, {0.f, 0.f}};
       for (int s = 0; s < ns; ++s) {
-        const float cv = (float)(kfac(e, m, i, j, s_tau + s * e.n, s_vt[s], v) * s_F[s]);
+        const float cv = (float)(kfac(e, iv, m, i, j, s_tau + s * e.n, s_vt[s], v) * s_F[s]);
         if (cv >= 0.0f) two_sum_add(L.pos, cv); else two_sum_add(L.neg, -cv);
       }
       ((float4*)part)[c * (uint64_t)e.nout + m] = make_float4(L.pos.hi, L.pos.lo, L.neg.hi, L.neg.lo);
@@ -283,13 +295,14 @@ __device__ __forceinline__ void accum_is_one(const EstShape& e, const double* __
   const int ns = (int)min((uint64_t)chunk, e.N - s0);
   int i = m, j = m;
   if (e.hessk) tri_ij(e.n, m, i, j);
+  const InvSigma iv(e.sigma);
   const double zm = !e.hessk ? z_grad(e.sigma) : (i == j ? z_diag(e.sigma) : z_grad(e.sigma) * z_grad(e.sigma));
   double pos64 = 0.0, neg64 = 0.0;
   Lobes32 L = {{0.f, 0.f}, {0.f, 0.f}};
   for (int s = 0; s < ns; ++s) {
     const uint64_t sidx = (uint64_t)m * e.N + s0 + s;
     const double* t = tau + sidx * (uint64_t)e.n;
-    const double d = kfac(e, m, i, j, t, 0.0, nullptr);
+    const double d = kfac(e, iv, m, i, j, t, 0.0, nullptr);
     const double w = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) * zm;
     const double cv = w * Fq[sidx];
     if (fp64) {
