@@ -124,6 +124,14 @@ def uneven_section(P, ctx, reps):
     for _ in range(reps):
         plain()
     t_plain = (time.perf_counter() - t0) / reps
+    log("bench: uneven batch, batched with the default raster configuration")
+    b0 = P.Batch(ctx, use_graph=True, autotune=False)
+    b0.run(qs)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b0.run(qs)
+    t_default = (time.perf_counter() - t0) / reps
+    b0.close()
     log("bench: uneven batch, batched (autotune on the first run)")
     b = P.Batch(ctx, use_graph=True, autotune=True)
     got = b.run(qs)
@@ -132,6 +140,11 @@ def uneven_section(P, ctx, reps):
         got = b.run(qs)
     t_batch = (time.perf_counter() - t0) / reps
     rep = b.report()
+    picks = {}
+    for sc in scenes:
+        spb, tile = P.tuned(ctx, sc)
+        key = f"S={spb},tile={('32x32', '32x32', '64x16', '16x64')[tile]}"
+        picks[key] = picks.get(key, 0) + 1
     identical = all(np.array_equal(x, y) for x, y in zip(got, ref))
     # precision plan: compensated-FP32 lobe sums against FP64 accumulation
     fp64 = P.Batch(ctx, use_graph=False).run([dict(q, accum_fp64=True) for q in qs])
@@ -147,6 +160,8 @@ def uneven_section(P, ctx, reps):
                         "Mpix_per_s": round(pixels / t_batch / 1e6, 1),
                         "graph": bool(rep["graph"]), "raster_items": rep["raster_items"],
                         "raster_blocks": rep["raster_blocks"]},
+            "batched_default_config_ms": round(t_default * 1e3, 3),
+            "autotuned_instances_by_choice": picks,
             "speedup": round(t_plain / t_batch, 3), "identical_to_plain": identical,
             "comp_fp32_vs_fp64_accum_max_rel": err, "reps": reps}
 
