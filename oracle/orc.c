@@ -653,7 +653,7 @@ static void weights(int hess, const tri_table* T, int K, const double* tau, doub
 }
 
 /* ========================================================================= */
-/* Estimator driver                                                          */
+/* Estimator loop                                                            */
 /* ========================================================================= */
 enum { W_GRAD = 0, W_HESS = 1, W_HVP = 2, W_HVPL = 3 };
 

@@ -2,7 +2,7 @@
 // scenes, workspace carving, the estimator pipeline
 //   draw tau -> perturbed renders + per-render loss -> per-draw weights ->
 //   compensated lobe sums -> FP64 finalisation
-// and the Newton-CG driver whose vector arithmetic runs on the GPU.
+// and the Newton-CG loop whose vector arithmetic runs on the GPU.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
