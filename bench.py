@@ -14,6 +14,7 @@ Also reported: p50/p99 latency of single HVP queries, the roofline of the
 dominant kernel (raster + MSE) from HIP events on its stream, and the CPU
 oracle on a bounded sample of the same workload; then, on the same line,
 `other_workloads` (one-disk gradient + Hessian, path-traced 6x6 Hessian),
+`extensions` (limit HVP, grey-box, comparators, optimiser loop),
 `uneven_batch` (64 uneven instances: plain calls vs one batch) and `serving`
 (Poisson-arriving Newton optimisations: server vs plain calls).
 
@@ -360,6 +361,57 @@ def configs_section(P, ctx, reps):
     return out
 
 
+def extensions_section(P, ctx, reps):
+    """The estimator's extensions on the 96-parameter raster scene, each timed
+    as host call to result: the limit-kernel HVP against the central
+    difference, the grey-box composition against the plain estimates, the
+    plain-Gaussian and FR22 comparators against the aggregate gradient, and
+    the optimiser loop (Newton-CG iterations with sigma annealing and a line
+    search on the smoothed loss)."""
+    import workloads as WL
+    w = WL.disks32()
+    sc = P.Scene.disks(ctx, w.W, w.H, w.C, w.colors, render_target_on_gpu(P, ctx, w),
+                       radius=w.radius, ppd=w.ppd)
+
+    def timed(fn):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    N = w.N
+    out = {"workload": "disks32_256x256_rgb", "draws": N}
+    hvp = timed(lambda: P.estimate("hvp", sc, w.theta0, w.sigma, N, w.seed, v=w.v))
+    lim = timed(lambda: P.estimate("hvp_limit", sc, w.theta0, w.sigma, N, w.seed, v=w.v))
+    out["hvp_central_ms"] = round(hvp, 3)
+    out["hvp_limit_ms"] = round(lim, 3)
+    # grey-box: 32 inner parameters (one scale per disk) mapped linearly onto
+    # the 96 scene parameters
+    J = np.zeros((w.n, 32))
+    for k in range(32):
+        J[3 * k:3 * k + 3, k] = w.theta0[3 * k:3 * k + 3]
+    y = w.theta0
+    out["greybox_grad_ms"] = round(timed(lambda: P.estimate_greybox("grad", sc, y, J, w.sigma, N,
+                                                                     w.seed)), 3)
+    out["plain_grad_ms"] = round(timed(lambda: P.estimate("grad", sc, y, w.sigma, N, w.seed)), 3)
+    out["greybox_hess_ms"] = round(timed(lambda: P.estimate_greybox("hess", sc, y, J, w.sigma,
+                                                                     4096, w.seed)), 3)
+    out["plain_hess_N4096_ms"] = round(timed(lambda: P.estimate("hess", sc, y, w.sigma, 4096,
+                                                                w.seed)), 3)
+    out["gauss_grad_ms"] = round(timed(lambda: P.estimate("grad", sc, y, w.sigma, N, w.seed,
+                                                          sampler=P.GAUSS)), 3)
+    out["fr22_grad_N1024_ms"] = round(timed(lambda: P.estimate("grad", sc, y, w.sigma, 1024,
+                                                               w.seed, sampler=P.FR22)), 3)
+    t0 = time.perf_counter()
+    P.optimize(sc, w.theta0, 16384, w.seed, 4, 0.04, 0.02, method="newton_cg", ls_iters=3,
+               N_loss=4096, cg_iters=4, trust_radius=0.05, modified=True)
+    out["optimiser_newton_cg_ms_per_iter"] = round((time.perf_counter() - t0) / 4 * 1e3, 3)
+    out["optimiser_setup"] = "N=16384, 4 CG products, 3 line-search halvings, N_loss=4096"
+    sc.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,8 +424,9 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB "
                          "(a kernel of known traffic for scaling memory counters)")
-    ap.add_argument("--sections", default="main,configs,uneven,serving",
-                    help="comma list of main, configs, uneven, serving (default: all)")
+    ap.add_argument("--sections", default="main,configs,extensions,uneven,serving",
+                    help="comma list of main, configs, extensions, uneven, serving "
+                         "(default: all)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--uneven-reps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
@@ -405,6 +458,8 @@ def main():
                 "note": "headline section skipped (--sections)"}
     if "configs" in sections:
         line["other_workloads"] = configs_section(P, ctx, 5)
+    if "extensions" in sections:
+        line["extensions"] = extensions_section(P, ctx, 3)
     if "uneven" in sections:
         line["uneven_batch"] = uneven_section(P, ctx, args.uneven_reps)
     if "serving" in sections:
