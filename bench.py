@@ -44,8 +44,8 @@ FLOP_PER_PIXEL = 12.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this SHA-256; reported as null once the source has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 467317673
-TRAFFIC_SOURCE_SHA256 = "9c7a39411d12847040118d0ae4fc7e90c958e2a41b12641c7924c7d5e0350f01"
+TRAFFIC_BYTES_PER_LAUNCH = 467321769
+TRAFFIC_SOURCE_SHA256 = "85b4df68b6f8ef8c572a1ae612d97f62cf94968ada97afc5588cd46672dfe191"
 
 
 def raster_traffic():

@@ -120,8 +120,8 @@ __device__ __noinline__ bool cover_fp64(RasterExact ex, uint64_t r, int k, int x
 
 __device__ __forceinline__ float dpp_quad_sum(float v) {
   // lanes (0,1,2,3) of every quad end with the quad's sum: xor 1, then xor 2
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
   return v;
 }
 
@@ -202,11 +202,14 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
   const int lane_d = lane < D ? lane : D - 1;
   float4 q_next = rp0[lane_d];
   const int nr_wave = live ? nr : 0;
+  // per pixel state: the LDS byte address of the top disk's colour; the
+  // colour table opens the dynamic LDS, which starts after the static LDS
+  const uint32_t col0 = __builtin_amdgcn_groupstaticsize();
   for (int rr = 0; rr < nr_wave; ++rr) {
     const float4* rp = rp0 + (uint64_t)rr * D;
-    int idx[kRows];
+    uint32_t idx[kRows];
 #pragma unroll
-    for (int i = 0; i < kRows; ++i) idx[i] = 0;
+    for (int i = 0; i < kRows; ++i) idx[i] = col0;
     uint64_t any = 0;
     for (int g0 = 0; g0 < D; g0 += 64) {
       float4 q;
@@ -233,7 +236,7 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
         const float r2lo = lane_bcast(q.w, l);
         const float dx = px - cx;
         const float dx2 = dx * dx;
-        const int id = g0 + l + 1;
+        const uint32_t id = col0 + (uint32_t)(g0 + l + 1) * (uint32_t)sizeof(float4);
         uint64_t amb[kRows];   // lanes whose squared distance fell inside the band
         uint64_t amb_any = 0;
 #pragma unroll
@@ -255,7 +258,7 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
           const double a = (rem % (uint64_t)ex.A) == 0 ? 1.0 : -1.0;
           const double* ts = ex.tau + (rem / (uint64_t)ex.A) * (uint64_t)ex.n;
           const double shift = sh == 0 ? ex.h : -ex.h;
-          const int k = id - 1;
+          const int k = g0 + l;
           double p[3];
           for (int qq = 0; qq < ex.ppd; ++qq) {
             const int jj = k * ex.ppd + qq;
@@ -283,9 +286,10 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
       e = t2;
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
-        const float4 col = s_col[idx[i]];
+        typedef float lds_f4 __attribute__((ext_vector_type(4)));
+        const lds_f4 col = *(const __attribute__((address_space(3))) lds_f4*)(uintptr_t)idx[i];
         const float cc[4] = {col.x, col.y, col.z, col.w};
-        float pe = C == 4 ? s_cc[idx[i]] : col.w;
+        float pe = C == 4 ? s_cc[(idx[i] - col0) / (uint32_t)sizeof(float4)] : col.w;
 #pragma unroll
         for (int c = 0; c < C; ++c) pe = fmaf(cc[c], tm2[i][c], pe);
         e += pe;
