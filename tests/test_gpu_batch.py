@@ -264,3 +264,43 @@ def test_server_admission_by_memory(P, ctx, scenes):
     ts = [srv.submit(sc, "grad", w.theta0, w.sigma, 64, 200 + i) for i in range(5)]
     assert all(srv.wait(t)[1]["batch_size"] == 1 for t in ts)
     srv.close()
+
+
+def test_server_concurrent_clients(P, ctx, scenes):
+    """Four client threads submit and wait at the same time (the binding drops
+    the GIL inside library calls); every result equals the query run alone."""
+    import threading
+    qs = [q for q in mixed_queries(scenes) if q["kind"] in ("grad", "hvp", "hess")]
+    alone = [single(P, q) for q in qs]
+    srv = P.Server(ctx, slots=3, max_batch=8, memory_bytes=1 << 30)
+    errors = []
+
+    def client(cid):
+        try:
+            for rnd in range(3):
+                order = list(range(len(qs)))[cid::2] if rnd % 2 else list(range(len(qs)))
+                tickets = []
+                for k in order:
+                    q = dict(qs[k])
+                    tickets.append((srv.submit(q.pop("scene"), q.pop("kind"), q.pop("theta"),
+                                               q.pop("sigma"), q.pop("N"), q.pop("seed"),
+                                               v=q.pop("v", None), **q), k))
+                for t, k in tickets:
+                    out, st = srv.wait(t)
+                    if st["status"] != 0 or not np.array_equal(np.ravel(out), np.ravel(alone[k])):
+                        errors.append((cid, k))
+        except Exception as e:   # reported below, not swallowed
+            errors.append((cid, repr(e)))
+
+    say("server: 4 concurrent client threads")
+    th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in th)
+    assert errors == []
+    assert srv.wait_any(timeout_ms=1.0) is None   # nothing left to hand out
+    s = srv.stats()
+    assert s["submitted"] == s["completed"]
+    srv.close()
