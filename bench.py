@@ -36,6 +36,12 @@ sys.path.insert(0, ROOT)
 METRIC = "Hessian-estimator throughput (perturbed Mpix/s) + p50/p99 HVP-query latency"
 PEAK_FP32_TFLOPS = 157.3          # MI355X fp32 vector (published)
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E (published)
+# path tracer, per path of one render (FMA = 2 FLOP, counted from the tracer's
+# code): 2 x (closest hit over 4 spheres, plane, light ~130) + 2 x (light
+# sample + shadow test ~142) + surface frames, bounce direction and
+# throughput ~90; plus ~25 square roots, reciprocals and sines not counted.
+# The camera ray and random words are shared by a draw's renders.
+PT_FLOP_PER_PATH = 630.0
 # algorithmic work per perturbed pixel of the bbox-culled rasteriser + loss:
 # 9 FLOP for the 3-channel squared error, 5 FLOP per disk test times the
 # 0.593 disks whose bounding box holds an average pixel (32 disks, E[r^2]).
@@ -169,7 +175,10 @@ def uneven_section(P, ctx, reps):
 
 def serving_section(P, ctx, args):
     """Newton optimisations arriving as a Poisson stream over the raster and
-    path-traced scenes: continuous-batching server vs plain per-query calls."""
+    path-traced scenes: continuous-batching server vs plain per-query calls
+    served one at a time in arrival order.  A saturating run first (its plain
+    throughput is the plain capacity), then offered loads of 0.5, 0.8, 1.0 and
+    1.5 x that capacity."""
     import workloads as WL
     from paper_2412_03489_amd import serving as SV
     wr = WL.disks32()
@@ -183,22 +192,43 @@ def serving_section(P, ctx, args):
     scenes = {"raster": sr, "pt": sp}
     sigma = {"raster": wr.sigma, "pt": wp.sigma}
     N = {"raster": args.serving_n_raster, "pt": args.serving_n_pt}
+    cg = args.serving_cg
+
+    def clients(specs):
+        return SV.make_clients(specs, scenes, sigma, N, cg, full_cg=True)
+
     # warm both paths
     warm = WL.serving_clients(4, rate=1e6, base_seed=99)
-    SV.run_plain(ctx, SV.make_clients(warm, scenes, sigma, N, args.serving_cg))
-    SV.run_served(ctx, SV.make_clients(warm, scenes, sigma, N, args.serving_cg))
+    SV.run_plain(ctx, clients(warm))
+    SV.run_served(ctx, clients(warm))
     rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
     out = {"clients": args.serving_clients,
-           "draws": {"raster_grad_hvp": N["raster"], "pt_grad_hess": N["pt"]},
-           "cg_iters": args.serving_cg}
-    for label, rate in (("saturated", args.serving_rate), ("moderate", args.serving_rate_low)):
-        specs = WL.serving_clients(args.serving_clients, rate=rate)
-        log(f"bench: serving {len(specs)} clients at {rate}/s, plain")
-        plain = SV.run_plain(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
-        log(f"bench: serving {len(specs)} clients at {rate}/s, continuous batching")
-        served = SV.run_served(ctx, SV.make_clients(specs, scenes, sigma, N, args.serving_cg))
-        out[label] = {"arrival_rate_per_s": rate, "plain": rnd(plain), "served": rnd(served),
-                      "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
+           "client": f"raster: 1 gradient + {cg} HVPs (N={N['raster']}); "
+                     f"path-traced: gradient + 6x6 Hessian (N={N['pt']})"}
+    specs = WL.serving_clients(args.serving_clients, rate=args.serving_rate)
+    log(f"bench: serving {len(specs)} clients at {args.serving_rate}/s, plain")
+    plain = SV.run_plain(ctx, clients(specs))
+    log(f"bench: serving {len(specs)} clients at {args.serving_rate}/s, continuous batching")
+    served = SV.run_served(ctx, clients(specs))
+    out["saturated"] = {"arrival_rate_per_s": args.serving_rate, "plain": rnd(plain),
+                        "served": rnd(served),
+                        "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
+    # offered-load sweep against the plain capacity (queries/s)
+    cap = plain["queries_per_s"]
+    per_client = (1 + cg + 2) / 2.0
+    sweep = []
+    for rho in (0.5, 0.8, 1.0, 1.5):
+        rate = rho * cap / per_client
+        specs = WL.serving_clients(args.serving_sweep_clients, rate=rate, base_seed=3000)
+        log(f"bench: serving load {rho} x plain capacity ({rate:.1f} clients/s)")
+        pl = SV.run_plain(ctx, clients(specs))
+        sv = SV.run_served(ctx, clients(specs))
+        keep = ("queries", "queries_per_s", "p50_ms", "p99_ms", "by_kind")
+        sweep.append({"load": rho, "clients_per_s": round(rate, 2),
+                      "plain": {k: pl[k] for k in keep}, "served": {k: sv[k] for k in keep}})
+    out["load_sweep"] = [{k: (rnd(v) if isinstance(v, dict) else v) for k, v in x.items()}
+                         for x in sweep]
+    out["plain_capacity_qps"] = round(cap, 2)
     sr.close()
     sp.close()
     return out
@@ -354,9 +384,15 @@ def configs_section(P, ctx, reps):
         P.estimate("hess", sp, wp.theta0, wp.sigma, wp.N, wp.seed)
     dt = (time.perf_counter() - t0) / reps
     renders = P.n_renders("hess", wp.n, wp.N)
+    paths = renders * wp.pixels * wp.spp
+    tflops = PT_FLOP_PER_PATH * paths / dt / 1e12
     out["pt_spheres_hessian"] = {"ms": round(dt * 1e3, 3), "renders": renders,
                                  "Mpix_per_s": round(renders * wp.pixels / dt / 1e6, 1),
-                                 "paths_per_s": round(renders * wp.pixels * wp.spp / dt, 1)}
+                                 "Mpaths_per_s": round(paths / dt / 1e6, 1),
+                                 "roofline": {"bound": "alu", "flop_per_path": PT_FLOP_PER_PATH,
+                                              "achieved": round(tflops, 3),
+                                              "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                              "frac": round(tflops / PEAK_FP32_TFLOPS, 4)}}
     sp.close()
     return out
 
@@ -432,10 +468,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serving-clients", type=int, default=256)
     ap.add_argument("--serving-rate", type=float, default=512.0)
-    ap.add_argument("--serving-rate-low", type=float, default=96.0)
+    ap.add_argument("--serving-sweep-clients", type=int, default=96)
     ap.add_argument("--serving-n-raster", type=int, default=16384)
     ap.add_argument("--serving-n-pt", type=int, default=2048)
-    ap.add_argument("--serving-cg", type=int, default=4)
+    ap.add_argument("--serving-cg", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "

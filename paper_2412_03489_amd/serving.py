@@ -28,11 +28,14 @@ EIG_FLOOR = 1e-3
 
 
 class NewtonClient:
-    """Application-side state of one Newton step (numpy, FP64)."""
+    """Application-side state of one Newton step (numpy, FP64).  With
+    full_cg the raster client makes all cg_iters products (the curvature
+    rule keeps every step well defined) and clips the final step to the trust
+    radius; otherwise CG stops as soon as the step reaches it."""
 
-    def __init__(self, spec, scene, sigma, N, cg_iters, steps=1):
+    def __init__(self, spec, scene, sigma, N, cg_iters, steps=1, full_cg=False):
         self.spec, self.scene, self.sigma, self.N = spec, scene, sigma, N
-        self.cg_iters, self.steps = cg_iters, steps
+        self.cg_iters, self.steps, self.full_cg = cg_iters, steps, full_cg
         self.theta = np.array(spec.theta0, dtype=np.float64)
         self.queries = 0
         self.step = 0
@@ -86,7 +89,8 @@ class NewtonClient:
         self.r = self.r - alpha * Hp
         self.it += 1
         rr_new = float(self.r @ self.r)
-        if self.it >= self.cg_iters or np.linalg.norm(self.d) >= TRUST or rr_new == 0.0:
+        at_trust = not self.full_cg and np.linalg.norm(self.d) >= TRUST
+        if self.it >= self.cg_iters or at_trust or rr_new == 0.0:
             return self._apply(self.d)
         self.p = self.r + (rr_new / rr) * self.p
         self.next = ("hvp", self.p.copy())
@@ -108,18 +112,29 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else float("nan")
 
 
-def _summary(lat_ms, t_total, nq, extra=None):
-    out = {"queries": nq, "seconds": t_total, "queries_per_s": nq / t_total,
-           "p50_ms": _pct(lat_ms, 50), "p99_ms": _pct(lat_ms, 99),
-           "mean_ms": float(np.mean(lat_ms)) if lat_ms else float("nan")}
+def _summary(lat, t_total, extra=None):
+    """lat: (query label, latency ms) pairs."""
+    ms = [x for _, x in lat]
+    out = {"queries": len(lat), "seconds": t_total, "queries_per_s": len(lat) / t_total,
+           "p50_ms": _pct(ms, 50), "p99_ms": _pct(ms, 99),
+           "mean_ms": float(np.mean(ms)) if ms else float("nan")}
+    by = {}
+    for label, x in lat:
+        by.setdefault(label, []).append(x)
+    out["by_kind"] = {k: {"queries": len(v), "p50_ms": round(_pct(v, 50), 3),
+                          "p99_ms": round(_pct(v, 99), 3)} for k, v in sorted(by.items())}
     if extra:
         out.update(extra)
     return out
 
 
-def make_clients(specs, scenes, sigma, N, cg_iters, steps=1):
-    return [NewtonClient(s, scenes[s.scene], sigma[s.scene], N[s.scene], cg_iters, steps)
-            for s in specs]
+def _label(client, q):
+    return f"{client.spec.scene}_{q['kind']}"
+
+
+def make_clients(specs, scenes, sigma, N, cg_iters, steps=1, full_cg=False):
+    return [NewtonClient(s, scenes[s.scene], sigma[s.scene], N[s.scene], cg_iters, steps,
+                         full_cg) for s in specs]
 
 
 def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_bytes=16 << 30,
@@ -135,9 +150,10 @@ def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_byt
 
     def submit(c, ts):
         q = c.query()
+        label = _label(c, q)
         t = srv.submit(q.pop("scene"), q.pop("kind"), q.pop("theta"), q.pop("sigma"),
                        q.pop("N"), q.pop("seed"), v=q.pop("v", None))
-        live[t] = (c, ts)
+        live[t] = (c, ts, label)
 
     while arrivals or live:
         now = time.perf_counter() - t0
@@ -152,16 +168,16 @@ def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_byt
         if t is None:
             continue
         out, st = srv.wait(t)
-        c, ts = live.pop(t)
+        c, ts, label = live.pop(t)
         tn = time.perf_counter()
-        lat.append((tn - ts) * 1e3)
+        lat.append((label, (tn - ts) * 1e3))
         sizes.append(st["batch_size"])
         if c.on_result(out):
             submit(c, tn)
     total = time.perf_counter() - t0
     s = srv.stats()
     srv.close()
-    return _summary(lat, total, len(lat), {"batches": s["batches"],
+    return _summary(lat, total, {"batches": s["batches"],
                                            "mean_batch": s["mean_batch"],
                                            "slots": slots, "max_batch": max_batch,
                                            "max_batch_ms": max_batch_ms})
@@ -186,13 +202,14 @@ def run_plain(ctx, clients):
             continue
         ts, _, c = heapq.heappop(queue)
         q = c.query()
+        label = _label(c, q)
         kind = q.pop("kind")
         out = estimate(kind, q.pop("scene"), q.pop("theta"), q.pop("sigma"), q.pop("N"),
                        q.pop("seed"), v=q.pop("v", None))
         tn = time.perf_counter()
-        lat.append((tn - ts) * 1e3)
+        lat.append((label, (tn - ts) * 1e3))
         if c.on_result(out):
             heapq.heappush(queue, (tn, order, c))
             order += 1
     total = time.perf_counter() - t0
-    return _summary(lat, total, len(lat))
+    return _summary(lat, total)
