@@ -32,7 +32,8 @@ def build(force: bool = True) -> str:
 class Opts(C.Structure):
     _fields_ = [("sampler", C.c_int), ("antithetic", C.c_int),
                 ("hvp_rel_step", C.c_double), ("nthreads", C.c_int),
-                ("s0", C.c_uint64), ("dbg_loss", C.POINTER(C.c_double))]
+                ("s0", C.c_uint64), ("dbg_loss", C.POINTER(C.c_double)),
+                ("hess_mix_n2", C.c_int)]
 
 
 class NcgOpts(C.Structure):
@@ -77,7 +78,7 @@ def lib():
         L.orc_scene_nparams.argtypes = [vp]; L.orc_scene_nparams.restype = i
         L.orc_render.argtypes = [vp, vp, u64, u32, i, vp]; L.orc_render.restype = i
         L.orc_loss.argtypes = [vp, vp, u64, u32]; L.orc_loss.restype = d
-        L.orc_draw_tau.argtypes = [i, i, d, u64, u32, i, i, vp, vp]; L.orc_draw_tau.restype = i
+        L.orc_draw_tau.argtypes = [i, i, d, u64, u32, i, i, i, vp, vp]; L.orc_draw_tau.restype = i
         for nm in ("orc_est_grad", "orc_est_hessian"):
             getattr(L, nm).argtypes = [vp, vp, d, u64, u64, C.POINTER(Opts), vp]
             getattr(L, nm).restype = i
@@ -129,11 +130,11 @@ def lambertw(z, branch):
     return lib().orc_lambertw(float(z), int(branch))
 
 
-def draw_tau(what, n, sigma, seed, s, sampler, stream=0):
+def draw_tau(what, n, sigma, seed, s, sampler, stream=0, mix_n2=False):
     tau = np.zeros(n)
     el = C.c_int(-1)
     st = lib().orc_draw_tau(int(what), int(n), float(sigma), int(seed), int(s), int(sampler),
-                            int(stream), _p(tau), C.byref(el))
+                            1 if mix_n2 else 0, int(stream), _p(tau), C.byref(el))
     if st:
         raise ValueError(f"orc_draw_tau failed ({st})")
     return tau, el.value
@@ -202,8 +203,9 @@ def loss(scene, theta, seed=0, s=0):
     return lib().orc_loss(scene.h, _p(th), int(seed), int(s))
 
 
-def _opts(sampler, antithetic, hvp_rel_step, nthreads, s0, dbg):
+def _opts(sampler, antithetic, hvp_rel_step, nthreads, s0, dbg, mix_n2=False):
     o = Opts()
+    o.hess_mix_n2 = 1 if mix_n2 else 0
     o.sampler = sampler
     o.antithetic = 1 if antithetic else 0
     o.hvp_rel_step = hvp_rel_step
@@ -223,14 +225,16 @@ def n_renders(kind, n, N, sampler=AIS, antithetic=True):
 
 
 def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic=True,
-             hvp_rel_step=0.1, nthreads=None, s0=0, return_losses=False):
-    """kind in {'grad', 'hess', 'hvp', 'hvp_limit'}; returns numpy array(s)."""
+             hvp_rel_step=0.1, nthreads=None, s0=0, return_losses=False, hess_mix_n2=False):
+    """kind in {'grad', 'hess', 'hvp', 'hvp_limit'}; returns numpy array(s).
+    hess_mix_n2: the aggregate Hessian mixture over all n^2 ordered pairs
+    instead of the n(n+1)/2 unique elements."""
     n = scene.n
     th = np.ascontiguousarray(theta, dtype=np.float64)
     if nthreads is None:
         nthreads = os.cpu_count() or 1
     dbg = np.zeros(n_renders(kind, n, N, sampler, antithetic)) if return_losses else None
-    o = _opts(sampler, antithetic, hvp_rel_step, nthreads, s0, dbg)
+    o = _opts(sampler, antithetic, hvp_rel_step, nthreads, s0, dbg, hess_mix_n2)
     L = lib()
     if kind == "grad":
         out = np.zeros(n)

@@ -583,8 +583,18 @@ static double kmass(int hess, const tri_table* T, int m, double sg) {
  * dimension of its draw is zero) */
 static int per_element(int sampler) { return sampler == ORC_IS || sampler == ORC_FR22; }
 
+/* Aggregate Hessian mixtures (section "Aggregate"): the element is either one
+ * of the K unique (i <= j) elements, or one of the n^2 ordered pairs (i, j),
+ * whose kernel and density are those of the unique element (min, max).  Under
+ * the n^2 mixture an off-diagonal element is chosen twice as often as a
+ * diagonal one. */
+static int tri_index(int n, int i, int j) {
+  int a = i < j ? i : j, b = i < j ? j : i;
+  return a * n - a * (a - 1) / 2 + (b - a);
+}
+
 static void draw(int hess, int n, double sg, uint64_t seed, uint32_t s, int sampler,
-                 int stream, double* tau, int* elem) {
+                 int mix_n2, int stream, double* tau, int* elem) {
   int K = hess ? n * (n + 1) / 2 : n;
   uint32_t tag = per_element(sampler) ? (uint32_t)stream
                                       : (sampler == ORC_AIS ? TAG_AIS : TAG_GAUSS);
@@ -602,7 +612,12 @@ static void draw(int hess, int n, double sg, uint64_t seed, uint32_t s, int samp
   if (sampler == ORC_AIS) {
     uint32_t w[4];
     philox_words(seed, s, DIM_SELECT, 0u, tag, w);
-    m = (int)(((uint64_t)w[0] * (uint64_t)K) >> 32);
+    if (hess && mix_n2) {
+      int pair = (int)(((uint64_t)w[0] * (uint64_t)n * (uint64_t)n) >> 32);
+      m = tri_index(n, pair / n, pair % n);
+    } else {
+      m = (int)(((uint64_t)w[0] * (uint64_t)K) >> 32);
+    }
   }
   if (m >= 0) {
     if (!hess) {
@@ -622,27 +637,41 @@ static void draw(int hess, int n, double sg, uint64_t seed, uint32_t s, int samp
 }
 
 int orc_draw_tau(int what, int n, double sigma, uint64_t seed, uint32_t s, int sampler,
-                 int stream, double* tau, int* element) {
-  if (n <= 0 || !(sigma > 0) || !tau) return -1;
+                 int mix_n2, int stream, double* tau, int* element) {
+  if (n <= 0 || !(sigma > 0) || !tau || (mix_n2 != 0 && mix_n2 != 1)) return -1;
   int e;
-  draw(what == 1, n, sigma, seed, s, sampler, stream, tau, &e);
+  draw(what == 1, n, sigma, seed, s, sampler, mix_n2, stream, tau, &e);
   if (element) *element = e;
   return 0;
 }
 
+/* Aggregate mixture density over the Gaussian: q = (1/K) sum_k |d_k| / Z_k
+ * over the K elements, or for the n^2 Hessian mixture (1/n^2) times the sum
+ * over all ordered pairs (i, j) of |d_ij| / Z_ij. */
+static double mixture_q(int hess, int mix_n2, int n, const tri_table* T, int K,
+                        const double* tau, double sg) {
+  double q = 0.0;
+  if (hess && mix_n2) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        int m = tri_index(n, i, j);
+        q += fabs(kfac(1, T, m, tau, sg)) / kmass(1, T, m, sg);
+      }
+    return q / ((double)n * (double)n);
+  }
+  for (int k = 0; k < K; ++k) q += fabs(kfac(hess, T, k, tau, sg)) / kmass(hess, T, k, sg);
+  return q / K;
+}
+
 /* Weights of all K elements for the draw tau:
  *  IS   : d_m N / p_m = sgn(d_m) Z_m
- *  AIS  : d_m N / q   with q = (1/K) sum_k |d_k| N / Z_k  (mixture of all K
- *         element densities, the "average of all stencils")
+ *  AIS  : d_m N / q   with q the mixture density above (the "average of all
+ *         stencils")
  *  GAUSS: d_m N / N = d_m */
-static void weights(int hess, const tri_table* T, int K, const double* tau, double sg,
-                    int sampler, double* w) {
+static void weights(int hess, int mix_n2, int n, const tri_table* T, int K, const double* tau,
+                    double sg, int sampler, double* w) {
   double q = 1.0;
-  if (sampler == ORC_AIS) {
-    q = 0.0;
-    for (int k = 0; k < K; ++k) q += fabs(kfac(hess, T, k, tau, sg)) / kmass(hess, T, k, sg);
-    q /= K;
-  }
+  if (sampler == ORC_AIS) q = mixture_q(hess, mix_n2, n, T, K, tau, sg);
   for (int m = 0; m < K; ++m) {
     double dm = kfac(hess, T, m, tau, sg);
     if (sampler == ORC_GAUSS) w[m] = dm;
@@ -659,7 +688,7 @@ enum { W_GRAD = 0, W_HESS = 1, W_HVP = 2, W_HVPL = 3 };
 
 typedef struct {
   const orc_scene* sc;
-  int what, n, K, sampler, A, nsh;
+  int what, n, K, sampler, mix_n2, A, nsh;
   const double* theta;
   double sg, h;
   const double* u;       /* HVP unit direction */
@@ -682,7 +711,7 @@ static void run_item(const job_t* J, uint64_t item) {
   double* ntau = (double*)malloc((size_t)n * sizeof(double));
   double* p = (double*)malloc((size_t)n * sizeof(double));
   int elem;
-  draw(hess_kernel, n, J->sg, J->seed, s, J->sampler, (int)stream, tau, &elem);
+  draw(hess_kernel, n, J->sg, J->seed, s, J->sampler, J->mix_n2, (int)stream, tau, &elem);
   for (int j = 0; j < n; ++j) ntau[j] = -tau[j];
 
   /* losses: f(theta - a tau) [+- h u for the HVP], a = +1 then -1 */
@@ -706,23 +735,14 @@ static void run_item(const job_t* J, uint64_t item) {
   if (J->what == W_HVPL) {
     /* weight of output i: sum_j v_j d_ij(tau) / q(tau), with the symmetric
      * Hessian kernel (d_ji = d_ij) and the aggregate mixture over i <= j */
-    int K = J->K;
     double q = 1.0;
-    if (J->sampler == ORC_AIS) {
-      q = 0.0;
-      for (int k = 0; k < K; ++k) q += fabs(kfac(1, J->T, k, tau, J->sg)) / kmass(1, J->T, k, J->sg);
-      q /= K;
-    }
+    if (J->sampler == ORC_AIS) q = mixture_q(1, J->mix_n2, n, J->T, J->K, tau, J->sg);
     double fs = 0.0;
     for (int ai = 0; ai < J->A; ++ai) fs += f[ai][0];
     double* c = J->contrib + item * (uint64_t)n;
     for (int i = 0; i < n; ++i) {
       double acc = 0.0;
-      for (int j = 0; j < n; ++j) {
-        int a = i < j ? i : j, b = i < j ? j : i;
-        int m = a * n - a * (a - 1) / 2 + (b - a);
-        acc += J->v[j] * kfac(1, J->T, m, tau, J->sg);
-      }
+      for (int j = 0; j < n; ++j) acc += J->v[j] * kfac(1, J->T, tri_index(n, i, j), tau, J->sg);
       /* the Hessian kernel is even in tau, so both antithetic renders share it */
       c[i] = acc / q * fs;
     }
@@ -731,7 +751,8 @@ static void run_item(const job_t* J, uint64_t item) {
     w[0] = (double*)malloc((size_t)J->K * sizeof(double));
     w[1] = (double*)malloc((size_t)J->K * sizeof(double));
     for (int ai = 0; ai < J->A; ++ai)
-      weights(hess_kernel, J->T, J->K, ai == 0 ? tau : ntau, J->sg, J->sampler, w[ai]);
+      weights(hess_kernel, J->mix_n2, n, J->T, J->K, ai == 0 ? tau : ntau, J->sg, J->sampler,
+              w[ai]);
     double fv[2];
     for (int ai = 0; ai < J->A; ++ai)
       fv[ai] = J->what == W_HVP ? J->vnorm * (f[ai][0] - f[ai][1]) / (2.0 * J->h) : f[ai][0];
@@ -778,6 +799,7 @@ static int run_estimator(const orc_scene* sc, int what, const double* theta, dou
   if (o->s0 + N > 0xFFFFFFFFull) return -1;
   for (int j = 0; j < n; ++j) if (!isfinite(theta[j])) return -1;
   if (o->sampler < 0 || o->sampler > 3) return -1;
+  if (o->hess_mix_n2 != 0 && o->hess_mix_n2 != 1) return -1;
   if (what == W_HVPL && per_element(o->sampler)) return -4;
   if (o->sampler == ORC_FR22 && what == W_HESS) return -4;
   int hess_kernel = (what == W_HESS || what == W_HVPL);
@@ -788,6 +810,7 @@ static int run_estimator(const orc_scene* sc, int what, const double* theta, dou
   job_t J;
   memset(&J, 0, sizeof(J));
   J.sc = sc; J.what = what; J.n = n; J.K = K; J.sampler = o->sampler; J.A = A;
+  J.mix_n2 = o->hess_mix_n2;
   J.nsh = what == W_HVP ? 2 : 1;
   J.theta = theta; J.sg = sg; J.N = N; J.seed = seed; J.s0 = o->s0; J.dbg = o->dbg_loss;
 
@@ -900,7 +923,7 @@ int orc_est_loss(const orc_scene* sc, const double* theta, double sigma, uint64_
   nsum acc = {0.0, 0.0};
   for (uint64_t s = 0; s < N; ++s) {
     int e;
-    draw(0, n, sigma, seed, (uint32_t)s, ORC_GAUSS, 0, tau, &e);
+    draw(0, n, sigma, seed, (uint32_t)s, ORC_GAUSS, 0, 0, tau, &e);
     for (int ai = 0; ai < A; ++ai) {
       double a = ai == 0 ? 1.0 : -1.0;
       for (int j = 0; j < n; ++j) p[j] = theta[j] - a * tau[j];

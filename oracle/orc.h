@@ -38,6 +38,9 @@ typedef struct {
   int nthreads;         /* worker threads over samples (>= 1)                 */
   uint64_t s0;          /* first sample index (prefix/sub-range evaluation)   */
   double* dbg_loss;     /* optional: per-render loss, canonical render order  */
+  int hess_mix_n2;      /* aggregate sampler, Hessian kernel: 0 mixes over the
+                           n(n+1)/2 unique elements, 1 over all n^2 ordered
+                           pairs (section "Aggregate")                       */
 } orc_opts;
 
 /* ---- random numbers (Salmon et al., SC'11) ---- */
@@ -69,7 +72,7 @@ double orc_loss(const orc_scene* sc, const double* theta, uint64_t seed, uint32_
 
 /* ---- draws: tau for one sample (for sampler tests) ---- */
 int orc_draw_tau(int what, int n, double sigma, uint64_t seed, uint32_t s, int sampler,
-                 int stream, double* tau, int* element);
+                 int mix_n2, int stream, double* tau, int* element);
 
 /* ---- estimators (sections "Gradients", "Hessians", "Hessian-vector product",
  *      "Aggregate") ---- */

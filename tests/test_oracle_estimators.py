@@ -72,6 +72,30 @@ def test_quad_hvp_unbiased(orc, quad, sampler):
     assert_within(m, se, A @ v)
 
 
+def test_quad_hessian_n2_mixture_unbiased(orc, quad):
+    """The n^2 aggregate mixture (section "Aggregate") is unbiased too: its
+    density counts every off-diagonal element twice, matching how often it is
+    drawn; the Hessian of a quadratic is A at any sigma."""
+    sc, A, b = quad
+    th = np.array([0.4, -0.9])
+    m, se = seeds_mean_se(lambda s: orc.estimate("hess", sc, th, 0.5, 3000, s,
+                                                 hess_mix_n2=True), 12)
+    assert_within(m, se, A)
+    v = np.array([1.5, 0.5])
+    m, se = seeds_mean_se(lambda s: orc.estimate("hvp_limit", sc, th, 0.5, 3000, s, v=v,
+                                                 hess_mix_n2=True), 12)
+    assert_within(m, se, A @ v)
+
+
+def test_n2_mixture_reduces_to_unique_mixture_for_one_parameter(orc):
+    """n = 1: one element, n^2 = n(n+1)/2 = 1, so both mixtures are the same
+    draws and weights."""
+    sc = orc.Scene.quad(np.array([[3.0]]), np.array([0.5]), 0.0)
+    a = orc.estimate("hess", sc, [0.2], 0.3, 500, 6)
+    b = orc.estimate("hess", sc, [0.2], 0.3, 500, 6, hess_mix_n2=True)
+    assert np.array_equal(a, b)
+
+
 def test_quad_hvp_limit_unbiased(orc, quad):
     sc, A, b = quad
     th = np.array([0.4, -0.9])

@@ -174,6 +174,22 @@ def test_ais_selector_uniform(orc):
     assert stats.chisquare(counts).pvalue > 1e-3
 
 
+def test_ais_n2_selector_counts_ordered_pairs(orc):
+    """Section "Aggregate", n^2 reading: the selector picks one of the n^2
+    ordered pairs uniformly, so a unique off-diagonal element (i < j) comes up
+    with probability 2/n^2 and a diagonal one with 1/n^2."""
+    n, count = 3, 9000
+    K = n * (n + 1) // 2
+    els = np.array([orc.draw_tau(1, n, 0.1, 11, i, orc.AIS, mix_n2=True)[1] for i in range(count)])
+    diag = [m for m, (i, j) in enumerate((i, j) for i in range(n) for j in range(i, n)) if i == j]
+    expected = np.array([1.0 if m in diag else 2.0 for m in range(K)]) / (n * n) * count
+    counts = np.bincount(els, minlength=K)
+    assert counts.sum() == count
+    assert stats.chisquare(counts, expected).pvalue > 1e-3
+    # and the unique-element selector on the same words is rejected by the same test
+    assert stats.chisquare(counts).pvalue < 1e-6
+
+
 def test_gauss_sampler_is_isotropic_gaussian(orc):
     taus, els = _ks_draws(orc, 0, 4, 0.2, orc.GAUSS, 0, 3000)
     assert (els == -1).all()
