@@ -92,6 +92,12 @@ typedef struct {
                            (S = 2 for the HVP, else 1); NULL = not wanted           */
   double* dbg_tau;      /* optional host buffer receiving the draws tau, streams*N*n
                            doubles in the order (stream*N + s)*n + j; NULL = not wanted */
+  int hess_mix_n2;      /* aggregate sampler with Hessian-kernel draws (Hessian, limit
+                           HVP), section "Aggregate": 0 (default) mixes over the
+                           n(n+1)/2 unique elements i <= j, 1 over all n^2 ordered
+                           pairs (an off-diagonal element drawn twice as often);
+                           ignored by the other samplers and estimators; other
+                           values are HR_EINVAL                                    */
 } hr_opts;
 
 /* Fills the defaults listed above. */

@@ -49,7 +49,8 @@ class HrError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("sampler", C.c_int), ("antithetic", C.c_int), ("hvp_rel_step", C.c_double),
                 ("accum_fp64", C.c_int), ("samples_per_block", C.c_int),
-                ("raster_tile", C.c_int), ("dbg_loss", C.POINTER(C.c_double)), ("dbg_tau", C.POINTER(C.c_double))]
+                ("raster_tile", C.c_int), ("dbg_loss", C.POINTER(C.c_double)),
+                ("dbg_tau", C.POINTER(C.c_double)), ("hess_mix_n2", C.c_int)]
 
 
 class NcgOpts(C.Structure):
@@ -175,7 +176,7 @@ def _p(a):
 
 
 def make_opts(sampler=AIS, antithetic=True, hvp_rel_step=0.1, accum_fp64=False,
-              samples_per_block=0, dbg=None, dbg_tau=None, raster_tile=0):
+              samples_per_block=0, dbg=None, dbg_tau=None, raster_tile=0, hess_mix_n2=False):
     o = Opts()
     lib().hr_opts_default(C.byref(o))
     o.sampler = sampler
@@ -184,6 +185,7 @@ def make_opts(sampler=AIS, antithetic=True, hvp_rel_step=0.1, accum_fp64=False,
     o.accum_fp64 = 1 if accum_fp64 else 0
     o.samples_per_block = samples_per_block
     o.raster_tile = raster_tile
+    o.hess_mix_n2 = 1 if hess_mix_n2 else 0
     o.dbg_loss = dbg.ctypes.data_as(C.POINTER(C.c_double)) if dbg is not None else None
     o.dbg_tau = dbg_tau.ctypes.data_as(C.POINTER(C.c_double)) if dbg_tau is not None else None
     return o
@@ -340,16 +342,17 @@ def n_streams(kind, n, sampler=AIS):
 
 def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic=True,
              hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0, return_losses=False,
-             return_draws=False, raster_tile=0):
+             return_draws=False, raster_tile=0, hess_mix_n2=False):
     """kind in {'grad', 'hess', 'hvp', 'hvp_limit'} (host-pointer entry points).
     With return_losses / return_draws the per-render losses and the draws are
-    returned as well (in that order)."""
+    returned as well (in that order).  hess_mix_n2: the aggregate Hessian
+    mixture over all n^2 ordered pairs."""
     n = scene.n
     th = np.ascontiguousarray(theta, dtype=np.float64)
     dbg = np.zeros(n_renders(kind, n, N, sampler, antithetic)) if return_losses else None
     taus = np.zeros(n_streams(kind, n, sampler) * N * n) if return_draws else None
     o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block, dbg, taus,
-                  raster_tile)
+                  raster_tile, hess_mix_n2)
     L = lib()
     if kind == "grad":
         out = np.zeros(n)
@@ -478,7 +481,7 @@ def out_shape(kind, n):
 
 
 _OPT_KEYS = ("sampler", "antithetic", "hvp_rel_step", "accum_fp64", "samples_per_block",
-             "raster_tile")
+             "raster_tile", "hess_mix_n2")
 
 
 def _query(scene, kind, theta, sigma, N, seed, v=None, out=None, **opt):
@@ -490,7 +493,8 @@ def _query(scene, kind, theta, sigma, N, seed, v=None, out=None, **opt):
     vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
     o = make_opts(opt.get("sampler", AIS), opt.get("antithetic", True),
                   opt.get("hvp_rel_step", 0.1), opt.get("accum_fp64", False),
-                  opt.get("samples_per_block", 0), raster_tile=opt.get("raster_tile", 0))
+                  opt.get("samples_per_block", 0), raster_tile=opt.get("raster_tile", 0),
+                  hess_mix_n2=opt.get("hess_mix_n2", False))
     q = Query(scene.h, KIND[kind], float(sigma), int(N), int(seed), _p(th),
               None if vv is None else _p(vv), C.pointer(o), None if out is None else _p(out))
     return q, (th, vv, o, out)

@@ -84,6 +84,7 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
   if (N == 0 || N >= 0xFFFFFFFFull) return fail(HR_EINVAL, "N must be in [1, 2^32 - 1)");
   if (o.sampler < 0 || o.sampler > 3) return fail(HR_EINVAL, "unknown sampler");
   if (o.raster_tile < 0 || o.raster_tile > 3) return fail(HR_EINVAL, "raster_tile must be in [0, 3]");
+  if (o.hess_mix_n2 != 0 && o.hess_mix_n2 != 1) return fail(HR_EINVAL, "hess_mix_n2 must be 0 or 1");
   if ((what == kHvp || what == kHvpLimit) && !has_v) return fail(HR_EINVAL, "v is NULL");
   if (what == kHvpLimit && per_element(o.sampler))
     return fail(HR_EUNSUPPORTED, "the limit-kernel HVP supports the aggregate and Gaussian samplers");
@@ -98,6 +99,7 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
   e.sampler = o.sampler;
   e.n = sc->n;
   e.hessk = (what == kHess || what == kHvpLimit) ? 1 : 0;
+  e.mix_n2 = (e.hessk && o.sampler == kAIS && o.hess_mix_n2) ? 1 : 0;
   e.K = what == kLoss ? 1 : (e.hessk ? e.n * (e.n + 1) / 2 : e.n);
   e.nout = what == kHess ? e.K : (what == kLoss ? 1 : e.n);
   e.N = N;
@@ -276,6 +278,7 @@ void hr_opts_default(hr_opts* o) {
   o->raster_tile = 0;
   o->dbg_loss = nullptr;
   o->dbg_tau = nullptr;
+  o->hess_mix_n2 = 0;
 }
 
 void hr_ncg_opts_default(hr_ncg_opts* o) {

@@ -5,6 +5,7 @@
 // factor d_m (D kappa_m(tau) = d_m(tau) N(tau)):
 //   est_m = 1/(A N) sum_s sum_a w_m(a tau_s) F(theta - a tau_s)
 //   IS    : w_m = sgn(d_m) Z_m     AIS: w_m = d_m / q,  q = 1/K sum_k |d_k|/Z_k
+//           (Hessian kernel, n^2 mixture: q = 1/n^2 sum_{i,j} |d_ij|/Z_ij)
 //   GAUSS : w_m = d_m
 // Gradient factors are odd in tau and Hessian factors even, so the antithetic
 // partner's weight is -w or +w; per draw the renders collapse to one scalar F_s.
@@ -25,9 +26,11 @@ inline unsigned grid_for(uint64_t total, int block) {
   return (unsigned)(g > 65536u * 16u ? 65536u * 16u : (g == 0 ? 1 : g));
 }
 
-// draw component gid = (stream * N + s) * n + j
-__device__ __forceinline__ void sample_one(int n, int K, int hessk, int sampler, uint64_t N,
-                                           uint64_t seed, double sg, uint64_t gid,
+// draw component gid = (stream * N + s) * n + j.  The aggregate selector picks
+// one of the K elements, or with mix_n2 one of the n^2 ordered pairs (i, j),
+// drawn with the lobes of the element (min, max).
+__device__ __forceinline__ void sample_one(int n, int K, int hessk, int mix_n2, int sampler,
+                                           uint64_t N, uint64_t seed, double sg, uint64_t gid,
                                            double* __restrict__ tau) {
   const int j = (int)(gid % (uint64_t)n);
   const uint64_t sidx = gid / (uint64_t)n;
@@ -35,22 +38,28 @@ __device__ __forceinline__ void sample_one(int n, int K, int hessk, int sampler,
   const uint32_t s = (uint32_t)(sidx % N);
   const uint32_t tag = per_element(sampler) ? stream : (sampler == kAIS ? kTagAIS : kTagGauss);
   const u32x4 w = philox_seeded(seed, s, (uint32_t)j, 0u, tag);
-  int m = -1;
+  int m = -1, i = -1, jj = -1;
   if (per_element(sampler)) m = (int)stream;
   if (sampler == kAIS) {
     const u32x4 ws = philox_seeded(seed, s, kDimSelect, 0u, tag);
-    m = (int)(((uint64_t)ws.x * (uint64_t)K) >> 32);
+    if (hessk && mix_n2) {
+      const uint64_t nn = (uint64_t)n * (uint64_t)n;
+      const int pair = (int)(((uint64_t)ws.x * nn) >> 32);
+      i = pair / n;
+      jj = pair % n;
+    } else {
+      m = (int)(((uint64_t)ws.x * (uint64_t)K) >> 32);
+    }
+  }
+  if (m >= 0) {
+    if (hessk) tri_ij(n, m, i, jj);
+    else i = jj = m;
   }
   bool lg = false, ld = false;
-  if (m >= 0) {
-    if (!hessk) {
-      lg = (j == m);
-    } else {
-      int i, jj;
-      tri_ij(n, m, i, jj);
-      if (i == jj) ld = (j == i);
-      else lg = (j == i || j == jj);
-    }
+  if (i >= 0) {
+    if (!hessk) lg = (j == i);
+    else if (i == jj) ld = (j == i);
+    else lg = (j == i || j == jj);
   }
   double t;
   if (ld) t = hdiag_lobe(w.z, sg);
@@ -61,11 +70,11 @@ __device__ __forceinline__ void sample_one(int n, int K, int hessk, int sampler,
 }
 
 // one thread per (stream, draw, dimension)
-__global__ void k_sample(int n, int K, int hessk, int sampler, uint64_t N, uint64_t seed,
-                         double sg, uint64_t total, double* __restrict__ tau) {
+__global__ void k_sample(int n, int K, int hessk, int mix_n2, int sampler, uint64_t N,
+                         uint64_t seed, double sg, uint64_t total, double* __restrict__ tau) {
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
        gid += (uint64_t)gridDim.x * blockDim.x)
-    sample_one(n, K, hessk, sampler, N, seed, sg, gid, tau);
+    sample_one(n, K, hessk, mix_n2, sampler, N, seed, sg, gid, tau);
 }
 
 __device__ __forceinline__ void vnorm_block(int n, const double* __restrict__ v,
@@ -192,10 +201,12 @@ __device__ __forceinline__ void prep_one(const EstShape& e, const double* __rest
           l1 += fabs(t[k]);
           l2 += t[k] * t[k];
         }
-        // sum_{i<j} |t_i t_j| = ((sum |t_i|)^2 - sum t_i^2) / 2
-        q = qd + 0.5 * (l1 * l1 - l2) * iv.is4 * izo;
+        // sum_{i<j} |t_i t_j| = ((sum |t_i|)^2 - sum t_i^2) / 2; the n^2 mixture
+        // counts each off-diagonal pair twice and divides by n^2
+        const double off = 0.5 * (l1 * l1 - l2) * iv.is4 * izo;
+        q = e.mix_n2 ? qd + 2.0 * off : qd + off;
       }
-      q /= (double)e.K;
+      q /= e.mix_n2 ? (double)e.n * (double)e.n : (double)e.K;
       F /= q;
     }
     Fq[sidx] = F;
@@ -414,7 +425,7 @@ __global__ __launch_bounds__(256) void k_batch_sample(const BatchTable* __restri
     }
     const EstShape& e = Q.e;
     elems_of_task(lt, e.streams * e.N * (uint64_t)e.n, [&](uint64_t g) {
-      sample_one(e.n, e.K, e.hessk, e.sampler, e.N, e.seed, e.sigma, g, Q.tau);
+      sample_one(e.n, e.K, e.hessk, e.mix_n2, e.sampler, e.N, e.seed, e.sigma, g, Q.tau);
     });
   }
 }
@@ -483,7 +494,7 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const BatchTable* __rest
 void launch_sample(hipStream_t st, const EstShape& e, double* tau) {
   const uint64_t total = e.streams * e.N * (uint64_t)e.n;
   hipLaunchKernelGGL(k_sample, dim3(grid_for(total, 256)), dim3(256), 0, st, e.n, e.K, e.hessk,
-                     e.sampler, e.N, e.seed, e.sigma, total, tau);
+                     e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau);
 }
 
 void launch_vnorm(hipStream_t st, int n, const double* v, double* u, double* vnorm) {

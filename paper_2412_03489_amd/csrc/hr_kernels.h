@@ -18,6 +18,7 @@ inline __host__ __device__ bool per_element(int sampler) { return sampler == kIS
 // with a = 0 for theta - tau, 1 for theta + tau; shift = 0 for +h u, 1 for -h u.
 struct EstShape {
   int what, sampler, n, K, hessk;   // hessk: draws/weights from the Hessian kernel
+  int mix_n2;                        // aggregate Hessian mixture over the n^2 ordered pairs
   int nout;                          // estimated elements (K for the Hessian, else n)
   uint64_t N, streams;               // streams = K for per-element IS, else 1
   int A, NH;                         // antithetic factor, shifts per render group

@@ -87,6 +87,10 @@ def mixed_queries(scenes):
              seed=11),
         dict(scene=s1, kind="hvp", theta=w1.theta0, sigma=w1.sigma, N=64, seed=12,
              v=np.zeros(2)),
+        dict(scene=s4, kind="hess", theta=w4.theta0, sigma=0.03, N=80, seed=13,
+             hess_mix_n2=True),
+        dict(scene=sp, kind="hvp_limit", theta=wp.theta0, sigma=wp.sigma, N=16, seed=14, v=vp,
+             hess_mix_n2=True),
     ]
 
 

@@ -40,20 +40,24 @@ def ctx(P):
 
 
 # ------------------------------------------------------------------- draws
-@pytest.mark.parametrize("kind,sampler", [("grad", 0), ("grad", 1), ("grad", 2), ("grad", 3),
-                                          ("hess", 0), ("hess", 1), ("hess", 2)])
-def test_draws_match_oracle(P, ctx, kind, sampler):
+@pytest.mark.parametrize("kind,sampler,n2", [("grad", 0, False), ("grad", 1, False),
+                                             ("grad", 2, False), ("grad", 3, False),
+                                             ("hess", 0, False), ("hess", 1, False),
+                                             ("hess", 2, False), ("hess", 0, True)])
+def test_draws_match_oracle(P, ctx, kind, sampler, n2):
     n = 4
     A = np.eye(n)
     g_sc = P.Scene.quad(ctx, A)
     N = 300
-    say(f"draws {kind} sampler={sampler} n={n} N={N}")
-    _, taus = P.estimate(kind, g_sc, np.zeros(n), 0.3, N, 99, sampler=sampler, return_draws=True)
+    say(f"draws {kind} sampler={sampler} n2={n2} n={n} N={N}")
+    _, taus = P.estimate(kind, g_sc, np.zeros(n), 0.3, N, 99, sampler=sampler, return_draws=True,
+                         hess_mix_n2=n2)
     streams = taus.size // (N * n)
     taus = taus.reshape(streams, N, n)
     for st in range(streams):
         for s in range(0, N, 7):
-            ref, _ = O.draw_tau(1 if kind == "hess" else 0, n, 0.3, 99, s, sampler, st)
+            ref, _ = O.draw_tau(1 if kind == "hess" else 0, n, 0.3, 99, s, sampler, st,
+                                mix_n2=n2)
             np.testing.assert_allclose(taus[st, s], ref, rtol=1e-13, atol=1e-15)
 
 
@@ -193,6 +197,43 @@ def test_ragged_scene_parity(P, ctx):
             assert rel_inf(got, ref) < TOL
 
 
+def test_n2_mixture_parity(P, ctx, quad_pair):
+    """The aggregate Hessian mixture over all n^2 ordered pairs: the analytic
+    quadratic in FP64, the one-disk scene at full size, a ragged 9-parameter
+    disk scene (Hessian and limit HVP) and the small path-traced scene."""
+    osc, gsc = quad_pair
+    th = np.array([0.3, -0.2, 0.5])
+    v = np.array([0.5, 1.0, -2.0])
+    for kind in ("hess", "hvp_limit"):
+        say(f"n2 quad {kind}")
+        ref = O.estimate(kind, osc, th, 0.4, 1037, 5, v=v, hess_mix_n2=True)
+        got = P.estimate(kind, gsc, th, 0.4, 1037, 5, v=v, hess_mix_n2=True, accum_fp64=True)
+        assert rel_inf(got, ref) < 1e-10
+        # a different estimator from the unique-element mixture on the same seed
+        other = O.estimate(kind, osc, th, 0.4, 1037, 5, v=v)
+        assert rel_inf(other, ref) > 1e-3
+    w = WL.one_disk()
+    tgt = disk_target(w)
+    o1, g1 = oracle_disks(w, tgt), gpu_disks(ctx, w, tgt)
+    say(f"n2 one_disk hess N={w.N}")
+    ref = O.estimate("hess", o1, w.theta0, w.sigma, w.N, w.seed, hess_mix_n2=True)
+    got = P.estimate("hess", g1, w.theta0, w.sigma, w.N, w.seed, hess_mix_n2=True)
+    assert rel_inf(got, ref) < TOL
+    g1.close()
+    w = small_disks(W=45, H=33, D=3, seed=12)
+    tgt = disk_target(w)
+    o3, g3 = oracle_disks(w, tgt), gpu_disks(ctx, w, tgt)
+    for kind in ("hess", "hvp_limit"):
+        say(f"n2 small disks {kind} n={w.n} N=200")
+        ref, lref = O.estimate(kind, o3, w.theta0, w.sigma, 200, w.seed, v=w.v,
+                               hess_mix_n2=True, return_losses=True)
+        got, lgot = P.estimate(kind, g3, w.theta0, w.sigma, 200, w.seed, v=w.v,
+                               hess_mix_n2=True, return_losses=True)
+        assert np.abs(lgot - lref).max() <= 1e-6 * np.abs(lref).max()
+        assert rel_inf(got, ref) < TOL
+    g3.close()
+
+
 @pytest.mark.parametrize("C_", [1, 2, 4])
 def test_channel_counts(P, ctx, C_):
     w = small_disks(W=40, H=40, D=6, C=C_, seed=3 + C_)
@@ -246,6 +287,14 @@ def test_pt_small_parity(P, pt_small, kind, sampler):
                            return_losses=True)
     # FP32 path tracing of the same paths: per-render losses agree to ~1e-5
     assert np.abs(lgot - lref).max() <= 2e-5 * np.abs(lref).max()
+    assert rel_inf(got, ref) < TOL
+
+
+def test_pt_small_n2_mixture_parity(P, pt_small):
+    w, osc, gsc = pt_small
+    say("pt_small hess n2 N=24")
+    ref = O.estimate("hess", osc, w.theta0, w.sigma, 24, w.seed, hess_mix_n2=True)
+    got = P.estimate("hess", gsc, w.theta0, w.sigma, 24, w.seed, hess_mix_n2=True)
     assert rel_inf(got, ref) < TOL
 
 
