@@ -9,8 +9,10 @@
 //   wave loads the disk records (one disk per lane, the next render's records
 //   already in flight), culls them against its sub-tile with a conservative
 //   circle/rectangle test, and walks the surviving disks in painter's order as
-//   a wave-uniform bit mask.  Per pixel only the index of the top disk is
-//   kept; its colour comes from LDS.
+//   a wave-uniform bit mask; with at most 64 disks the lanes park the
+//   records next to the disks' colours in LDS and a survivor's record is one
+//   broadcast LDS read, otherwise it comes by lane broadcasts.  Per pixel only
+//   the LDS address of the top disk's colour is kept.
 //
 // Coverage is decided exactly as the FP64 definition: every record carries
 // r^2 widened and narrowed by the FP32 error band of the test; the FP32 test
@@ -129,6 +131,111 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// float4 slots of the colour table (see raster_block)
+__host__ __device__ inline int raster_table_slots(int D) {
+  return D <= 64 ? 4 * (D + 1) * 2 : D + 1;
+}
+
+// Coverage of the wave's pixels by one surviving disk s = (cx, cy, r^2 + band,
+// r^2 - band) with colour address id: per row the pixel's top-disk address
+// becomes id where the FP32 test decides (d^2 < r^2 - band); pixels inside the
+// band are decided in FP64 from the unrounded parameters (rare, wave-uniform
+// branch).
+template <class Ex>
+__device__ __forceinline__ void cover_disk(const float4 s, int k, uint32_t id,
+                                           float px, const float (&py)[kRows],
+                                           uint32_t (&idx)[kRows], const Ex& ex, uint64_t r,
+                                           int x, int yb, int W, int H, int lane) {
+  const float dx = px - s.x;
+  const float dx2 = dx * dx;
+  uint64_t amb[kRows];   // lanes whose squared distance fell inside the band
+  uint64_t amb_any = 0;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const float dy = py[i] - s.y;
+    const float d2 = fmaf(dy, dy, dx2);
+    // lane masks straight from the compares (v_cmp into SGPRs)
+    const uint64_t m_hi = __builtin_amdgcn_fcmpf(d2, s.z, 4 /* ordered < */);
+    const uint64_t m_lo = __builtin_amdgcn_fcmpf(d2, s.w, 4 /* ordered < */);
+    amb[i] = m_hi & ~m_lo;
+    amb_any |= amb[i];
+    idx[i] = d2 < s.w ? id : idx[i];
+  }
+  if (amb_any) {
+    const int sh = (int)(r % (uint64_t)ex.NH);
+    const uint64_t rem = r / (uint64_t)ex.NH;
+    const double a = (rem % (uint64_t)ex.A) == 0 ? 1.0 : -1.0;
+    const double* ts = ex.tau + (rem / (uint64_t)ex.A) * (uint64_t)ex.n;
+    const double shift = sh == 0 ? ex.h : -ex.h;
+    double p[3];
+    for (int qq = 0; qq < ex.ppd; ++qq) {
+      const int jj = k * ex.ppd + qq;
+      double base = ex.theta[jj];
+      if (ex.NH == 2) base = base + shift * ex.u[jj];
+      p[qq] = base - a * ts[jj];
+    }
+    const double rad = ex.ppd == 3 ? p[2] : (double)ex.radius[k];
+    const double dxd = ((double)x + 0.5) / (double)W - p[0];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      if ((amb[i] >> lane) & 1) {
+        const double dyd = ((double)(yb + i) + 0.5) / (double)H - p[1];
+        const bool cov = rad > 0.0 && dxd * dxd + dyd * dyd < rad * rad;
+        idx[i] = cov ? id : idx[i];
+      }
+    }
+  }
+}
+
+// Loss of one render on the wave's tile when all disks fit one wavefront (D <=
+// 64): lane l holds disk l's record q for the cull and parks it in the wave's
+// table in front of disk l's colour (LDS byte address rec_slot); a survivor's
+// record is then one broadcast LDS read at its entry's address, the address
+// its pixels keep.  col0 is the wave's table (entry 0 = background, stride
+// 32 B, colour at +16).
+// Returns the lane-quad sum of the pixels' squared errors (every lane of a
+// quad holds it).
+template <int C, class Ex>
+__device__ __forceinline__ float render_one_group(
+    const float4 q, uint32_t rec_slot, uint64_t dmask, float mx, float my, float hx, float hy,
+    float px, const float (&py)[kRows], const float (&tm2)[kRows][C], float t2, float e_empty,
+    uint32_t col0, const float* s_cc, const Ex& ex, uint64_t r, int x, int yb, int W, int H,
+    int lane) {
+  typedef float lds_f4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) lds_f4 LdsF4;
+  *(LdsF4*)(uintptr_t)rec_slot = lds_f4{q.x, q.y, q.z, q.w};
+  // conservative cull against the sub-tile rectangle; the [0, 1] clamp (an
+  // output modifier) can only shorten the distance, so no covering disk is
+  // dropped.  r <= 0 records carry r^2 = -1 and never pass; lanes >= D repeat
+  // disk D-1 and are masked out.
+  const float ddx = __builtin_amdgcn_fmed3f(fabsf(q.x - mx) - hx, 0.0f, 1.0f);
+  const float ddy = __builtin_amdgcn_fmed3f(fabsf(q.y - my) - hy, 0.0f, 1.0f);
+  uint64_t mask =
+      __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z, 5 /* ordered <= */) & dmask;
+  if (mask == 0) return e_empty;
+  uint32_t idx[kRows];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) idx[i] = col0;
+  while (mask) {
+    const int l = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const uint32_t id = col0 + (uint32_t)(l + 1) * 32u;
+    const lds_f4 v = *(const LdsF4*)(uintptr_t)id;
+    cover_disk(make_float4(v.x, v.y, v.z, v.w), l, id, px, py, idx, ex, r, x, yb, W, H, lane);
+  }
+  float e = t2;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const lds_f4 col = *(const LdsF4*)(uintptr_t)(idx[i] + (uint32_t)sizeof(float4));
+    const float cc[4] = {col.x, col.y, col.z, col.w};
+    float pe = C == 4 ? s_cc[(idx[i] - col0) / 32u] : col.w;
+#pragma unroll
+    for (int c = 0; c < C; ++c) pe = fmaf(cc[c], tm2[i][c], pe);
+    e += pe;
+  }
+  return dpp_quad_sum(e);
+}
+
 // One block's work: renders [r0, r0 + nr) of one query on one 32x32 tile.
 // Shared by the per-query kernel and the persistent batch kernel, so a render's
 // tile partial is the same bits whichever launch computes it.
@@ -144,23 +251,33 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
   float* __restrict__ partial = a.partial;
   auto& ex = a.ex;
   const uint64_t r_base = a.r_base;
-  float4* s_col = smem;                        // D + 1 colours, index 0 = background
-  float* s_q = (float*)(smem + (D + 1));       // [S][4 waves][kQuadStride]
+  // colour table, entry 0 = background.  Up to 64 disks every wave has its
+  // own table whose entry k + 1 holds disk k's record of the render in flight
+  // followed by disk k's colour (stride 32 B; a pixel keeps the entry's
+  // address); beyond 64 disks the block shares one table of colours (stride
+  // 16 B; a pixel keeps the colour's address).
+  float4* s_col = smem;
+  const int tab_slots = raster_table_slots(D);
+  float* s_q = (float*)(smem + tab_slots);     // [S][4 waves][kQuadStride]
   float* s_cc = s_q + S * 4 * kQuadStride;     // D + 1 squared norms (C == 4)
   __syncthreads();   // the previous work item's readers of LDS are done
 
-  // colour table: channels, and |c|^2 in .w (C <= 3) or in s_cc (C == 4)
-  for (int k = threadIdx.x; k <= D; k += blockDim.x) {
+  // channels, and |c|^2 in .w (C <= 3) or in s_cc (C == 4)
+  for (int t = threadIdx.x; t < (kOneGroup ? 4 : 1) * (D + 1); t += blockDim.x) {
+    const int k = t % (D + 1);
     float cc[4] = {0.f, 0.f, 0.f, 0.f};
     if (k > 0)
       for (int c = 0; c < C; ++c) cc[c] = colors[(size_t)(k - 1) * C + c];
     float n2 = 0.0f;
     for (int c = 0; c < C; ++c) n2 = fmaf(cc[c], cc[c], n2);
-    s_col[k] = make_float4(cc[0], cc[1], cc[2], C == 4 ? cc[3] : n2);
-    if (C == 4) s_cc[k] = n2;
+    s_col[kOneGroup ? 2 * t + 1 : t] = make_float4(cc[0], cc[1], cc[2], C == 4 ? cc[3] : n2);
+    if (C == 4 && t <= D) s_cc[k] = n2;
   }
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index is wave-uniform: said so, everything derived from it
+  // (tile origin, liveness, the render loop bound) stays in scalar registers
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int bx0 = (tile % tiles_x) * (kSub * bwx), by0 = (tile / tiles_x) * (kSub * a.bwy);
   const int tx0 = bx0 + (wave % bwx) * kSub;
   const int ty0 = by0 + (wave / bwx) * kSub;
@@ -197,106 +314,94 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
   __syncthreads();
 
   const float4* rp0 = rec + r0 * (uint64_t)D;
-  // single group (D <= 64): lane l holds disk l; the next render's record is
-  // loaded while this render is processed (clamped on the last render)
-  const int lane_d = lane < D ? lane : D - 1;
-  float4 q_next = rp0[lane_d];
   const int nr_wave = live ? nr : 0;
   // per pixel state: the LDS byte address of the top disk's colour; the
   // colour table opens the dynamic LDS, which starts after the static LDS
   const uint32_t col0 = __builtin_amdgcn_groupstaticsize();
-  for (int rr = 0; rr < nr_wave; ++rr) {
-    const float4* rp = rp0 + (uint64_t)rr * D;
-    uint32_t idx[kRows];
+  // this lane's slot of the per-render quad partials [S][4 waves][kQuadStride]
+  float* sq = s_q + wave * kQuadStride + (lane >> 2);
+  const bool quad_head = (lane & 3) == 0;
+  if constexpr (kOneGroup) {
+    // lane l culls disk l; the next render's records are loaded while this
+    // render is processed (clamped on the last render), alternating between
+    // two registers sets
+    const int lane_d = lane < D ? lane : D - 1;
+    const uint64_t dmask = D < 64 ? (1ull << D) - 1 : ~0ull;
+    const char* rb = (const char*)rp0;
+    const uint64_t rstride = (uint64_t)D * sizeof(float4);
+    const uint32_t loff = (uint32_t)lane_d * (uint32_t)sizeof(float4);
+    // this wave's table and this lane's record slot in it
+    const uint32_t colw = col0 + (uint32_t)(wave * (D + 1)) * 32u;
+    const uint32_t rec_slot = colw + (uint32_t)(lane_d + 1) * 32u;
+    auto lane_rec = [&](int rr) {
+      // the render's base address is formed in scalar registers and the lane
+      // adds its 32-bit offset (a global load with a scalar base)
+      const uint64_t base = (uint64_t)rb + (uint64_t)min(rr, nr - 1) * rstride;
+      const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+      const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+      typedef const char __attribute__((address_space(1))) GlobalByte;
+      typedef float g_f4 __attribute__((ext_vector_type(4)));
+      GlobalByte* p = (GlobalByte*)(((uint64_t)hi << 32) | lo);
+      const g_f4 v = *(const __attribute__((address_space(1))) g_f4*)(p + loff);
+      return make_float4(v.x, v.y, v.z, v.w);
+    };
+    float4 qa = lane_rec(0);
+    for (int rr = 0; rr < nr_wave; rr += 2) {
+      const float4 qb = lane_rec(rr + 1);
+      float e = render_one_group<C>(qa, rec_slot, dmask, mx, my, hx, hy, px, py, tm2, t2,
+                                    e_empty, colw, s_cc, ex, r_base + r0 + (uint64_t)rr, x, yb,
+                                    W, H, lane);
+      if (quad_head) sq[rr * 4 * kQuadStride] = e;
+      if (rr + 1 >= nr_wave) break;
+      qa = lane_rec(rr + 2);
+      e = render_one_group<C>(qb, rec_slot, dmask, mx, my, hx, hy, px, py, tm2, t2,
+                              e_empty, colw, s_cc, ex, r_base + r0 + (uint64_t)(rr + 1), x, yb,
+                              W, H, lane);
+      if (quad_head) sq[(rr + 1) * 4 * kQuadStride] = e;
+    }
+  } else {
+    for (int rr = 0; rr < nr_wave; ++rr) {
+      const float4* rp = rp0 + (uint64_t)rr * D;
+      const uint64_t r = r_base + r0 + (uint64_t)rr;
+      uint32_t idx[kRows];
 #pragma unroll
-    for (int i = 0; i < kRows; ++i) idx[i] = col0;
-    uint64_t any = 0;
-    for (int g0 = 0; g0 < D; g0 += 64) {
-      float4 q;
-      if (kOneGroup) {
-        q = q_next;
-        q_next = rp0[(uint64_t)min(rr + 1, nr - 1) * D + lane_d];
-      } else {
+      for (int i = 0; i < kRows; ++i) idx[i] = col0;
+      uint64_t any = 0;
+      for (int g0 = 0; g0 < D; g0 += 64) {
         const int k = g0 + lane;
-        q = k < D ? rp[k] : make_float4(0.f, 0.f, -1.f, -1.f);
+        const float4 q = k < D ? rp[k] : make_float4(0.f, 0.f, -1.f, -1.f);
+        const float ddx = fmaxf(fabsf(q.x - mx) - hx, 0.0f);
+        const float ddy = fmaxf(fabsf(q.y - my) - hy, 0.0f);
+        uint64_t mask = __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z, 5 /* <= */);
+        any |= mask;
+        while (mask) {
+          const int l = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          const float4 sd = make_float4(lane_bcast(q.x, l), lane_bcast(q.y, l),
+                                        lane_bcast(q.z, l), lane_bcast(q.w, l));
+          cover_disk(sd, g0 + l, col0 + (uint32_t)(g0 + l + 1) * (uint32_t)sizeof(float4), px, py,
+                     idx, ex, r, x, yb, W, H, lane);
+        }
       }
-      const float ddx = fmaxf(fabsf(q.x - mx) - hx, 0.0f);
-      const float ddy = fmaxf(fabsf(q.y - my) - hy, 0.0f);
-      // r <= 0 records carry r^2 = -1 and never pass; lanes >= D repeat disk
-      // D-1 and are masked out
-      uint64_t mask = __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z, 5 /* ordered <= */);
-      if (kOneGroup && D < 64) mask &= (1ull << D) - 1;
-      any |= mask;
-      while (mask) {
-        const int l = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        const float cx = lane_bcast(q.x, l);
-        const float cy = lane_bcast(q.y, l);
-        const float r2hi = lane_bcast(q.z, l);
-        const float r2lo = lane_bcast(q.w, l);
-        const float dx = px - cx;
-        const float dx2 = dx * dx;
-        const uint32_t id = col0 + (uint32_t)(g0 + l + 1) * (uint32_t)sizeof(float4);
-        uint64_t amb[kRows];   // lanes whose squared distance fell inside the band
-        uint64_t amb_any = 0;
+      float e;
+      if (any == 0) {
+        e = e_empty;
+      } else {
+        e = t2;
 #pragma unroll
         for (int i = 0; i < kRows; ++i) {
-          const float dy = py[i] - cy;
-          const float d2 = fmaf(dy, dy, dx2);
-          // lane masks straight from the compares (v_cmp into SGPRs)
-          const uint64_t m_hi = __builtin_amdgcn_fcmpf(d2, r2hi, 4 /* ordered < */);
-          const uint64_t m_lo = __builtin_amdgcn_fcmpf(d2, r2lo, 4 /* ordered < */);
-          amb[i] = m_hi & ~m_lo;
-          amb_any |= amb[i];
-          idx[i] = d2 < r2lo ? id : idx[i];
+          typedef float lds_f4 __attribute__((ext_vector_type(4)));
+          const lds_f4 col = *(const __attribute__((address_space(3))) lds_f4*)(uintptr_t)idx[i];
+          const float cc[4] = {col.x, col.y, col.z, col.w};
+          float pe = C == 4 ? s_cc[(idx[i] - col0) / (uint32_t)sizeof(float4)] : col.w;
+#pragma unroll
+          for (int c = 0; c < C; ++c) pe = fmaf(cc[c], tm2[i][c], pe);
+          e += pe;
         }
-        if (amb_any) {
-          // rare: decide the band's pixels in FP64 from the unrounded parameters
-          const uint64_t r = r_base + r0 + (uint64_t)rr;
-          const int sh = (int)(r % (uint64_t)ex.NH);
-          const uint64_t rem = r / (uint64_t)ex.NH;
-          const double a = (rem % (uint64_t)ex.A) == 0 ? 1.0 : -1.0;
-          const double* ts = ex.tau + (rem / (uint64_t)ex.A) * (uint64_t)ex.n;
-          const double shift = sh == 0 ? ex.h : -ex.h;
-          const int k = g0 + l;
-          double p[3];
-          for (int qq = 0; qq < ex.ppd; ++qq) {
-            const int jj = k * ex.ppd + qq;
-            double base = ex.theta[jj];
-            if (ex.NH == 2) base = base + shift * ex.u[jj];
-            p[qq] = base - a * ts[jj];
-          }
-          const double rad = ex.ppd == 3 ? p[2] : (double)ex.radius[k];
-          const double dxd = ((double)x + 0.5) / (double)W - p[0];
-#pragma unroll
-          for (int i = 0; i < kRows; ++i) {
-            if ((amb[i] >> lane) & 1) {
-              const double dyd = ((double)(yb + i) + 0.5) / (double)H - p[1];
-              const bool cov = rad > 0.0 && dxd * dxd + dyd * dyd < rad * rad;
-              idx[i] = cov ? id : idx[i];
-            }
-          }
-        }
+        e = dpp_quad_sum(e);
       }
+      if (quad_head) sq[rr * 4 * kQuadStride] = e;
     }
-    float e;
-    if (any == 0) {
-      e = e_empty;
-    } else {
-      e = t2;
-#pragma unroll
-      for (int i = 0; i < kRows; ++i) {
-        typedef float lds_f4 __attribute__((ext_vector_type(4)));
-        const lds_f4 col = *(const __attribute__((address_space(3))) lds_f4*)(uintptr_t)idx[i];
-        const float cc[4] = {col.x, col.y, col.z, col.w};
-        float pe = C == 4 ? s_cc[(idx[i] - col0) / (uint32_t)sizeof(float4)] : col.w;
-#pragma unroll
-        for (int c = 0; c < C; ++c) pe = fmaf(cc[c], tm2[i][c], pe);
-        e += pe;
-      }
-      e = dpp_quad_sum(e);
-    }
-    if ((lane & 3) == 0) s_q[(rr * 4 + wave) * kQuadStride + (lane >> 2)] = e;
   }
   __syncthreads();
   // fixed-order sum of each wave's 16 quad partials: one partial per wave tile
@@ -448,8 +553,8 @@ void raster_geometry(RasterQuery& a, int shape) {
 }
 
 size_t raster_lds_bytes(int D, int S) {
-  return (size_t)(D + 1) * sizeof(float4) + (size_t)S * 4 * kQuadStride * sizeof(float) +
-         (size_t)(D + 1) * sizeof(float);
+  return (size_t)raster_table_slots(D) * sizeof(float4) +
+         (size_t)S * 4 * kQuadStride * sizeof(float) + (size_t)(D + 1) * sizeof(float);
 }
 
 int raster_max_samples() { return kMaxS; }
