@@ -239,7 +239,7 @@ __device__ __forceinline__ float render_one_group(
 // One block's work: renders [r0, r0 + nr) of one query on one 32x32 tile.
 // Shared by the per-query kernel and the persistent batch kernel, so a render's
 // tile partial is the same bits whichever launch computes it.
-template <int C, bool kOneGroup, class Query>
+template <int C, bool kOneGroup, bool kBufLoad, class Query>
 __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t r0, int nr,
                                              float4* smem) {
   const int W = a.W, H = a.H, D = a.D, S = a.S, tiles_x = a.tiles_x, bwx = a.bwx;
@@ -333,31 +333,46 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
     // this wave's table and this lane's record slot in it
     const uint32_t colw = col0 + (uint32_t)(wave * (D + 1)) * 32u;
     const uint32_t rec_slot = colw + (uint32_t)(lane_d + 1) * 32u;
+    // kBufLoad: the block's records as one buffer of nr * D records, the
+    // lane's byte offset in a vector register and the render's in a scalar
+    // one (no address arithmetic on the vector unit; descriptor word 3 is the
+    // gfx9 raw buffer format, 32-bit data).  Otherwise a global load from the
+    // render's base address in scalar registers: the persistent batch kernel
+    // has no scalar registers to spare for a descriptor.
+    typedef float g_f4 __attribute__((ext_vector_type(4)));
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)rb, (short)0, (int)((uint64_t)nr * rstride), 0x00020000);
     auto lane_rec = [&](int rr) {
-      // the render's base address is formed in scalar registers and the lane
-      // adds its 32-bit offset (a global load with a scalar base)
-      const uint64_t base = (uint64_t)rb + (uint64_t)min(rr, nr - 1) * rstride;
-      const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-      const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-      typedef const char __attribute__((address_space(1))) GlobalByte;
-      typedef float g_f4 __attribute__((ext_vector_type(4)));
-      GlobalByte* p = (GlobalByte*)(((uint64_t)hi << 32) | lo);
-      const g_f4 v = *(const __attribute__((address_space(1))) g_f4*)(p + loff);
+      g_f4 v;
+      if constexpr (kBufLoad) {
+        v = __builtin_bit_cast(
+            g_f4, __builtin_amdgcn_raw_buffer_load_b128(
+                      rsrc, (int)loff, (int)((uint32_t)min(rr, nr - 1) * (uint32_t)rstride), 0));
+      } else {
+        const uint64_t base = (uint64_t)rb + (uint64_t)min(rr, nr - 1) * rstride;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+        typedef const char __attribute__((address_space(1))) GlobalByte;
+        GlobalByte* p = (GlobalByte*)(((uint64_t)hi << 32) | lo);
+        v = *(const __attribute__((address_space(1))) g_f4*)(p + loff);
+      }
       return make_float4(v.x, v.y, v.z, v.w);
     };
     float4 qa = lane_rec(0);
+    float* sqr = sq;   // advanced by two renders' partials per pass
     for (int rr = 0; rr < nr_wave; rr += 2) {
       const float4 qb = lane_rec(rr + 1);
       float e = render_one_group<C>(qa, rec_slot, dmask, mx, my, hx, hy, px, py, tm2, t2,
                                     e_empty, colw, s_cc, ex, r_base + r0 + (uint64_t)rr, x, yb,
                                     W, H, lane);
-      if (quad_head) sq[rr * 4 * kQuadStride] = e;
+      if (quad_head) sqr[0] = e;
       if (rr + 1 >= nr_wave) break;
       qa = lane_rec(rr + 2);
       e = render_one_group<C>(qb, rec_slot, dmask, mx, my, hx, hy, px, py, tm2, t2,
                               e_empty, colw, s_cc, ex, r_base + r0 + (uint64_t)(rr + 1), x, yb,
                               W, H, lane);
-      if (quad_head) sq[(rr + 1) * 4 * kQuadStride] = e;
+      if (quad_head) sqr[4 * kQuadStride] = e;
+      sqr += 8 * kQuadStride;
     }
   } else {
     for (int rr = 0; rr < nr_wave; ++rr) {
@@ -428,7 +443,7 @@ __global__ __launch_bounds__(256) void k_raster_loss(RasterQuery a, uint64_t chu
   if (chunk >= chunks) return;
   const uint64_t r0 = chunk * (uint64_t)a.S;
   const int nr = (int)min((uint64_t)a.S, a.R - r0);
-  raster_block<C, kOneGroup, RasterQuery>(a, tile, r0, nr, smem);
+  raster_block<C, kOneGroup, true, RasterQuery>(a, tile, r0, nr, smem);
 }
 
 // single render at theta, coverage in FP64 (the definition)
@@ -509,14 +524,14 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restri
       const int nr = (int)min((uint64_t)a.S, a.R - r0);
       const bool one = a.D <= 64;
       switch (a.C) {
-        case 1: if (one) raster_block<1, true, ConstRasterQuery>(a, tile, r0, nr, smem);
-                else raster_block<1, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
-        case 2: if (one) raster_block<2, true, ConstRasterQuery>(a, tile, r0, nr, smem);
-                else raster_block<2, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
-        case 3: if (one) raster_block<3, true, ConstRasterQuery>(a, tile, r0, nr, smem);
-                else raster_block<3, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
-        default: if (one) raster_block<4, true, ConstRasterQuery>(a, tile, r0, nr, smem);
-                 else raster_block<4, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+        case 1: if (one) raster_block<1, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
+                else raster_block<1, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+        case 2: if (one) raster_block<2, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
+                else raster_block<2, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+        case 3: if (one) raster_block<3, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
+                else raster_block<3, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
+        default: if (one) raster_block<4, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
+                 else raster_block<4, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
       }
     }
   }
