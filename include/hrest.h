@@ -346,7 +346,9 @@ typedef struct {
   int pt_blocks;
   uint64_t workspace_bytes; /* device workspace of the batch                    */
   uint64_t lds_bytes;       /* dynamic LDS of the persistent rasteriser         */
-  int graph;                /* 1 if the launches ran as a graph replay          */
+  int graph;                /* 1 if the launches ran as a graph replay; a batch
+                               of one query runs the per-query kernels directly
+                               (same result bits) and reports 0               */
 } hr_batch_report;
 
 typedef struct hr_batch hr_batch;

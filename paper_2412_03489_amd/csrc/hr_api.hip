@@ -147,6 +147,55 @@ QueryBufs carve(const QueryPlan& p, void* base) {
   return b;
 }
 
+void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBufs& qb,
+                  const double* d_theta, const double* d_v, double* d_out, int S, int shape,
+                  bool timing) {
+  const hr_scene* sc = pl.sc;
+  const hr_opts& o = pl.o;
+  const EstShape& e = pl.e;
+  const int chunk = pl.chunk;
+  const int tiles = pl.stride;
+  const int what = e.what;
+  auto T = [&](const char* name, auto&& fn) {
+    if (timing) timed(ctx, name, fn);
+    else fn();
+  };
+  double* tau = qb.tau;
+  double* u = qb.u;
+  double* vnorm = qb.vnorm;
+  float4* rec = qb.rec;
+  float* partial = qb.partial;
+  double* f = qb.f;
+  double* Fq = qb.Fq;
+  double* vt = qb.vt;
+  void* acc = qb.acc;
+
+  if (what == kHvp || what == kHvpLimit) launch_vnorm(s, e.n, d_v, u, vnorm);
+  T("sample", [&] { launch_sample(s, e, tau); });
+  const int spb = S;
+  if (sc->kind == kDisks) {
+    DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};
+    T("records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
+    RasterExact ex{d_theta, tau, u, sc->radius, e.n, sc->ppd, e.A, e.NH, e.h};
+    T("raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, shape, ex, partial); });
+    T("tile_reduce", [&] {
+      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
+    });
+  } else if (sc->kind == kPT) {
+    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
+    T("pt_loss", [&] { launch_pt_loss(s, e, ps, d_theta, tau, u, spb, partial); });
+    T("tile_reduce", [&] {
+      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f);
+    });
+  } else {
+    AnalyticScene as{sc->kind == kQuad ? 0 : 1, sc->n, sc->A, sc->b, sc->c, sc->s1};
+    launch_analytic(s, e, as, d_theta, tau, u, f);
+  }
+  launch_prep(s, e, f, tau, vnorm, d_v, Fq, vt);
+  T("accumulate", [&] { launch_accum(s, e, tau, Fq, vt, d_v, o.accum_fp64, acc, chunk); });
+  launch_finalize(s, e, acc, o.accum_fp64, chunk, d_out);
+}
+
 }  // namespace rt
 }  // namespace hr
 
@@ -175,8 +224,7 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
   const hr_opts& o = pl.o;
   const EstShape& e = pl.e;
   N = e.N;
-  const int chunk = pl.chunk;
-  const int tiles = pl.stride;
+  (void)what;
   HR_HIP(hipSetDevice(ctx->device));
   (void)hipGetLastError();   // launch checks below report this call's errors only
   if (pl.total > ctx->budget)
@@ -185,41 +233,10 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
   st = ensure(ctx, &ctx->ws, &ctx->ws_bytes, pl.total);
   if (st) return st;
   const QueryBufs qb = carve(pl, ctx->ws);
-  double* tau = qb.tau;
-  double* u = qb.u;
-  double* vnorm = qb.vnorm;
-  float4* rec = qb.rec;
-  float* partial = qb.partial;
-  double* f = qb.f;
-  double* Fq = qb.Fq;
-  double* vt = qb.vt;
-  void* acc = qb.acc;
-
   hipStream_t s = ctx->stream;
-  if (what == kHvp || what == kHvpLimit) launch_vnorm(s, e.n, d_v, u, vnorm);
-  timed(ctx, "sample", [&] { launch_sample(s, e, tau); });
-  const int spb = o.samples_per_block;
-  if (sc->kind == kDisks) {
-    DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};
-    timed(ctx, "records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
-    RasterExact ex{d_theta, tau, u, sc->radius, e.n, sc->ppd, e.A, e.NH, e.h};
-    timed(ctx, "raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, o.raster_tile, ex, partial); });
-    timed(ctx, "tile_reduce", [&] {
-      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
-    });
-  } else if (sc->kind == kPT) {
-    PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
-    timed(ctx, "pt_loss", [&] { launch_pt_loss(s, e, ps, d_theta, tau, u, spb, partial); });
-    timed(ctx, "tile_reduce", [&] {
-      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f);
-    });
-  } else {
-    AnalyticScene as{sc->kind == kQuad ? 0 : 1, sc->n, sc->A, sc->b, sc->c, sc->s1};
-    launch_analytic(s, e, as, d_theta, tau, u, f);
-  }
-  launch_prep(s, e, f, tau, vnorm, d_v, Fq, vt);
-  timed(ctx, "accumulate", [&] { launch_accum(s, e, tau, Fq, vt, d_v, o.accum_fp64, acc, chunk); });
-  launch_finalize(s, e, acc, o.accum_fp64, chunk, d_out);
+  launch_query(ctx, s, pl, qb, d_theta, d_v, d_out, o.samples_per_block, o.raster_tile, true);
+  double* tau = qb.tau;
+  double* f = qb.f;
   HR_HIP(hipGetLastError());
   if (h_dbg) HR_HIP(hipMemcpyAsync(h_dbg, f, e.R * 8, hipMemcpyDeviceToHost, s));
   if (h_tau) HR_HIP(hipMemcpyAsync(h_tau, tau, e.streams * N * (uint64_t)e.n * 8, hipMemcpyDeviceToHost, s));

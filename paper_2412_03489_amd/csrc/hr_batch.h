@@ -24,8 +24,11 @@ struct BatchSlot {
   hr_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  int cus = 1, phase_blocks = 1, raster_blocks = 1;
+  int cus = 1, phase_blocks = 1;
+  int raster_blocks[kRasterClasses] = {};   // persistent blocks per raster class
   int pt_blocks[3] = {1, 1, 1};    // per renders-per-draw class (1, 2, 4)
+  uint64_t raster_class_items[kRasterClasses] = {};   // work items per class
+  uint64_t pt_class_items[3] = {};
   void* dev = nullptr;             // device table: header, queries, task lists,
   void* host = nullptr;            //   queue segments, counters, theta/v, outputs
   size_t table_bytes = 0;          //   (pinned host mirror of the same layout)
@@ -33,12 +36,22 @@ struct BatchSlot {
   size_t ws_bytes = 0;
   hipGraphExec_t exec = nullptr;   // the captured launch sequence
   size_t exec_lds = 0;
+  unsigned exec_classes = 0;       // render classes launched by the captured sequence
   size_t lds = 0;                  // dynamic LDS of the persistent rasteriser
   bool graph_used = false;
   bool allow_timing = true;        // phase timers (batch entry point only)
   int nq_ = 0;
   size_t upload_bytes_ = 0, out_off_ = 0, out_doubles_ = 0;
   uint64_t raster_items_ = 0, pt_items_ = 0;
+  // A batch of one query runs the per-query kernels on this slot's stream and
+  // workspace (the same bits as the batch kernels; no task lists, no queues).
+  bool single_ = false;
+  QueryPlan single_plan_{};
+  QueryBufs single_bufs_{};
+  const double* single_theta_ = nullptr;   // device pointers into the table
+  const double* single_v_ = nullptr;
+  double* single_out_ = nullptr;
+  int single_S_ = 0, single_shape_ = 0;
 
   hr_status init(hr_ctx* c);
   void release();
@@ -51,6 +64,8 @@ struct BatchSlot {
   // copies each item's result from the pinned mirror to its destination
   void scatter(const std::vector<BatchItem>& items) const;
   void launches(hipStream_t st, bool time_phases);
+  // render classes with work: raster classes in bits 0-7, path-traced in 8-10
+  unsigned classes() const;
 };
 
 // validates one public query and plans it

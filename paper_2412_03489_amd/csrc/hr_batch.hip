@@ -171,8 +171,8 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
 
   struct Q8 { std::vector<WorkSeg> seg[8]; uint64_t items[8] = {0, 0, 0, 0, 0, 0, 0, 0}; };
-  Q8 rq, pq[3];   // path-traced queues by renders per draw (1, 2, 4)
-  uint64_t rchunks = 0, pchunks[3] = {0, 0, 0};
+  Q8 rq[kRasterClasses], pq[3];   // raster queues by class, path-traced by renders per draw
+  uint64_t rchunks[kRasterClasses] = {}, pchunks[3] = {0, 0, 0};
   auto add_segments = [](Q8& Qs, uint64_t& cbase, int q, uint64_t chunks, int tiles) {
     for (int x = 0; x < 8; ++x) {
       const int c0 = (int)(((uint64_t)x + 8u - (cbase & 7u)) & 7u);
@@ -195,7 +195,8 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       a = RasterQuery{};
       a.W = sc->W; a.H = sc->H; a.C = sc->C; a.D = sc->D; a.S = qS[q];
       raster_geometry(a, qshape[q]);
-      add_segments(rq, rchunks, q, (p.e.R + qS[q] - 1) / qS[q], a.tiles);
+      const int cls = raster_class(sc->C, sc->D);
+      add_segments(rq[cls], rchunks[cls], q, (p.e.R + qS[q] - 1) / qS[q], a.tiles);
     } else if (sc->kind == kPT) {
       const uint64_t draws = p.e.streams * p.e.N;
       const int nr = p.e.A * p.e.NH;
@@ -204,15 +205,19 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
     }
   }
   raster_items_ = pt_items_ = 0;
+  for (int c = 0; c < kRasterClasses; ++c) raster_class_items[c] = 0;
+  for (int c = 0; c < 3; ++c) pt_class_items[c] = 0;
   for (int x = 0; x < 8; ++x) {
-    raster_items_ += rq.items[x];
-    for (int c = 0; c < 3; ++c) pt_items_ += pq[c].items[x];
+    for (int c = 0; c < kRasterClasses; ++c) raster_class_items[c] += rq[c].items[x];
+    for (int c = 0; c < 3; ++c) pt_class_items[c] += pq[c].items[x];
   }
+  for (int c = 0; c < kRasterClasses; ++c) raster_items_ += raster_class_items[c];
+  for (int c = 0; c < 3; ++c) pt_items_ += pt_class_items[c];
 
   // table layout
-  size_t nrs = 0, nps[3] = {0, 0, 0}, nin = 0, nout = 0;
+  size_t nrs[kRasterClasses] = {}, nps[3] = {0, 0, 0}, nin = 0, nout = 0;
   for (int x = 0; x < 8; ++x) {
-    nrs += rq.seg[x].size();
+    for (int c = 0; c < kRasterClasses; ++c) nrs[c] += rq[c].seg[x].size();
     for (int c = 0; c < 3; ++c) nps[c] += pq[c].seg[x].size();
   }
   for (auto& it : items) {
@@ -224,10 +229,10 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   const size_t o_hdr = take(sizeof(BatchTable));
   const size_t o_q = take((size_t)nq * sizeof(BatchQuery));
   const size_t o_off = take((size_t)kNumPhases * (nq + 1) * 8);
-  const size_t o_rs = take(std::max<size_t>(nrs, 1) * sizeof(WorkSeg));
-  size_t o_ps[3];
+  size_t o_rs[kRasterClasses], o_ps[3];
+  for (int c = 0; c < kRasterClasses; ++c) o_rs[c] = take(std::max<size_t>(nrs[c], 1) * sizeof(WorkSeg));
   for (int c = 0; c < 3; ++c) o_ps[c] = take(std::max<size_t>(nps[c], 1) * sizeof(WorkSeg));
-  const size_t o_ctr = take(32 * 8);
+  const size_t o_ctr = take(kWorkCounters * 8);
   const size_t o_in = take(nin * 8);
   upload_bytes_ = off;
   const size_t o_out = take(nout * 8);
@@ -243,6 +248,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   T->nq = nq;
   T->q = (const BatchQuery*)(Dv + o_q);
   T->off = (const uint64_t*)(Dv + o_off);
+  T->ctr = (unsigned long long*)(Dv + o_ctr);
   auto fill_queues = [&](WorkQueues& W, Q8& Qs, size_t o_seg, size_t ctr_index) {
     WorkSeg* hs = (WorkSeg*)(H + o_seg);
     uint64_t k = 0;
@@ -255,8 +261,8 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
     W.seg = (const WorkSeg*)(Dv + o_seg);
     W.ctr = (unsigned long long*)(Dv + o_ctr) + ctr_index;
   };
-  fill_queues(T->raster, rq, o_rs, 0);
-  for (int c = 0; c < 3; ++c) fill_queues(T->pt[c], pq[c], o_ps[c], 8 + 8 * c);
+  for (int c = 0; c < kRasterClasses; ++c) fill_queues(T->raster[c], rq[c], o_rs[c], 8 * c);
+  for (int c = 0; c < 3; ++c) fill_queues(T->pt[c], pq[c], o_ps[c], 8 * (kRasterClasses + c));
 
   BatchQuery* HQ = (BatchQuery*)(H + o_q);
   double* hin = (double*)(H + o_in);
@@ -320,6 +326,16 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       b.as = AnalyticScene{sc->kind == kQuad ? 0 : 1, n, sc->A, sc->b, sc->c, sc->s1};
     }
   }
+  single_ = nq == 1;
+  if (single_) {
+    single_plan_ = items[0].plan;
+    single_bufs_ = carve(single_plan_, (char*)ws + items[0].ws_off);
+    single_theta_ = HQ[0].theta;
+    single_v_ = HQ[0].v;
+    single_out_ = HQ[0].out;
+    single_S_ = qS[0];
+    single_shape_ = qshape[0];
+  }
   uint64_t* ho = (uint64_t*)(H + o_off);
   for (int ph = 0; ph < kNumPhases; ++ph) {
     uint64_t acc = 0;
@@ -336,6 +352,14 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
 
 void BatchSlot::launches(hipStream_t st, bool time_phases) {
   const BatchTable* T = (const BatchTable*)dev;
+  if (single_) {
+    hipStream_t keep = ctx->stream;
+    if (time_phases) ctx->stream = st;
+    launch_query(ctx, st, single_plan_, single_bufs_, single_theta_, single_v_, single_out_,
+                 single_S_, single_shape_, time_phases);
+    if (time_phases) ctx->stream = keep;
+    return;
+  }
   auto run = [&](const char* name, auto&& fn) {
     if (time_phases) {
       hipStream_t keep = ctx->stream;
@@ -349,9 +373,15 @@ void BatchSlot::launches(hipStream_t st, bool time_phases) {
   run("batch_sample", [&] { launch_batch_sample(st, T, phase_blocks); });
   run("batch_records", [&] { launch_batch_records(st, T, phase_blocks); });
   run("batch_analytic", [&] { launch_batch_analytic(st, T, phase_blocks); });
-  run("batch_raster", [&] { launch_batch_raster(st, T, raster_blocks, lds); });
+  // only the render classes with work are launched
+  const unsigned cl = classes();
+  run("batch_raster", [&] {
+    for (int c = 0; c < kRasterClasses; ++c)
+      if (cl & (1u << c)) launch_batch_raster(st, T, c, raster_blocks[c], lds);
+  });
   run("batch_pt", [&] {
-    for (int c = 0; c < 3; ++c) launch_batch_pt(st, T, 1 << c, pt_blocks[c]);
+    for (int c = 0; c < 3; ++c)
+      if (cl & (1u << (8 + c))) launch_batch_pt(st, T, 1 << c, pt_blocks[c]);
   });
   run("batch_reduce", [&] { launch_batch_reduce(st, T, phase_blocks); });
   run("batch_prep", [&] { launch_batch_prep(st, T, phase_blocks); });
@@ -359,15 +389,28 @@ void BatchSlot::launches(hipStream_t st, bool time_phases) {
   run("batch_finalize", [&] { launch_batch_finalize(st, T, phase_blocks); });
 }
 
+unsigned BatchSlot::classes() const {
+  unsigned m = 0;
+  for (int c = 0; c < kRasterClasses; ++c)
+    if (raster_class_items[c]) m |= 1u << c;
+  for (int c = 0; c < 3; ++c)
+    if (pt_class_items[c]) m |= 1u << (8 + c);
+  return m;
+}
+
 hr_status BatchSlot::enqueue(bool use_graph) {
   HR_HIP(hipSetDevice(ctx->device));
   (void)hipGetLastError();
-  raster_blocks = cus * batch_raster_blocks_per_cu(lds);
+  const unsigned cl = classes();
+  for (int c = 0; c < kRasterClasses; ++c)
+    if (cl & (1u << c)) raster_blocks[c] = cus * batch_raster_blocks_per_cu(c, lds);
   HR_HIP(hipMemcpyAsync(dev, host, upload_bytes_, hipMemcpyHostToDevice, stream));
   graph_used = false;
   const bool timing = allow_timing && ctx->timing;
-  if (use_graph && !timing) {
-    if (exec && exec_lds != lds) {
+  // a one-query batch launches its per-query kernels directly: their launch
+  // parameters are the query's own, so a captured sequence would not be reusable
+  if (use_graph && !timing && !single_) {
+    if (exec && (exec_lds != lds || exec_classes != cl)) {
       (void)hipGraphExecDestroy(exec);
       exec = nullptr;
     }
@@ -383,6 +426,7 @@ hr_status BatchSlot::enqueue(bool use_graph) {
         return fail(HR_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
       }
       exec_lds = lds;
+      exec_classes = cl;
     }
     HR_HIP(hipGraphLaunch(exec, stream));
     graph_used = true;
@@ -449,13 +493,16 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
         if (st) break;
         // time the raster kernel alone, twice, on the prepared records
         const BatchTable* T = (const BatchTable*)slot.dev;
-        const int blocks = slot.cus * batch_raster_blocks_per_cu(slot.lds);
+        const unsigned cl = slot.classes();
         float best_ms = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {
           // the work counters restart from zero before each timed launch
           launch_batch_sample(slot.stream, T, slot.phase_blocks);
           if (hipEventRecord(a, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }
-          launch_batch_raster(slot.stream, T, blocks, slot.lds);
+          for (int c = 0; c < kRasterClasses; ++c)
+            if (cl & (1u << c))
+              launch_batch_raster(slot.stream, T, c, slot.cus * batch_raster_blocks_per_cu(c, slot.lds),
+                                  slot.lds);
           if (hipEventRecord(b, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }
           if (hipEventSynchronize(b) != hipSuccess) { st = fail(HR_EDEVICE, "event sync"); break; }
           float ms = 0.f;
@@ -594,7 +641,13 @@ hr_status hr_batch_run(hr_batch* b, const hr_query* queries, int count) {
   b->slot.scatter(items);
   b->last.raster_items = b->slot.raster_items_;
   b->last.pt_items = b->slot.pt_items_;
-  b->last.raster_blocks = b->slot.raster_blocks;
+  {
+    int rb = 0;
+    const unsigned cl = b->slot.classes();
+    for (int c = 0; c < kRasterClasses; ++c)
+      if (cl & (1u << c)) rb = std::max(rb, b->slot.raster_blocks[c]);
+    b->last.raster_blocks = rb;
+  }
   b->last.pt_blocks = b->slot.pt_blocks[0];
   b->last.workspace_bytes = ws;
   b->last.graph = b->slot.graph_used ? 1 : 0;

@@ -392,11 +392,11 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// elements [t * kBatchElems, min(total, (t + 1) * kBatchElems)) of a step
-template <class F>
+// elements [t * kElems, min(total, (t + 1) * kElems)) of a step
+template <int kElems = kBatchElems, class F>
 __device__ __forceinline__ void elems_of_task(uint64_t t, uint64_t total, F&& fn) {
-  const uint64_t b = t * (uint64_t)kBatchElems;
-  const uint64_t e = umin64(total, b + kBatchElems);
+  const uint64_t b = t * (uint64_t)kElems;
+  const uint64_t e = umin64(total, b + kElems);
   for (uint64_t g = b + threadIdx.x; g < e; g += blockDim.x) fn(g);
 }
 
@@ -405,11 +405,7 @@ __global__ __launch_bounds__(256) void k_batch_sample(const BatchTable* __restri
   const int nq = T->nq;
   const uint64_t* off = T->off + (uint64_t)kPhSample * (nq + 1);
   // the render work queues start empty
-  if (blockIdx.x == 0 && threadIdx.x < 32) {
-    const int set = threadIdx.x >> 3;
-    unsigned long long* c = set == 0 ? T->raster.ctr : T->pt[set - 1].ctr;
-    c[threadIdx.x & 7] = 0ull;
-  }
+  if (blockIdx.x == 0 && threadIdx.x < kWorkCounters) T->ctr[threadIdx.x] = 0ull;
   const uint64_t total = off[nq];
   for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int q = batch_find(off, nq, t);
@@ -439,7 +435,7 @@ __global__ __launch_bounds__(256) void k_batch_analytic(const BatchTable* __rest
     const BatchQuery& Q = T->q[q];
     const EstShape& e = Q.e;
     const AnalyticScene& a = Q.as;
-    elems_of_task(t - off[q], e.R, [&](uint64_t r) {
+    elems_of_task<kBatchHeavyElems>(t - off[q], e.R, [&](uint64_t r) {
       analytic_one(a.kind, a.n, a.A, a.b, a.c, a.s1, Q.theta, Q.tau, Q.u, e.A, e.NH, e.h, r, Q.f);
     });
   }
@@ -452,7 +448,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(const BatchTable* __restrict
   for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int q = batch_find(off, nq, t);
     const BatchQuery& Q = T->q[q];
-    elems_of_task(t - off[q], Q.e.streams * Q.e.N, [&](uint64_t sidx) {
+    elems_of_task<kBatchHeavyElems>(t - off[q], Q.e.streams * Q.e.N, [&](uint64_t sidx) {
       prep_one(Q.e, Q.f, Q.tau, Q.u + Q.e.n, Q.v, sidx, Q.Fq, Q.vt);
     });
   }
@@ -551,11 +547,11 @@ uint64_t batch_tasks(const BatchQuery& q, int phase) {
     case kPhRecords:
       return q.scene == kDisks ? ceil_div(e.R * (uint64_t)q.ds.D, kBatchElems) : 0;
     case kPhAnalytic:
-      return render ? 0 : ceil_div(e.R, kBatchElems);
+      return render ? 0 : ceil_div(e.R, kBatchHeavyElems);
     case kPhReduce:
       return render ? ceil_div(e.R, kBatchRenders) : 0;
     case kPhPrep:
-      return ceil_div(e.streams * e.N, kBatchElems);
+      return ceil_div(e.streams * e.N, kBatchHeavyElems);
     case kPhAccum:
       return per_element(e.sampler) ? ceil_div(q.nchunks * (uint64_t)e.nout, 256) : q.nchunks;
     case kPhFinalize:

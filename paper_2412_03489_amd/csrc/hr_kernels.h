@@ -123,6 +123,8 @@ void launch_finalize(hipStream_t st, const EstShape& e, const void* part, int fp
 // single-query kernels (so every output is the same bits).  Renders come from
 // two persistent kernels that pull work items from eight queues, one per XCD.
 constexpr int kBatchElems = 2048;    // elements per task of an elementwise step
+constexpr int kBatchHeavyElems = 256; // per task where an element costs O(n) or more
+                                      // (per-draw prep, analytic renders): one per thread
 constexpr int kBatchRenders = 64;    // renders per task of the tile reduction
 
 enum SceneKind { kDisks = 0, kPT = 1, kQuad = 2, kNegGauss = 3 };
@@ -165,12 +167,20 @@ struct BatchQuery {
 };
 enum BatchPhase { kPhSample = 0, kPhRecords, kPhAnalytic, kPhReduce, kPhPrep, kPhAccum,
                   kPhFinalize, kNumPhases };
+// Raster items are queued by class -- channel count and whether all disks
+// fit one wavefront -- and each class has its own persistent kernel, which
+// holds only that variant's registers.
+constexpr int kRasterClasses = 8;
+__host__ __device__ inline int raster_class(int C, int D) { return (C - 1) * 2 + (D > 64 ? 1 : 0); }
+constexpr int kWorkCounters = 8 * (kRasterClasses + 3);   // 8 per queue set
+
 struct BatchTable {
   int nq, pad;
   const BatchQuery* q;
   const uint64_t* off;       // [kNumPhases][nq + 1]
-  WorkQueues raster;
+  WorkQueues raster[kRasterClasses];
   WorkQueues pt[3];          // path-traced items by renders per draw: 1, 2, 4
+  unsigned long long* ctr;   // kWorkCounters item counters, zeroed by the sampling phase
 };
 // device-side lookup: the query owning task t of a phase (t < off[nq])
 __device__ __forceinline__ int batch_find(const uint64_t* off, int nq, uint64_t t) {
@@ -200,7 +210,7 @@ uint64_t batch_tasks(const BatchQuery& q, int phase);
 void launch_batch_sample(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_records(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_analytic(hipStream_t st, const BatchTable* T, int blocks);
-void launch_batch_raster(hipStream_t st, const BatchTable* T, int blocks, size_t lds);
+void launch_batch_raster(hipStream_t st, const BatchTable* T, int cls, int blocks, size_t lds);
 // path-traced items with nr renders per draw (1, 2 or 4)
 void launch_batch_pt(hipStream_t st, const BatchTable* T, int nr, int blocks);
 void launch_batch_reduce(hipStream_t st, const BatchTable* T, int blocks);
@@ -208,7 +218,7 @@ void launch_batch_prep(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_accum(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_finalize(hipStream_t st, const BatchTable* T, int blocks);
 // occupancy of the persistent raster kernel (blocks per CU) for a given LDS size
-int batch_raster_blocks_per_cu(size_t lds);
+int batch_raster_blocks_per_cu(int cls, size_t lds);
 int batch_pt_blocks_per_cu(int nr);
 // path tracer constants for device-resident scenes
 size_t pt_const_bytes();

@@ -349,12 +349,13 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
             g_f4, __builtin_amdgcn_raw_buffer_load_b128(
                       rsrc, (int)loff, (int)((uint32_t)min(rr, nr - 1) * (uint32_t)rstride), 0));
       } else {
+        // a descriptor of this render's records only, built where it is used
         const uint64_t base = (uint64_t)rb + (uint64_t)min(rr, nr - 1) * rstride;
         const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
         const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-        typedef const char __attribute__((address_space(1))) GlobalByte;
-        GlobalByte* p = (GlobalByte*)(((uint64_t)hi << 32) | lo);
-        v = *(const __attribute__((address_space(1))) g_f4*)(p + loff);
+        const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(((uint64_t)hi << 32) | lo), (short)0, (int)rstride, 0x00020000);
+        v = __builtin_bit_cast(g_f4, __builtin_amdgcn_raw_buffer_load_b128(r1, (int)loff, 0, 0));
       }
       return make_float4(v.x, v.y, v.z, v.w);
     };
@@ -482,17 +483,19 @@ __global__ __launch_bounds__(256) void k_batch_records(const BatchTable* __restr
   }
 }
 
-// Persistent raster over the eight work queues.  Queue x holds the chunks of
-// S renders whose position in the batch's chunk sequence is x mod 8, each
+// Persistent raster over the eight work queues of one raster class (channel
+// count C, all disks in one wavefront or not).  Queue x holds the chunks of
+// S renders whose position in the class's chunk sequence is x mod 8, each
 // chunk as one item per block of its image; blocks start on the queue of
 // their XCD (block id mod 8), so the records of a chunk are read by one XCD,
 // and move on to the other queues when theirs is empty.  Every item is
 // claimed by exactly one atomic increment; a block leaves after seeing all
 // eight queues exhausted.
+template <int C, bool kOneGroup>
 __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restrict__ T) {
   extern __shared__ float4 smem[];
   __shared__ unsigned long long s_item;
-  const WorkQueues& W = T->raster;
+  const WorkQueues& W = T->raster[raster_class(C, kOneGroup ? 1 : 65)];
   const int home = blockIdx.x & 7;
   uint64_t all = 0;
   for (int x = 0; x < 8; ++x) all += W.items[x];
@@ -522,17 +525,7 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restri
       const int tile = (int)(l % (uint64_t)sg.tiles);
       const uint64_t r0 = chunk * (uint64_t)a.S;
       const int nr = (int)min((uint64_t)a.S, a.R - r0);
-      const bool one = a.D <= 64;
-      switch (a.C) {
-        case 1: if (one) raster_block<1, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
-                else raster_block<1, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
-        case 2: if (one) raster_block<2, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
-                else raster_block<2, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
-        case 3: if (one) raster_block<3, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
-                else raster_block<3, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
-        default: if (one) raster_block<4, true, false, ConstRasterQuery>(a, tile, r0, nr, smem);
-                 else raster_block<4, false, false, ConstRasterQuery>(a, tile, r0, nr, smem); break;
-      }
+      raster_block<C, kOneGroup, false, ConstRasterQuery>(a, tile, r0, nr, smem);
     }
   }
 }
@@ -620,12 +613,26 @@ void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& 
 void launch_batch_records(hipStream_t st, const BatchTable* T, int blocks) {
   hipLaunchKernelGGL(k_batch_records, dim3(blocks), dim3(256), 0, st, T);
 }
-void launch_batch_raster(hipStream_t st, const BatchTable* T, int blocks, size_t lds) {
-  hipLaunchKernelGGL(k_batch_raster, dim3(blocks), dim3(256), lds, st, T);
+typedef void (*BatchRasterKernel)(const BatchTable*);
+static BatchRasterKernel batch_raster_kernel(int cls) {
+  switch (cls) {
+    case 0: return k_batch_raster<1, true>;
+    case 1: return k_batch_raster<1, false>;
+    case 2: return k_batch_raster<2, true>;
+    case 3: return k_batch_raster<2, false>;
+    case 4: return k_batch_raster<3, true>;
+    case 5: return k_batch_raster<3, false>;
+    case 6: return k_batch_raster<4, true>;
+    default: return k_batch_raster<4, false>;
+  }
 }
-int batch_raster_blocks_per_cu(size_t lds) {
+void launch_batch_raster(hipStream_t st, const BatchTable* T, int cls, int blocks, size_t lds) {
+  hipLaunchKernelGGL(batch_raster_kernel(cls), dim3(blocks), dim3(256), lds, st, T);
+}
+int batch_raster_blocks_per_cu(int cls, size_t lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_raster, 256, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_raster_kernel(cls), 256, lds) !=
+      hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }

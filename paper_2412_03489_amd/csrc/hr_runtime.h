@@ -131,6 +131,13 @@ struct QueryBufs {
   void* acc;
 };
 QueryBufs carve(const QueryPlan& p, void* base);
+// The kernels of one planned query on stream s, its workspace carved as qb;
+// theta, v (or nullptr) and the output are device pointers.  S and shape pick
+// the raster configuration (0: library choice).  With timing, the launches
+// are timed under the per-query kernel names (ctx->stream must be s).
+void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBufs& qb,
+                  const double* d_theta, const double* d_v, double* d_out, int S, int shape,
+                  bool timing);
 
 }  // namespace rt
 }  // namespace hr
