@@ -317,12 +317,14 @@ __global__ __launch_bounds__(256) void k_batch_pt(const BatchTable* __restrict__
     const int x = (home + k) & 7;
     const uint64_t nitems = W.items[x];
     const uint64_t sb = W.seg_off[x], se = W.seg_off[x + 1];
-    for (;;) {
-      if (threadIdx.x == 0) s_item = atomicAdd(&W.ctr[x], 1ull);
-      __syncthreads();
-      const uint64_t it = uniform64(s_item);
-      __syncthreads();
-      if (it >= nitems) break;
+    if (threadIdx.x == 0) s_item = atomicAdd(&W.ctr[x], 1ull);
+    __syncthreads();
+    uint64_t it = uniform64(s_item);
+    __syncthreads();
+    while (it < nitems) {
+      // the next item is claimed before this one's work (as in the rasteriser)
+      unsigned long long next = 0;
+      if (threadIdx.x == 0) next = atomicAdd(&W.ctr[x], 1ull);
       uint64_t lo = sb, hi = se - 1;
       while (lo < hi) {
         const uint64_t mid = (lo + hi + 1) >> 1;
@@ -345,6 +347,10 @@ __global__ __launch_bounds__(256) void k_batch_pt(const BatchTable* __restrict__
       const int nd = (int)min((uint64_t)S, e.streams * e.N - d0);
       pt_block<NR>(P, (const double*)qp[0], (const double*)qp[1], (const double*)qp[2],
                    (const float*)qp[3], e, tiles_x, tiles, tile, d0, nd, partial, s_part);
+      if (threadIdx.x == 0) s_item = next;
+      __syncthreads();
+      it = uniform64(s_item);
+      __syncthreads();
     }
   }
 }

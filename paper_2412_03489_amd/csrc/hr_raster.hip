@@ -504,12 +504,15 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restri
     const int x = (home + k) & 7;
     const uint64_t nitems = W.items[x];
     const uint64_t sb = W.seg_off[x], se = W.seg_off[x + 1];
-    for (;;) {
-      if (threadIdx.x == 0) s_item = atomicAdd(&W.ctr[x], 1ull);
-      __syncthreads();
-      const uint64_t it = uniform64(s_item);
-      __syncthreads();   // every thread has read s_item before it is reused
-      if (it >= nitems) break;
+    if (threadIdx.x == 0) s_item = atomicAdd(&W.ctr[x], 1ull);
+    __syncthreads();
+    uint64_t it = uniform64(s_item);
+    __syncthreads();   // every thread has read s_item before it is reused
+    while (it < nitems) {
+      // claim the next item now: the counter's round trip overlaps this
+      // item's work (the claimed item is this block's next, whatever it is)
+      unsigned long long next = 0;
+      if (threadIdx.x == 0) next = atomicAdd(&W.ctr[x], 1ull);
       // segment of the item: largest s in [sb, se) with seg[s].item0 <= it
       uint64_t lo = sb, hi = se - 1;
       while (lo < hi) {
@@ -526,6 +529,10 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restri
       const uint64_t r0 = chunk * (uint64_t)a.S;
       const int nr = (int)min((uint64_t)a.S, a.R - r0);
       raster_block<C, kOneGroup, false, ConstRasterQuery>(a, tile, r0, nr, smem);
+      if (threadIdx.x == 0) s_item = next;
+      __syncthreads();
+      it = uniform64(s_item);
+      __syncthreads();
     }
   }
 }
