@@ -50,8 +50,8 @@ FLOP_PER_PIXEL = 12.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this SHA-256; reported as null once the source has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 467321769
-TRAFFIC_SOURCE_SHA256 = "85b4df68b6f8ef8c572a1ae612d97f62cf94968ada97afc5588cd46672dfe191"
+TRAFFIC_BYTES_PER_LAUNCH = 467524988
+TRAFFIC_SOURCE_SHA256 = "e4a70e06163ac9667c2328331c6c0f7d129752414a04449738062a8ee2db59e2"
 
 
 def raster_traffic():
