@@ -174,11 +174,13 @@ def uneven_section(P, ctx, reps):
 
 
 def serving_section(P, ctx, args):
-    """Newton optimisations arriving as a Poisson stream over the raster and
-    path-traced scenes: continuous-batching server vs plain per-query calls
-    served one at a time in arrival order.  A saturating run first (its plain
-    throughput is the plain capacity), then offered loads of 0.5, 0.8, 1.0 and
-    1.5 x that capacity."""
+    """Newton optimisations over the raster and path-traced scenes:
+    continuous-batching server vs plain per-query calls served one at a time
+    in the order queries become ready.  An open-loop saturating run first
+    (Poisson arrivals of 256 optimisations of one step each), then 256
+    closed-loop clients: with no think time (the plain capacity of their query
+    mix), and with think times offering 0.5, 0.8, 1.0 and 1.5 x that
+    capacity."""
     import workloads as WL
     from paper_2412_03489_amd import serving as SV
     wr = WL.disks32()
@@ -194,8 +196,8 @@ def serving_section(P, ctx, args):
     N = {"raster": args.serving_n_raster, "pt": args.serving_n_pt}
     cg = args.serving_cg
 
-    def clients(specs):
-        return SV.make_clients(specs, scenes, sigma, N, cg, full_cg=True)
+    def clients(specs, steps=1):
+        return SV.make_clients(specs, scenes, sigma, N, cg, steps=steps, full_cg=True)
 
     # warm both paths
     warm = WL.serving_clients(4, rate=1e6, base_seed=99)
@@ -213,22 +215,35 @@ def serving_section(P, ctx, args):
     out["saturated"] = {"arrival_rate_per_s": args.serving_rate, "plain": rnd(plain),
                         "served": rnd(served),
                         "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
-    # offered-load sweep against the plain capacity (queries/s)
-    cap = plain["queries_per_s"]
-    per_client = (1 + cg + 2) / 2.0
+    # closed loop: the clients all start together and keep taking Newton
+    # steps, thinking an exponential time before each query; no query becomes
+    # ready after the measurement window.  Every client issues queries at the
+    # same rate, so path-traced queries are half the mix (a third of the open
+    # loop's share of raster work): the plain capacity of this mix is measured
+    # first, with no think time, and the offered loads are scaled from it
+    # (think mean = clients / (load x capacity)).
+    win = args.serving_window
+    nc = args.serving_sweep_clients
+    keep = ("queries", "queries_per_s", "p50_ms", "p99_ms", "by_kind")
+    specs = WL.serving_clients(nc, rate=1e6, base_seed=3000)
+    log(f"bench: serving closed loop, {nc} clients, no think time (capacity)")
+    pl = SV.run_plain(ctx, clients(specs, 10 ** 6), think_ms=0.0, window_s=win)
+    sv = SV.run_served(ctx, clients(specs, 10 ** 6), think_ms=0.0, window_s=win)
+    cap = pl["queries_per_s"]
+    out["closed_loop_saturated"] = {"clients": nc, "window_s": win,
+                                    "plain": rnd({k: pl[k] for k in keep}),
+                                    "served": rnd({k: sv[k] for k in keep})}
     sweep = []
     for rho in (0.5, 0.8, 1.0, 1.5):
-        rate = rho * cap / per_client
-        specs = WL.serving_clients(args.serving_sweep_clients, rate=rate, base_seed=3000)
-        log(f"bench: serving load {rho} x plain capacity ({rate:.1f} clients/s)")
-        pl = SV.run_plain(ctx, clients(specs))
-        sv = SV.run_served(ctx, clients(specs))
-        keep = ("queries", "queries_per_s", "p50_ms", "p99_ms", "by_kind")
-        sweep.append({"load": rho, "clients_per_s": round(rate, 2),
+        think_ms = 1e3 * nc / (rho * cap)
+        log(f"bench: serving closed loop, load {rho} x plain capacity (think {think_ms:.0f} ms)")
+        pl = SV.run_plain(ctx, clients(specs, 10 ** 6), think_ms=think_ms, window_s=win)
+        sv = SV.run_served(ctx, clients(specs, 10 ** 6), think_ms=think_ms, window_s=win)
+        sweep.append({"load": rho, "think_ms": round(think_ms, 1), "window_s": win,
                       "plain": {k: pl[k] for k in keep}, "served": {k: sv[k] for k in keep}})
-    out["load_sweep"] = [{k: (rnd(v) if isinstance(v, dict) else v) for k, v in x.items()}
-                         for x in sweep]
-    out["plain_capacity_qps"] = round(cap, 2)
+    out["closed_loop_sweep"] = [{k: (rnd(v) if isinstance(v, dict) else v) for k, v in x.items()}
+                                for x in sweep]
+    out["closed_loop_plain_capacity_qps"] = round(cap, 2)
     sr.close()
     sp.close()
     return out
@@ -468,7 +483,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serving-clients", type=int, default=256)
     ap.add_argument("--serving-rate", type=float, default=512.0)
-    ap.add_argument("--serving-sweep-clients", type=int, default=96)
+    ap.add_argument("--serving-sweep-clients", type=int, default=256)
+    ap.add_argument("--serving-window", type=float, default=4.0,
+                    help="seconds of closed-loop traffic per offered load")
     ap.add_argument("--serving-n-raster", type=int, default=16384)
     ap.add_argument("--serving-n-pt", type=int, default=2048)
     ap.add_argument("--serving-cg", type=int, default=10)

@@ -1,10 +1,13 @@
-"""Serving load: Newton optimisations arriving as a Poisson stream, each a
-closed loop of estimator queries, run either through the continuous-batching
-server (hr_server) or as plain per-query calls served one at a time in
-arrival order.  Both modes issue the same queries (results are the same bits
-either way, so every client follows the same trajectory) and report queries
-per second over the run with p50 / p99 query latency (submission to result
-on the host).
+"""Serving load: Newton optimisations, each a loop of dependent estimator
+queries, run either through the continuous-batching server (hr_server) or as
+plain per-query calls served one at a time in the order they become ready.
+Two client models: open loop (clients arrive as a Poisson stream and issue
+their queries back to back) and closed loop (all clients start together and
+wait an exponential think time before each query, drawn from the client's
+own seeded generator).  Both modes issue the same queries (results are the
+same bits either way, so every client follows the same trajectory) and report
+queries per second over the run with p50 / p99 query latency (from the
+moment a query is ready to its result, on the host).
 
 Client step (the Newton step of section "Newton's method"):
   raster (96 params): gradient, then `cg_iters` HVPs of a conjugate-gradient
@@ -15,7 +18,6 @@ Client step (the Newton step of section "Newton's method"):
 """
 from __future__ import annotations
 
-import collections
 import heapq
 import time
 
@@ -39,7 +41,12 @@ class NewtonClient:
         self.theta = np.array(spec.theta0, dtype=np.float64)
         self.queries = 0
         self.step = 0
+        self._think = np.random.default_rng(spec.seed + 7919)
         self._start_step()
+
+    def think_s(self, mean_s):
+        """The next exponential think time (seconds) of this client."""
+        return float(self._think.exponential(mean_s))
 
     def _seed(self):
         return self.spec.seed * 1000 + self.step
@@ -137,15 +144,31 @@ def make_clients(specs, scenes, sigma, N, cg_iters, steps=1, full_cg=False):
                          full_cg) for s in specs]
 
 
+def _first_ready(clients, think_ms, window_s=None):
+    """(ready time in seconds from the start, order, client) of each first
+    query that falls within the window."""
+    ev = []
+    for k, c in enumerate(sorted(clients, key=lambda c: c.spec.arrival)):
+        t = c.spec.arrival if think_ms is None else c.think_s(think_ms / 1e3)
+        if window_s is None or t <= window_s:
+            ev.append((t, k, c))
+    heapq.heapify(ev)
+    return ev
+
+
 def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_bytes=16 << 30,
-               use_graph=True):
-    """All clients through one continuous-batching server."""
+               use_graph=True, think_ms=None, window_s=None):
+    """All clients through one continuous-batching server.  think_ms None: open
+    loop (queries back to back after the client's arrival); else closed loop
+    with exponential think times of that mean before every query.  window_s:
+    no query becomes ready after this time (the clients stop; the ones in
+    flight finish)."""
     srv = Server(ctx, slots=slots, max_batch=max_batch, max_batch_ms=max_batch_ms,
                  memory_bytes=memory_bytes, use_graph=use_graph)
-    arrivals = collections.deque(sorted(clients, key=lambda c: c.spec.arrival))
+    ready = _first_ready(clients, think_ms, window_s)
+    order = len(clients)
     live = {}
     lat = []
-    sizes = []
     t0 = time.perf_counter()
 
     def submit(c, ts):
@@ -155,12 +178,12 @@ def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_byt
                        q.pop("N"), q.pop("seed"), v=q.pop("v", None))
         live[t] = (c, ts, label)
 
-    while arrivals or live:
+    while ready or live:
         now = time.perf_counter() - t0
-        while arrivals and arrivals[0].spec.arrival <= now:
-            c = arrivals.popleft()
-            submit(c, t0 + c.spec.arrival)
-        wait = -1.0 if not arrivals else max(0.0, (arrivals[0].spec.arrival - now) * 1e3)
+        while ready and ready[0][0] <= now:
+            tr, _, c = heapq.heappop(ready)
+            submit(c, t0 + tr)
+        wait = -1.0 if not ready else max(0.0, (ready[0][0] - now) * 1e3)
         if not live:
             time.sleep(wait / 1e3)
             continue
@@ -171,45 +194,49 @@ def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_byt
         c, ts, label = live.pop(t)
         tn = time.perf_counter()
         lat.append((label, (tn - ts) * 1e3))
-        sizes.append(st["batch_size"])
         if c.on_result(out):
-            submit(c, tn)
+            nxt = tn - t0 if think_ms is None else tn - t0 + c.think_s(think_ms / 1e3)
+            if window_s is None or nxt <= window_s:
+                if think_ms is None:
+                    submit(c, tn)
+                else:
+                    heapq.heappush(ready, (nxt, order, c))
+                    order += 1
     total = time.perf_counter() - t0
     s = srv.stats()
     srv.close()
     return _summary(lat, total, {"batches": s["batches"],
-                                           "mean_batch": s["mean_batch"],
-                                           "slots": slots, "max_batch": max_batch,
-                                           "max_batch_ms": max_batch_ms})
+                                 "mean_batch": s["mean_batch"],
+                                 "slots": slots, "max_batch": max_batch,
+                                 "max_batch_ms": max_batch_ms})
 
 
-def run_plain(ctx, clients):
+def run_plain(ctx, clients, think_ms=None, window_s=None):
     """The same clients, each query a plain single-query call, served one at a
-    time in arrival order."""
-    arrivals = collections.deque(sorted(clients, key=lambda c: c.spec.arrival))
-    queue = []   # (submission time, order, client): served oldest first
-    order = 0
+    time in the order the queries become ready (think_ms, window_s as in
+    run_served)."""
+    ready = _first_ready(clients, think_ms, window_s)
+    order = len(clients)
     lat = []
     t0 = time.perf_counter()
-    while arrivals or queue:
+    while ready:
         now = time.perf_counter() - t0
-        while arrivals and arrivals[0].spec.arrival <= now:
-            c = arrivals.popleft()
-            heapq.heappush(queue, (t0 + c.spec.arrival, order, c))
-            order += 1
-        if not queue:
-            time.sleep(max(0.0, arrivals[0].spec.arrival - now))
+        tr, _, c = ready[0]
+        if tr > now:
+            time.sleep(tr - now)
             continue
-        ts, _, c = heapq.heappop(queue)
+        heapq.heappop(ready)
         q = c.query()
         label = _label(c, q)
         kind = q.pop("kind")
         out = estimate(kind, q.pop("scene"), q.pop("theta"), q.pop("sigma"), q.pop("N"),
                        q.pop("seed"), v=q.pop("v", None))
         tn = time.perf_counter()
-        lat.append((label, (tn - ts) * 1e3))
+        lat.append((label, (tn - (t0 + tr)) * 1e3))
         if c.on_result(out):
-            heapq.heappush(queue, (tn, order, c))
-            order += 1
+            nxt = tn - t0 if think_ms is None else tn - t0 + c.think_s(think_ms / 1e3)
+            if window_s is None or nxt <= window_s:
+                heapq.heappush(ready, (nxt, order, c))
+                order += 1
     total = time.perf_counter() - t0
     return _summary(lat, total)
