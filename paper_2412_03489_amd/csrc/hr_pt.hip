@@ -13,6 +13,12 @@
 // words and the primary ray are generated once per (pixel, spp) and traced
 // against each render's light/sphere placement.  Loss partials per
 // (render, tile) as in the rasteriser.
+//
+// Arithmetic: FP32 with the hardware's one-instruction reciprocal, square
+// root, reciprocal square root and sine/cosine (the bounce angle is 2 pi u,
+// and the hardware sine takes its argument in revolutions), within a few ulp;
+// the path semantics are those of the FP64 reference.  Reciprocals of the
+// sphere radii and the light's Le side^2 / pi are precomputed per scene.
 #include <cstring>
 
 #include "hr_device.h"
@@ -27,7 +33,6 @@ constexpr int kMaxSpheres = 16;
 constexpr int kPtMaxS = 32;
 constexpr float kEps = 1e-4f;
 constexpr float kTmin = 1e-6f;
-constexpr float kPiF = 3.14159265358979323846f;
 
 struct PTConst {
   float eye[3], fwd[3], right[3], up[3];
@@ -35,7 +40,11 @@ struct PTConst {
   float side, Le, ground[3];
   int ns, W, H, spp;
   float sph[kMaxSpheres][7];       // centre[3], radius, albedo[3]; centre of 0 from theta
+  float inv_r[kMaxSpheres];        // 1 / radius
+  float k_nee;                     // Le side^2 / pi
 };
+
+__device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
 
 struct V3 { float x, y, z; };
 __host__ __device__ __forceinline__ V3 v3(float x, float y, float z) { return {x, y, z}; }
@@ -59,7 +68,7 @@ __device__ __forceinline__ float hit_sphere(V3 o, V3 d, V3 c, float r) {
   const V3 l = oc - d * b;
   const float disc = fmaf(r, r, -dot3(l, l));
   if (disc < 0.0f) return -1.0f;
-  const float sq = sqrtf(disc);
+  const float sq = __builtin_amdgcn_sqrtf(disc);
   float t = -b - sq;
   if (!(t > kTmin)) t = -b + sq;
   return t > kTmin ? t : -1.0f;
@@ -75,9 +84,10 @@ __device__ int intersect(const Consts& P, const Placement& pl, V3 o, V3 d, float
     if (t > 0.0f && t < best) { best = t; id = i; }
   }
   if (d.y != 0.0f) {
-    const float t = -o.y / d.y;
+    const float idy = rcp_f(d.y);
+    const float t = -o.y * idy;
     if (t > kTmin && t < best) { best = t; id = P.ns; }
-    const float tl = (pl.light.y - o.y) / d.y;
+    const float tl = (pl.light.y - o.y) * idy;
     if (tl > kTmin && tl < best) {
       const V3 p = o + d * tl;
       const float half = 0.5f * P.side;
@@ -96,7 +106,7 @@ __device__ bool occluded(const Consts& P, const Placement& pl, V3 o, V3 d, float
     if (t > 0.0f && t < tmax) return true;
   }
   if (d.y != 0.0f) {
-    const float t = -o.y / d.y;
+    const float t = -o.y * rcp_f(d.y);
     if (t > kTmin && t < tmax) return true;
   }
   return false;
@@ -108,19 +118,20 @@ __device__ float nee(const Consts& P, const Placement& pl, V3 o, V3 n, float u1,
   const V3 y = v3(pl.light.x + (u1 - 0.5f) * P.side, pl.light.y, pl.light.z + (u2 - 0.5f) * P.side);
   const V3 wv = y - o;
   const float d2 = dot3(wv, wv);
-  const float dist = sqrtf(d2);
-  const V3 wi = wv * (1.0f / dist);
+  const float idist = __builtin_amdgcn_rsqf(d2);
+  const float dist = d2 * idist;
+  const V3 wi = wv * idist;
   const float cx = dot3(n, wi), cl = wi.y;
   if (!(cx > 0.0f) || !(cl > 0.0f)) return 0.0f;
   if (occluded(P, pl, o, wi, dist)) return 0.0f;
-  return P.Le * cx * cl * P.side * P.side / d2 / kPiF;
+  return P.k_nee * cx * cl * (idist * idist);
 }
 
 template <class Consts>
 __device__ __forceinline__ void surface(const Consts& P, const Placement& pl, int id, V3 x, V3& n,
                                         V3& alb) {
   if (id < P.ns) {
-    n = (x - sph_c(P, pl, id)) * (1.0f / P.sph[id][3]);
+    n = (x - sph_c(P, pl, id)) * P.inv_r[id];
     alb = v3(P.sph[id][4], P.sph[id][5], P.sph[id][6]);
   } else {
     n = v3(0.0f, 1.0f, 0.0f);
@@ -143,15 +154,15 @@ __device__ V3 radiance(const Consts& P, const Placement& pl, V3 eye, V3 d, const
   const float e1 = nee(P, pl, o1, n, u[2], u[3]);
   V3 L = alb * e1;
   // cosine-weighted direction (Malley) in the basis of Duff et al. 2017
-  const float rr = sqrtf(u[4]), ph = 2.0f * kPiF * u[5];
+  const float rr = __builtin_amdgcn_sqrtf(u[4]);
   const float sgn = copysignf(1.0f, n.z);
-  const float a = -1.0f / (sgn + n.z);
+  const float a = -rcp_f(sgn + n.z);   // |sgn + n.z| >= 1
   const float bb = n.x * n.y * a;
   const V3 b1 = v3(1.0f + sgn * n.x * n.x * a, sgn * bb, -sgn * n.x);
   const V3 b2 = v3(bb, sgn + n.y * n.y * a, -n.y);
-  float sp, cp;
-  sincosf(ph, &sp, &cp);
-  const V3 dir = b1 * (rr * cp) + b2 * (rr * sp) + n * sqrtf(1.0f - u[4]);
+  // angle 2 pi u[5]: the hardware sine and cosine take revolutions
+  const float sp = __builtin_amdgcn_sinf(u[5]), cp = __builtin_amdgcn_cosf(u[5]);
+  const V3 dir = b1 * (rr * cp) + b2 * (rr * sp) + n * __builtin_amdgcn_sqrtf(1.0f - u[4]);
   float t2;
   const int id2 = intersect(P, pl, o1, dir, t2);
   if (id2 < 0 || id2 == P.ns + 1) return L;
@@ -174,13 +185,13 @@ __device__ __forceinline__ void path_uniforms(uint64_t seed, uint32_t s, uint32_
 
 template <class Consts>
 __device__ __forceinline__ V3 camera_dir(const Consts& P, int x, int y, float jx, float jy) {
-  const float sx = (2.0f * ((float)x + jx) / (float)P.W - 1.0f) * P.sx_scale;
-  const float sy = (1.0f - 2.0f * ((float)y + jy) / (float)P.H) * P.sy_scale;
+  const float sx = (2.0f * ((float)x + jx) * rcp_f((float)P.W) - 1.0f) * P.sx_scale;
+  const float sy = (1.0f - 2.0f * ((float)y + jy) * rcp_f((float)P.H)) * P.sy_scale;
   const V3 f = v3(P.fwd[0], P.fwd[1], P.fwd[2]);
   const V3 r = v3(P.right[0], P.right[1], P.right[2]);
   const V3 up = v3(P.up[0], P.up[1], P.up[2]);
   const V3 d = f + r * sx + up * sy;
-  return d * (1.0f / sqrtf(dot3(d, d)));
+  return d * __builtin_amdgcn_rsqf(dot3(d, d));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -388,8 +399,11 @@ PTConst make_const(const PTScene& s, int spp) {
   P.ground[0] = d[9]; P.ground[1] = d[10]; P.ground[2] = d[11];
   P.ns = s.nspheres;
   P.W = s.W; P.H = s.H; P.spp = spp;
-  for (int i = 0; i < s.nspheres && i < kMaxSpheres; ++i)
+  for (int i = 0; i < s.nspheres && i < kMaxSpheres; ++i) {
     for (int k = 0; k < 7; ++k) P.sph[i][k] = d[23 + 7 * i + k];
+    P.inv_r[i] = 1.0f / P.sph[i][3];
+  }
+  P.k_nee = (float)((double)P.Le * P.side * P.side / 3.14159265358979323846);
   return P;
 }
 
