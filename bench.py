@@ -36,12 +36,14 @@ sys.path.insert(0, ROOT)
 METRIC = "Hessian-estimator throughput (perturbed Mpix/s) + p50/p99 HVP-query latency"
 PEAK_FP32_TFLOPS = 157.3          # MI355X fp32 vector (published)
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E (published)
-# path tracer, per path of one render (FMA = 2 FLOP, counted from the tracer's
-# code): 2 x (closest hit over 4 spheres, plane, light ~130) + 2 x (light
-# sample + shadow test ~142) + surface frames, bounce direction and
-# throughput ~90; plus ~25 square roots, reciprocals and sines not counted.
-# The camera ray and random words are shared by a draw's renders.
-PT_FLOP_PER_PATH = 630.0
+# path tracer, FP32 arithmetic per path of one render (FMA = 2 FLOP): the
+# FMA/ADD/MUL instruction counters of the Hessian launch per path at full
+# lanes.  A path that takes every branch (two closest-hit searches over 4
+# spheres, plane and light, two light samples with shadow tests, frames,
+# bounce, throughput) is ~550 by hand; rays that leave the scene and shadow
+# tests that stop at their first blocker make the average path cheaper.
+# Square roots, reciprocals and sines (one instruction each) are not counted.
+PT_FLOP_PER_PATH = 434.0
 # algorithmic work per perturbed pixel of the bbox-culled rasteriser + loss:
 # 9 FLOP for the 3-channel squared error, 5 FLOP per disk test times the
 # 0.593 disks whose bounding box holds an average pixel (32 disks, E[r^2]).
