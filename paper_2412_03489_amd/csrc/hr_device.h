@@ -29,9 +29,11 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint32_t a = 0xD2511F53u, b = 0xCD9E8D57u;
-    uint32_t hi_a = __umulhi(a, c0), lo_a = a * c0;
-    uint32_t hi_b = __umulhi(b, c2), lo_b = b * c2;
+    // each 32 x 32 -> 64-bit product as one multiply (v_mad_u64_u32) rather
+    // than separate high and low halves
+    const uint64_t pa = (uint64_t)0xD2511F53u * c0, pb = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+    const uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
     uint32_t n0 = hi_b ^ c1 ^ k0;
     uint32_t n2 = hi_a ^ c3 ^ k1;
     c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
