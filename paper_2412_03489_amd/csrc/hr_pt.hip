@@ -100,16 +100,19 @@ __device__ int intersect(const Consts& P, const Placement& pl, V3 o, V3 d, float
 
 template <class Consts>
 __device__ bool occluded(const Consts& P, const Placement& pl, V3 o, V3 d, float dist) {
+  // every blocker is tested (no per-lane early exit: the wave would run on
+  // until its last lane finished anyway)
   const float tmax = dist - kEps;
+  bool hit = false;
   for (int i = 0; i < P.ns; ++i) {
     const float t = hit_sphere(o, d, sph_c(P, pl, i), P.sph[i][3]);
-    if (t > 0.0f && t < tmax) return true;
+    hit = hit || (t > 0.0f && t < tmax);
   }
   if (d.y != 0.0f) {
     const float t = -o.y * rcp_f(d.y);
-    if (t > kTmin && t < tmax) return true;
+    hit = hit || (t > kTmin && t < tmax);
   }
-  return false;
+  return hit;
 }
 
 // Le cos_x cos_l A / (pi d^2) for a uniform light point, visibility included
