@@ -65,3 +65,45 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     with pytest.raises(RuntimeError, match="missing"):
         P.lib()
     importlib.reload(P)
+
+
+# ctypes mirror of each public struct in the binding, by C type name
+_STRUCTS = {"hr_opts": "Opts", "hr_ncg_opts": "NcgOpts", "hr_ncg_report": "NcgReport",
+            "hr_optim_opts": "OptimOpts", "hr_query": "Query", "hr_batch_opts": "BatchOpts",
+            "hr_batch_report": "BatchReport", "hr_server_opts": "ServerOpts",
+            "hr_query_stats": "QueryStats", "hr_server_stats": "ServerStats"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct (gcc, no GPU)."""
+    import ctypes
+    import re
+    import subprocess
+
+    import paper_2412_03489_amd as P
+    hdr = open(os.path.join(ROOT, "include", "hrest.h")).read()
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "hrest.h"', "int main(void) {"]
+    for cname, pname in _STRUCTS.items():
+        py = getattr(P, pname)
+        assert re.search(r"\}\s*" + cname + r"\s*;", hdr), cname
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, pname in _STRUCTS.items():
+        py = getattr(P, pname)
+        assert ctypes.sizeof(py) == got[(cname, "size")], cname
+        for fname, _ in py._fields_:
+            assert getattr(py, fname).offset == got[(cname, fname)], (cname, fname)
