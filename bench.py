@@ -369,8 +369,9 @@ def main_section(P, ctx, args):
 
 def configs_section(P, ctx, reps):
     """The other workloads of the estimator: the one-disk gradient + Hessian
-    (64x64, N = 4096) and the path-traced full 6x6 Hessian (128x128, 4 spp,
-    N = 8192), each timed as host call to result."""
+    (64x64, N = 4096; mean per pair and p50/p99 latency per call) and the
+    path-traced full 6x6 Hessian (128x128, 4 spp, N = 8192), each timed as
+    host call to result."""
     import workloads as WL
     out = {}
     w = WL.one_disk()
@@ -387,8 +388,19 @@ def configs_section(P, ctx, reps):
         one_disk()
     dt = (time.perf_counter() - t0) / reps
     renders = 2 * P.n_renders("grad", w.n, w.N)
+    # latency of single calls (host pointer in, result on the host), 200 each
+    lat = {}
+    for kind in ("grad", "hess"):
+        xs = []
+        for i in range(200):
+            t1 = time.perf_counter()
+            P.estimate(kind, sc, w.theta0, w.sigma, w.N, w.seed + i)
+            xs.append((time.perf_counter() - t1) * 1e3)
+        lat[kind] = {"p50_ms": round(float(np.percentile(xs, 50)), 4),
+                     "p99_ms": round(float(np.percentile(xs, 99)), 4)}
     out["one_disk_grad_hess"] = {"ms": round(dt * 1e3, 3), "renders": renders,
-                                 "Mpix_per_s": round(renders * w.pixels / dt / 1e6, 1)}
+                                 "Mpix_per_s": round(renders * w.pixels / dt / 1e6, 1),
+                                 "latency": lat}
     sc.close()
     wp = WL.pt_spheres()
     s0 = P.Scene.pt(ctx, wp.W, wp.H, wp.spp, wp.desc, np.zeros((wp.H, wp.W, 3), np.float32))

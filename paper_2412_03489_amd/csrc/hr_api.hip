@@ -50,6 +50,25 @@ hr_status ensure(hr_ctx* ctx, void** buf, size_t* have, size_t need) {
   return HR_OK;
 }
 
+hr_status ensure_host(hr_ctx* ctx, void** buf, size_t* have, size_t need) {
+  if (need <= *have) return HR_OK;
+  if (*buf) {
+    HR_HIP(hipStreamSynchronize(ctx->stream));
+    HR_HIP(hipHostFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+  }
+  size_t sz = align256(need + need / 4);
+  hipError_t e = hipHostMalloc(buf, sz, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    (void)hipGetLastError();
+    return fail(HR_ENOMEM, "pinned host allocation of " + std::to_string(sz) + " bytes failed");
+  }
+  *have = sz;
+  return HR_OK;
+}
+
 hr_status drain_timers(hr_ctx* ctx) {
   for (auto& p : ctx->pending) {
     HR_HIP(hipEventSynchronize(p.b));
@@ -267,17 +286,26 @@ hr_status run_host(hr_scene* sc, int what, const double* theta, double sigma, ui
       return HR_OK;
     }
   }
-  hr_status st = ensure(ctx, &ctx->stage, &ctx->stage_bytes, (2 * (size_t)n + nout) * 8);
+  const size_t bytes = (2 * (size_t)n + nout) * 8;
+  hr_status st = ensure(ctx, &ctx->stage, &ctx->stage_bytes, bytes);
+  if (!st) st = ensure_host(ctx, &ctx->hstage, &ctx->hstage_bytes, bytes);
   if (st) return st;
+  // theta and v go up, and the result comes down, through the pinned mirror
+  // (the previous call's copies have completed: every call ends synchronised)
+  double* h_in = (double*)ctx->hstage;
   double* d_theta = (double*)ctx->stage;
   double* d_v = d_theta + n;
   double* d_out = d_v + n;
-  HR_HIP(hipMemcpyAsync(d_theta, theta, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
-  if (v) HR_HIP(hipMemcpyAsync(d_v, v, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+  memcpy(h_in, theta, (size_t)n * 8);
+  if (v) memcpy(h_in + n, v, (size_t)n * 8);
+  HR_HIP(hipMemcpyAsync(d_theta, h_in, (size_t)n * (v ? 16 : 8), hipMemcpyHostToDevice,
+                        ctx->stream));
   st = run_est(sc, what, d_theta, sigma, N, seed, v ? d_v : nullptr, o, d_out, o.dbg_loss, o.dbg_tau);
   if (st) return st;
-  HR_HIP(hipMemcpyAsync(out, d_out, nout * 8, hipMemcpyDeviceToHost, ctx->stream));
+  double* h_out = h_in + 2 * (size_t)n;
+  HR_HIP(hipMemcpyAsync(h_out, d_out, nout * 8, hipMemcpyDeviceToHost, ctx->stream));
   HR_HIP(hipStreamSynchronize(ctx->stream));
+  memcpy(out, h_out, nout * 8);
   return HR_OK;
 }
 
@@ -340,6 +368,7 @@ void hr_ctx_destroy(hr_ctx* ctx) {
   ctx->scenes.clear();
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->stage) (void)hipFree(ctx->stage);
+  if (ctx->hstage) (void)hipHostFree(ctx->hstage);
   if (ctx->cg) (void)hipFree(ctx->cg);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;

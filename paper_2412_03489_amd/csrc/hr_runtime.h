@@ -23,6 +23,8 @@ struct hr_ctx {
   size_t ws_bytes = 0;
   void* stage = nullptr;      // host-call staging: theta, v, outputs
   size_t stage_bytes = 0;
+  void* hstage = nullptr;     // pinned host mirror of the staging (async copies)
+  size_t hstage_bytes = 0;
   void* cg = nullptr;         // Newton-CG vectors and state
   size_t cg_bytes = 0;
   uint64_t budget = 64ull << 30;
@@ -85,6 +87,8 @@ hr_opts resolve(const hr_opts* o);
 // Grows a device buffer to at least `need` bytes (synchronising the context
 // stream before freeing the old one).
 hr_status ensure(hr_ctx* ctx, void** buf, size_t* have, size_t need);
+// grow-only pinned host buffer (hipHostMalloc)
+hr_status ensure_host(hr_ctx* ctx, void** buf, size_t* have, size_t need);
 
 // Records `fn`'s launches between two events on the context stream when
 // timing is enabled.
