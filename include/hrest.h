@@ -342,8 +342,9 @@ typedef struct {
   uint64_t queries;         /* queries in the last run                          */
   uint64_t raster_items;    /* work items of the persistent rasteriser          */
   uint64_t pt_items;        /* work items of the persistent path tracer         */
-  int raster_blocks;        /* persistent grid sizes                            */
-  int pt_blocks;
+  int raster_blocks;        /* persistent grid size of the rasteriser (largest
+                               over the raster classes launched)              */
+  int pt_blocks;            /* persistent grid size of the path tracer         */
   uint64_t workspace_bytes; /* device workspace of the batch                    */
   uint64_t lds_bytes;       /* dynamic LDS of the persistent rasteriser         */
   int graph;                /* 1 if the launches ran as a graph replay; a batch
