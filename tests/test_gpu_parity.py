@@ -456,6 +456,16 @@ def test_errors_and_edge_cases(P, ctx, quad_pair):
     with pytest.raises(P.HrError, match="EUNSUPPORTED"):
         P.estimate("hess", gsc, th, 0.1, 10, 1, sampler=3)
     assert np.array_equal(P.estimate("hvp", gsc, th, 0.1, 10, 1, v=np.zeros(3)), np.zeros(3))
+    # an option outside its documented values is refused at the boundary
+    import ctypes as C
+    o = P.make_opts()
+    o.hess_mix_n2 = 2
+    H = np.zeros((3, 3))
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    assert P.lib().hr_est_hessian(gsc.h, dp(th), 0.1, 10, 1, C.byref(o), dp(H)) == -1   # EINVAL
+    o.hess_mix_n2 = 0
+    o.raster_tile = 7
+    assert P.lib().hr_est_hessian(gsc.h, dp(th), 0.1, 10, 1, C.byref(o), dp(H)) == -1
     c2 = P.Context(0)
     try:
         c2.set_memory_budget(1024)

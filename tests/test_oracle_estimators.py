@@ -332,6 +332,14 @@ def test_invalid_arguments_rejected(orc, quad):
         orc.estimate("grad", sc, [np.nan, 0.0], 0.1, 10, 1)
     with pytest.raises(ValueError):
         orc.estimate("hvp_limit", sc, [0.0, 0.0], 0.1, 10, 1, v=[1.0, 0.0], sampler=1)
+    # the mixture flag takes 0 or 1 only
+    import ctypes as C
+    o = orc._opts(0, True, 0.1, 1, 0, None)
+    o.hess_mix_n2 = 2
+    H = np.zeros((2, 2))
+    th = np.zeros(2)
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    assert orc.lib().orc_est_hessian(sc.h, dp(th), 0.1, 10, 1, C.byref(o), dp(H)) == -1
 
 
 def test_modified_cg_equals_steihaug_on_psd_quadratic(orc):
