@@ -40,8 +40,8 @@ double predict_ms(const QueryPlan& p) {
   const hr_scene* sc = p.sc;
   const double R = (double)p.e.R;
   double ms = 0.02;
-  if (sc->kind == kDisks) ms += R * sc->W * sc->H / 2.0e9;
-  else if (sc->kind == kPT) ms += R * sc->W * sc->H * sc->spp / 6.0e7;
+  if (sc->kind == kDisks) ms += R * sc->W * sc->H / 2.5e9;
+  else if (sc->kind == kPT) ms += R * sc->W * sc->H * sc->spp / 8.0e7;
   else ms += R * p.e.n * p.e.n / 1.0e9;
   ms += (double)p.e.streams * (double)p.e.N * (double)p.e.nout / 2.0e8;
   return ms;
