@@ -50,6 +50,8 @@ def scenes(P, ctx):
     out["ragged"] = (wr, gpu_disks(ctx, wr, disk_target(wr)))
     w4 = small_disks(W=40, H=70, D=12, C=4, seed=5)
     out["c4"] = (w4, gpu_disks(ctx, w4, disk_target(w4)))
+    w2 = small_disks(W=33, H=47, D=9, C=2, seed=6)
+    out["c2"] = (w2, gpu_disks(ctx, w2, disk_target(w2)))
     wp = WL.pt_spheres()
     tgt = pt_target(wp, spp=64, W=32, H=24)
     out["pt"] = (wp, P.Scene.pt(ctx, 32, 24, 2, wp.desc, tgt))
@@ -68,6 +70,7 @@ def mixed_queries(scenes):
     wp, sp = scenes["pt"]
     _, sq = scenes["quad"]
     _, sn = scenes["neggauss"]
+    w2, s2 = scenes["c2"]
     vr = wr.v / np.linalg.norm(wr.v)
     vp = np.array([1.0, 0.2, -0.5, 0.3, 0.0, 0.7])
     return [
@@ -91,6 +94,7 @@ def mixed_queries(scenes):
              hess_mix_n2=True),
         dict(scene=sp, kind="hvp_limit", theta=wp.theta0, sigma=wp.sigma, N=16, seed=14, v=vp,
              hess_mix_n2=True),
+        dict(scene=s2, kind="grad", theta=w2.theta0, sigma=0.02, N=150, seed=15),
     ]
 
 
@@ -145,7 +149,7 @@ def test_batch_graph_replays_match_eager(P, ctx, scenes):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("name", ["one_disk", "ragged", "c4"])
+@pytest.mark.parametrize("name", ["one_disk", "ragged", "c4", "c2"])
 def test_raster_tiles_and_samples_do_not_change_bits(P, ctx, scenes, name):
     w, sc = scenes[name]
     base = P.estimate("grad", sc, w.theta0, w.sigma, 200, 5)
