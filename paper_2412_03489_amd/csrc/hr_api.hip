@@ -189,8 +189,10 @@ void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBu
   double* vt = qb.vt;
   void* acc = qb.acc;
 
-  if (what == kHvp || what == kHvpLimit) launch_vnorm(s, e.n, d_v, u, vnorm);
-  T("sample", [&] { launch_sample(s, e, tau); });
+  if (what == kHvp || what == kHvpLimit)
+    T("sample", [&] { launch_sample_vnorm(s, e, tau, d_v, u, vnorm); });
+  else
+    T("sample", [&] { launch_sample(s, e, tau); });
   const int spb = S;
   if (sc->kind == kDisks) {
     DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};

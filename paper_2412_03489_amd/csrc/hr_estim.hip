@@ -94,10 +94,20 @@ __device__ __forceinline__ void vnorm_block(int n, const double* __restrict__ v,
   if (threadIdx.x == 0) *vnorm = nv;
 }
 
-__global__ __launch_bounds__(256) void k_vnorm(int n, const double* __restrict__ v,
-                                               double* __restrict__ u, double* __restrict__ vnorm) {
+// the draws of an HVP query, with |v| and v / |v| from block 0 first (one
+// launch instead of two; the same arithmetic as the batch sampling phase)
+__global__ __launch_bounds__(256) void k_sample_vnorm(int n, int K, int hessk, int mix_n2,
+                                                      int sampler, uint64_t N, uint64_t seed,
+                                                      double sg, uint64_t total,
+                                                      double* __restrict__ tau,
+                                                      const double* __restrict__ v,
+                                                      double* __restrict__ u,
+                                                      double* __restrict__ vnorm) {
   __shared__ double s_acc[256];
-  vnorm_block(n, v, u, vnorm, s_acc);
+  if (blockIdx.x == 0) vnorm_block(n, v, u, vnorm, s_acc);
+  for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
+       gid += (uint64_t)gridDim.x * blockDim.x)
+    sample_one(n, K, hessk, mix_n2, sampler, N, seed, sg, gid, tau);
 }
 
 // analytic scenes: render r in FP64
@@ -493,9 +503,13 @@ void launch_sample(hipStream_t st, const EstShape& e, double* tau) {
                      e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau);
 }
 
-void launch_vnorm(hipStream_t st, int n, const double* v, double* u, double* vnorm) {
-  hipLaunchKernelGGL(k_vnorm, dim3(1), dim3(256), 0, st, n, v, u, vnorm);
+void launch_sample_vnorm(hipStream_t st, const EstShape& e, double* tau, const double* v,
+                         double* u, double* vnorm) {
+  const uint64_t total = e.streams * e.N * (uint64_t)e.n;
+  hipLaunchKernelGGL(k_sample_vnorm, dim3(grid_for(total, 256)), dim3(256), 0, st, e.n, e.K,
+                     e.hessk, e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau, v, u, vnorm);
 }
+
 
 void launch_analytic(hipStream_t st, const EstShape& e, const AnalyticScene& s,
                      const double* theta, const double* tau, const double* u, double* f) {

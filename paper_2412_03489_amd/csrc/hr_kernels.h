@@ -29,7 +29,9 @@ struct EstShape {
 
 // ---- sampling ----
 void launch_sample(hipStream_t st, const EstShape& e, double* tau);
-void launch_vnorm(hipStream_t st, int n, const double* v, double* u, double* vnorm);
+// sampling with |v| and v / |v| of an HVP query computed by block 0
+void launch_sample_vnorm(hipStream_t st, const EstShape& e, double* tau, const double* v,
+                         double* u, double* vnorm);
 
 // ---- renders ----
 struct DiskScene {
