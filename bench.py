@@ -52,8 +52,8 @@ FLOP_PER_PIXEL = 12.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this SHA-256; reported as null once the source has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 467524988
-TRAFFIC_SOURCE_SHA256 = "e4a70e06163ac9667c2328331c6c0f7d129752414a04449738062a8ee2db59e2"
+TRAFFIC_BYTES_PER_LAUNCH = 467551414
+TRAFFIC_SOURCE_SHA256 = "8c2fe34896d7cd5378ace775a1fc33f2ed145cef019c8552fa21ad900f91e794"
 
 
 def raster_traffic():

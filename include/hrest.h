@@ -82,8 +82,10 @@ typedef struct {
   double hvp_rel_step;  /* HVP central-difference step h = hvp_rel_step * sigma (0.1) */
   int accum_fp64;       /* 0 (default): compensated-FP32 lobe sums; 1: FP64 sums        */
   int samples_per_block;/* renders per raster/path-tracer block; 0 = library choice     */
-  int raster_tile;      /* raster block of 16x16 wave tiles: 0 = library choice,
-                           1 = 32x32, 2 = 64x16, 3 = 16x64.  Neither this nor
+  int raster_tile;      /* raster block of 16x16 wave tiles: 1 = 32x32,
+                           2 = 64x16, 3 = 16x64; 0 = library choice: the shape
+                           that covers the image with the fewest blocks, ties
+                           going to 16x64, then 32x32.  Neither this nor
                            samples_per_block changes any result bit: every wave
                            tile's loss partial is summed in a fixed order.          */
   double* dbg_loss;     /* optional host buffer receiving every render's loss, in the
@@ -335,7 +337,8 @@ typedef struct {
                                block shape for every not yet tuned class of
                                disk scene (channels, disk count, image size
                                buckets) and keep the fastest in the context;
-                               0 (default): 64 renders per 32x32 block        */
+                               0 (default): 64 renders per block of the
+                               library's shape (raster_tile 0)                 */
 } hr_batch_opts;
 
 typedef struct {

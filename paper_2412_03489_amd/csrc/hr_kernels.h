@@ -68,8 +68,9 @@ struct RasterQuery {
   uint64_t R, r_base;
   RasterExact ex;
 };
-// block shapes: 0 or 1 = 32x32, 2 = 64x16, 3 = 16x64
-void raster_block_shape(int shape, int* bwx, int* bwy);
+// block shapes: 1 = 32x32, 2 = 64x16, 3 = 16x64, 0 = the fewest blocks for a
+// W x H image (ties: 16x64, then 32x32)
+void raster_block_shape(int shape, int W, int H, int* bwx, int* bwy);
 size_t raster_lds_bytes(int D, int S);
 int raster_max_samples();
 // fills the geometry fields of a RasterQuery (W, H must be set)

@@ -26,6 +26,8 @@
 // partials in LDS; after the S renders the block sums each wave's 16 in a
 // fixed order, giving one FP32 partial per (render, wave tile) -- the same
 // bits for any block shape and any S.
+#include <type_traits>
+
 #include "hr_device.h"
 #include "hr_kernels.h"
 
@@ -33,10 +35,11 @@ namespace hr {
 
 namespace {
 
+typedef const RasterExact __attribute__((address_space(4))) ConstExact;
 constexpr int kSub = 16;         // wave tile side (pixels)
 constexpr int kRows = 4;         // rows per lane
 constexpr int kMaxS = 64;        // renders per block (upper bound)
-constexpr int kQuadStride = 17;  // 16 quad partials per wave-render, padded
+constexpr int kFlush = 16;       // renders whose quad partials a wave holds in LDS
 constexpr float kFar = 1.0e18f;  // centre of pixels outside the image
 
 // Half-width of the band around r^2 outside which the FP32 and the FP64
@@ -133,7 +136,7 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
 
 // float4 slots of the colour table (see raster_block)
 __host__ __device__ inline int raster_table_slots(int D) {
-  return D <= 64 ? 4 * (D + 1) * 2 : D + 1;
+  return D <= 32 ? 8 * (D + 1) * 2 : (D <= 64 ? 4 * (D + 1) * 2 : D + 1);
 }
 
 // Coverage of the wave's pixels by one surviving disk s = (cx, cy, r^2 + band,
@@ -141,10 +144,9 @@ __host__ __device__ inline int raster_table_slots(int D) {
 // becomes id where the FP32 test decides (d^2 < r^2 - band); pixels inside the
 // band are decided in FP64 from the unrounded parameters (rare, wave-uniform
 // branch).
-template <class Ex>
 __device__ __forceinline__ void cover_disk(const float4 s, int k, uint32_t id,
                                            float px, const float (&py)[kRows],
-                                           uint32_t (&idx)[kRows], const Ex& ex, uint64_t r,
+                                           uint32_t (&idx)[kRows], const ConstExact* exq, uint64_t r,
                                            int x, int yb, int W, int H, int lane) {
   const float dx = px - s.x;
   const float dx2 = dx * dx;
@@ -162,6 +164,12 @@ __device__ __forceinline__ void cover_disk(const float4 s, int k, uint32_t id,
     idx[i] = d2 < s.w ? id : idx[i];
   }
   if (amb_any) {
+    // the parameters of this rare path are read here, through an address the
+    // compiler cannot see through, so that they do not hold scalar registers
+    // for the whole render loop
+    uint64_t ex_addr = (uint64_t)exq;
+    __asm__ volatile("" : "+s"(ex_addr));
+    const ConstExact& ex = *(const ConstExact*)ex_addr;
     const int sh = (int)(r % (uint64_t)ex.NH);
     const uint64_t rem = r / (uint64_t)ex.NH;
     const double a = (rem % (uint64_t)ex.A) == 0 ? 1.0 : -1.0;
@@ -187,31 +195,20 @@ __device__ __forceinline__ void cover_disk(const float4 s, int k, uint32_t id,
   }
 }
 
-// Loss of one render on the wave's tile when all disks fit one wavefront (D <=
-// 64): lane l holds disk l's record q for the cull and parks it in the wave's
-// table in front of disk l's colour (LDS byte address rec_slot); a survivor's
-// record is then one broadcast LDS read at its entry's address, the address
-// its pixels keep.  col0 is the wave's table (entry 0 = background, stride
-// 32 B, colour at +16).
-// Returns the lane-quad sum of the pixels' squared errors (every lane of a
-// quad holds it).
-template <int C, class Ex>
-__device__ __forceinline__ float render_one_group(
-    const float4 q, uint32_t rec_slot, uint64_t dmask, float mx, float my, float hx, float hy,
-    float px, const float (&py)[kRows], const float (&tm2)[kRows][C], float t2, float e_empty,
-    uint32_t col0, const float* s_cc, const Ex& ex, uint64_t r, int x, int yb, int W, int H,
-    int lane) {
-  typedef float lds_f4 __attribute__((ext_vector_type(4)));
-  typedef __attribute__((address_space(3))) lds_f4 LdsF4;
-  *(LdsF4*)(uintptr_t)rec_slot = lds_f4{q.x, q.y, q.z, q.w};
-  // conservative cull against the sub-tile rectangle; the [0, 1] clamp (an
-  // output modifier) can only shorten the distance, so no covering disk is
-  // dropped.  r <= 0 records carry r^2 = -1 and never pass; lanes >= D repeat
-  // disk D-1 and are masked out.
-  const float ddx = __builtin_amdgcn_fmed3f(fabsf(q.x - mx) - hx, 0.0f, 1.0f);
-  const float ddy = __builtin_amdgcn_fmed3f(fabsf(q.y - my) - hy, 0.0f, 1.0f);
-  uint64_t mask =
-      __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z, 5 /* ordered <= */) & dmask;
+typedef float lds_f4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) lds_f4 LdsF4;
+
+// Loss of one render on the wave's tile, given the lane mask of the disks that
+// survived the cull (bit l = disk l): a survivor's record is one broadcast LDS
+// read at its entry's address in the wave's table col0 (entry 0 =
+// background, stride 32 B: record, then colour), the address its covered
+// pixels keep.  Returns the lane-quad sum of the pixels' squared errors (every
+// lane of a quad holds it).
+template <int C>
+__device__ __forceinline__ float render_survivors(
+    uint64_t mask, float px, const float (&py)[kRows], const float (&tm2)[kRows][C], float t2,
+    float e_empty, uint32_t col0, const float* s_cc, const ConstExact* ex, uint64_t r, int x, int yb,
+    int W, int H, int lane) {
   if (mask == 0) return e_empty;
   uint32_t idx[kRows];
 #pragma unroll
@@ -236,34 +233,52 @@ __device__ __forceinline__ float render_one_group(
   return dpp_quad_sum(e);
 }
 
-// One block's work: renders [r0, r0 + nr) of one query on one 32x32 tile.
+// Cull of the records q the lanes hold against the wave tile (centre mx, my,
+// half extent hx, hy), after parking each in its table slot (LDS byte address
+// rec_slot) for the survivors' broadcast reads.  The [0, 1] clamp (an output
+// modifier) can only shorten the distance, so no covering disk is dropped;
+// r <= 0 records carry r^2 = -1 and never pass; lanes outside dmask (repeats
+// of the last disk, or a render past the end) are masked out.
+__device__ __forceinline__ uint64_t park_and_cull(const float4 q, uint32_t rec_slot,
+                                                  uint64_t dmask, float mx, float my, float hx,
+                                                  float hy) {
+  *(LdsF4*)(uintptr_t)rec_slot = lds_f4{q.x, q.y, q.z, q.w};
+  const float ddx = __builtin_amdgcn_fmed3f(fabsf(q.x - mx) - hx, 0.0f, 1.0f);
+  const float ddy = __builtin_amdgcn_fmed3f(fabsf(q.y - my) - hy, 0.0f, 1.0f);
+  return __builtin_amdgcn_fcmpf(fmaf(ddy, ddy, ddx * ddx), q.z, 5 /* ordered <= */) & dmask;
+}
+
+// One block's work: renders [r0, r0 + nr) of one query on one block of four
+// 16x16 wave tiles (2x2, 4x1 or 1x4).
 // Shared by the per-query kernel and the persistent batch kernel, so a render's
 // tile partial is the same bits whichever launch computes it.
 template <int C, bool kOneGroup, bool kBufLoad, class Query>
-__device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t r0, int nr,
-                                             float4* smem) {
-  const int W = a.W, H = a.H, D = a.D, S = a.S, tiles_x = a.tiles_x, bwx = a.bwx;
+__device__ __forceinline__ void raster_block(const Query& a, const ConstExact* exq, int tile,
+                                             uint64_t r0, int nr, float4* smem) {
+  const int W = a.W, H = a.H, D = a.D, tiles_x = a.tiles_x, bwx = a.bwx;
   const int subs_x = a.subs_x;
   const uint64_t subs = (uint64_t)a.subs;
   const float4* __restrict__ rec = a.rec;
   const float* __restrict__ target = a.target;
   const float* __restrict__ colors = a.colors;
   float* __restrict__ partial = a.partial;
-  auto& ex = a.ex;
+  const ConstExact* ex = exq;
   const uint64_t r_base = a.r_base;
   // colour table, entry 0 = background.  Up to 64 disks every wave has its
-  // own table whose entry k + 1 holds disk k's record of the render in flight
-  // followed by disk k's colour (stride 32 B; a pixel keeps the entry's
-  // address); beyond 64 disks the block shares one table of colours (stride
-  // 16 B; a pixel keeps the colour's address).
+  // own table (two up to 32 disks, one per render of a cull pass) whose entry
+  // k + 1 holds disk k's record of the render in flight followed by disk k's
+  // colour (stride 32 B; a pixel keeps the entry's address); beyond 64 disks
+  // the block shares one table of colours (stride 16 B; a pixel keeps the
+  // colour's address).
   float4* s_col = smem;
   const int tab_slots = raster_table_slots(D);
-  float* s_q = (float*)(smem + tab_slots);     // [S][4 waves][kQuadStride]
-  float* s_cc = s_q + S * 4 * kQuadStride;     // D + 1 squared norms (C == 4)
+  float* s_q = (float*)(smem + tab_slots);     // [4 waves][kFlush][16] quad partials
+  float* s_cc = s_q + 4 * kFlush * 16;         // D + 1 squared norms (C == 4)
   __syncthreads();   // the previous work item's readers of LDS are done
 
   // channels, and |c|^2 in .w (C <= 3) or in s_cc (C == 4)
-  for (int t = threadIdx.x; t < (kOneGroup ? 4 : 1) * (D + 1); t += blockDim.x) {
+  const int ntab = kOneGroup ? (D <= 32 ? 8 : 4) : 1;   // tables of the block
+  for (int t = threadIdx.x; t < ntab * (D + 1); t += blockDim.x) {
     const int k = t % (D + 1);
     float cc[4] = {0.f, 0.f, 0.f, 0.f};
     if (k > 0)
@@ -318,63 +333,111 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
   // per pixel state: the LDS byte address of the top disk's colour; the
   // colour table opens the dynamic LDS, which starts after the static LDS
   const uint32_t col0 = __builtin_amdgcn_groupstaticsize();
-  // this lane's slot of the per-render quad partials [S][4 waves][kQuadStride]
-  float* sq = s_q + wave * kQuadStride + (lane >> 2);
+  // the wave's quad partials of up to kFlush renders, [render][quad]; the
+  // quad heads write them, and every kFlush renders the wave sums each
+  // render's 16 in a fixed order into the wave tile's loss partial
+  float* s_qw = s_q + wave * kFlush * 16;
+  float* sq = s_qw + (lane >> 2);
   const bool quad_head = (lane & 3) == 0;
+  const uint64_t sub_w = (uint64_t)(ty0 / kSub) * (uint64_t)subs_x + (uint64_t)(tx0 / kSub);
+  // renders [f0, f0 + cnt) of the block: lane 4j + i adds quads 4i..4i+3 of
+  // render f0 + j, the lane quad adds the four sums (two DPP adds)
+  auto flush = [&](int f0, int cnt) {
+    typedef float lds_f4v __attribute__((ext_vector_type(4)));
+    const lds_f4v v = *(const __attribute__((address_space(3))) lds_f4v*)(uintptr_t)(
+        s_qw + lane * 4);
+    const float acc = dpp_quad_sum(((v.x + v.y) + v.z) + v.w);
+    const int j = lane >> 2;
+    if (quad_head && j < cnt) partial[(r0 + (uint64_t)(f0 + j)) * subs + sub_w] = acc;
+  };
   if constexpr (kOneGroup) {
-    // lane l culls disk l; the next render's records are loaded while this
-    // render is processed (clamped on the last render), alternating between
-    // two registers sets
-    const int lane_d = lane < D ? lane : D - 1;
-    const uint64_t dmask = D < 64 ? (1ull << D) - 1 : ~0ull;
-    const char* rb = (const char*)rp0;
-    const uint64_t rstride = (uint64_t)D * sizeof(float4);
-    const uint32_t loff = (uint32_t)lane_d * (uint32_t)sizeof(float4);
-    // this wave's table and this lane's record slot in it
-    const uint32_t colw = col0 + (uint32_t)(wave * (D + 1)) * 32u;
-    const uint32_t rec_slot = colw + (uint32_t)(lane_d + 1) * 32u;
-    // kBufLoad: the block's records as one buffer of nr * D records, the
-    // lane's byte offset in a vector register and the render's in a scalar
-    // one (no address arithmetic on the vector unit; descriptor word 3 is the
-    // gfx9 raw buffer format, 32-bit data).  Otherwise a global load from the
-    // render's base address in scalar registers: the persistent batch kernel
-    // has no scalar registers to spare for a descriptor.
-    typedef float g_f4 __attribute__((ext_vector_type(4)));
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)rb, (short)0, (int)((uint64_t)nr * rstride), 0x00020000);
-    auto lane_rec = [&](int rr) {
-      g_f4 v;
-      if constexpr (kBufLoad) {
-        v = __builtin_bit_cast(
-            g_f4, __builtin_amdgcn_raw_buffer_load_b128(
-                      rsrc, (int)loff, (int)((uint32_t)min(rr, nr - 1) * (uint32_t)rstride), 0));
-      } else {
-        // a descriptor of this render's records only, built where it is used
-        const uint64_t base = (uint64_t)rb + (uint64_t)min(rr, nr - 1) * rstride;
-        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-        const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(((uint64_t)hi << 32) | lo), (short)0, (int)rstride, 0x00020000);
-        v = __builtin_bit_cast(g_f4, __builtin_amdgcn_raw_buffer_load_b128(r1, (int)loff, 0, 0));
+    // Up to 32 disks, lanes 0-31 hold the records of one render and lanes
+    // 32-63 those of the next, so one cull serves two renders, each half with
+    // its own table; up to 64 disks, lane l holds disk l of one render.  The
+    // next pass's records are loaded while this one is processed, alternating
+    // between two register sets.
+    auto passes = [&](auto g) {
+      constexpr int G = decltype(g)::value;   // renders per cull
+      const int half = G == 2 ? lane >> 5 : 0;
+      const int lane_d = min(G == 2 ? lane & 31 : lane, D - 1);
+      const uint64_t dm = D < 64 ? (1ull << D) - 1 : ~0ull;
+      const char* rb = (const char*)rp0;
+      const uint64_t rstride = (uint64_t)D * sizeof(float4);
+      const uint32_t loff = (uint32_t)half * (uint32_t)rstride + (uint32_t)lane_d * 16u;
+      // this wave's G tables and this lane's record slot in them
+      const uint32_t colw = col0 + (uint32_t)(wave * G * (D + 1)) * 32u;
+      const uint32_t colb = colw + (uint32_t)(D + 1) * 32u;
+      const uint32_t rec_slot = colw + (uint32_t)(half * (D + 1) + lane_d + 1) * 32u;
+      // kBufLoad: the block's records as one buffer of nr * D records, the
+      // lane's byte offset in a vector register and the pass's in a scalar one
+      // (no address arithmetic on the vector unit; descriptor word 3 is the
+      // gfx9 raw buffer format, 32-bit data); lanes past the buffer's end read
+      // zeros.  Otherwise a global load from the pass's base address in scalar
+      // registers: the persistent batch kernel has no scalar registers to spare
+      // for a block-wide descriptor.
+      typedef float g_f4 __attribute__((ext_vector_type(4)));
+      const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)rb, (short)0, (int)((uint64_t)nr * rstride), 0x00020000);
+      auto lane_rec = [&](int rr) {
+        const uint32_t r1 = (uint32_t)min(rr, nr - 1);
+        g_f4 v;
+        if constexpr (kBufLoad) {
+          v = __builtin_bit_cast(g_f4, __builtin_amdgcn_raw_buffer_load_b128(
+                                           rsrc, (int)loff, (int)(r1 * (uint32_t)rstride), 0));
+        } else {
+          // a descriptor of this pass's records only, built where it is used
+          const uint64_t base = (uint64_t)rb + (uint64_t)r1 * rstride;
+          const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+          const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+          const int len = (int)((uint32_t)min(G, nr - (int)r1) * (uint32_t)rstride);
+          const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+              (void*)(((uint64_t)hi << 32) | lo), (short)0, len, 0x00020000);
+          v = __builtin_bit_cast(g_f4,
+                                 __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)loff, 0, 0));
+        }
+        return make_float4(v.x, v.y, v.z, v.w);
+      };
+      // lanes that take part in the cull of the pass starting at render rr
+      auto pass_mask = [&](int rr) {
+        return G == 2 ? (rr + 1 < nr_wave ? dm | (dm << 32) : dm) : dm;
+      };
+      const uint64_t rq = r_base + r0;
+      float4 qa = lane_rec(0);
+      // kFlush is a multiple of 2 * G: a flush group ends after whole passes
+      for (int f0 = 0; f0 < nr_wave; f0 += kFlush) {
+        const int fe = min(f0 + kFlush, nr_wave);
+        float* sqr = sq;   // advanced by two passes' partials
+        for (int rr = f0; rr < fe; rr += 2 * G) {
+          const float4 qb = lane_rec(rr + G);
+          uint64_t m = park_and_cull(qa, rec_slot, pass_mask(rr), mx, my, hx, hy);
+          float e = render_survivors<C>(m & dm, px, py, tm2, t2, e_empty, colw, s_cc, ex,
+                                        rq + (uint64_t)rr, x, yb, W, H, lane);
+          if (quad_head) sqr[0] = e;
+          if (G == 2 && rr + 1 < nr_wave) {
+            e = render_survivors<C>(m >> 32, px, py, tm2, t2, e_empty, colb, s_cc, ex,
+                                    rq + (uint64_t)(rr + 1), x, yb, W, H, lane);
+            if (quad_head) sqr[16] = e;
+          }
+          if (rr + G >= nr_wave) break;
+          qa = lane_rec(rr + 2 * G);
+          m = park_and_cull(qb, rec_slot, pass_mask(rr + G), mx, my, hx, hy);
+          e = render_survivors<C>(m & dm, px, py, tm2, t2, e_empty, colw, s_cc, ex,
+                                  rq + (uint64_t)(rr + G), x, yb, W, H, lane);
+          if (quad_head) sqr[G * 16] = e;
+          if (G == 2 && rr + 3 < nr_wave) {
+            e = render_survivors<C>(m >> 32, px, py, tm2, t2, e_empty, colb, s_cc, ex,
+                                    rq + (uint64_t)(rr + 3), x, yb, W, H, lane);
+            if (quad_head) sqr[48] = e;
+          }
+          sqr += 2 * G * 16;
+        }
+        flush(f0, fe - f0);
       }
-      return make_float4(v.x, v.y, v.z, v.w);
     };
-    float4 qa = lane_rec(0);
-    float* sqr = sq;   // advanced by two renders' partials per pass
-    for (int rr = 0; rr < nr_wave; rr += 2) {
-      const float4 qb = lane_rec(rr + 1);
-      float e = render_one_group<C>(qa, rec_slot, dmask, mx, my, hx, hy, px, py, tm2, t2,
-                                    e_empty, colw, s_cc, ex, r_base + r0 + (uint64_t)rr, x, yb,
-                                    W, H, lane);
-      if (quad_head) sqr[0] = e;
-      if (rr + 1 >= nr_wave) break;
-      qa = lane_rec(rr + 2);
-      e = render_one_group<C>(qb, rec_slot, dmask, mx, my, hx, hy, px, py, tm2, t2,
-                              e_empty, colw, s_cc, ex, r_base + r0 + (uint64_t)(rr + 1), x, yb,
-                              W, H, lane);
-      if (quad_head) sqr[4 * kQuadStride] = e;
-      sqr += 8 * kQuadStride;
-    }
+    if (D <= 32)
+      passes(std::integral_constant<int, 2>{});
+    else
+      passes(std::integral_constant<int, 1>{});
   } else {
     for (int rr = 0; rr < nr_wave; ++rr) {
       const float4* rp = rp0 + (uint64_t)rr * D;
@@ -416,24 +479,14 @@ __device__ __forceinline__ void raster_block(const Query& a, int tile, uint64_t 
         }
         e = dpp_quad_sum(e);
       }
-      if (quad_head) sq[rr * 4 * kQuadStride] = e;
+      if (quad_head) sq[(rr % kFlush) * 16] = e;
+      if ((rr + 1) % kFlush == 0 || rr + 1 == nr_wave) flush(rr - rr % kFlush, rr % kFlush + 1);
     }
-  }
-  __syncthreads();
-  // fixed-order sum of each wave's 16 quad partials: one partial per wave tile
-  for (int t = threadIdx.x; t < nr * 4; t += blockDim.x) {
-    const int w = t & 3;
-    const int wx0 = bx0 + (w % bwx) * kSub, wy0 = by0 + (w / bwx) * kSub;
-    if (wx0 >= W || wy0 >= H) continue;
-    float acc = 0.0f;
-    for (int qd = 0; qd < 16; ++qd) acc += s_q[t * kQuadStride + qd];
-    const uint64_t sub = (uint64_t)(wy0 / kSub) * (uint64_t)subs_x + (uint64_t)(wx0 / kSub);
-    partial[(r0 + (uint64_t)(t >> 2)) * subs + sub] = acc;
   }
 }
 
 template <int C, bool kOneGroup>
-__global__ __launch_bounds__(256) void k_raster_loss(RasterQuery a, uint64_t chunks) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_raster_loss(RasterQuery a, uint64_t chunks) {
   extern __shared__ float4 smem[];
   // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
   // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
@@ -444,7 +497,12 @@ __global__ __launch_bounds__(256) void k_raster_loss(RasterQuery a, uint64_t chu
   if (chunk >= chunks) return;
   const uint64_t r0 = chunk * (uint64_t)a.S;
   const int nr = (int)min((uint64_t)a.S, a.R - r0);
-  raster_block<C, kOneGroup, true, RasterQuery>(a, tile, r0, nr, smem);
+  // the query's exact-path parameters where they sit in the kernel arguments
+  // (the query is the first argument)
+  const ConstExact* exq = (const ConstExact*)((const __attribute__((address_space(4))) char*)
+                                                  __builtin_amdgcn_kernarg_segment_ptr() +
+                                              offsetof(RasterQuery, ex));
+  raster_block<C, kOneGroup, true, RasterQuery>(a, exq, tile, r0, nr, smem);
 }
 
 // single render at theta, coverage in FP64 (the definition)
@@ -492,7 +550,7 @@ __global__ __launch_bounds__(256) void k_batch_records(const BatchTable* __restr
 // claimed by exactly one atomic increment; a block leaves after seeing all
 // eight queues exhausted.
 template <int C, bool kOneGroup>
-__global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restrict__ T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_batch_raster(const BatchTable* __restrict__ T) {
   extern __shared__ float4 smem[];
   __shared__ unsigned long long s_item;
   const WorkQueues& W = T->raster[raster_class(C, kOneGroup ? 1 : 65)];
@@ -528,7 +586,7 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchTable* __restri
       const int tile = (int)(l % (uint64_t)sg.tiles);
       const uint64_t r0 = chunk * (uint64_t)a.S;
       const int nr = (int)min((uint64_t)a.S, a.R - r0);
-      raster_block<C, kOneGroup, false, ConstRasterQuery>(a, tile, r0, nr, smem);
+      raster_block<C, kOneGroup, false, ConstRasterQuery>(a, &a.ex, tile, r0, nr, smem);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
@@ -553,13 +611,27 @@ void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const
 
 int raster_subtiles(int W, int H) { return ((W + kSub - 1) / kSub) * ((H + kSub - 1) / kSub); }
 
-void raster_block_shape(int shape, int* bwx, int* bwy) {
-  *bwx = shape == 2 ? 4 : (shape == 3 ? 1 : 2);
+// shape 0 (the library's choice): of the three block shapes, the one that
+// covers the W x H image with the fewest blocks; ties go to the 16x64 column of
+// four wave tiles, then to 32x32.  A 256x256 image needs 64 blocks of each
+// shape, and there the column is 3% faster than 32x32 and 16% faster than
+// 64x16; an image only two wave tiles wide or tall would leave half of a
+// column's (or a row's) wave tiles idle
+void raster_block_shape(int shape, int W, int H, int* bwx, int* bwy) {
+  if (shape <= 0 || shape > 3) {
+    const int64_t sx = (W + kSub - 1) / kSub, sy = (H + kSub - 1) / kSub;
+    auto blocks = [&](int64_t bx) { return ((sx + bx - 1) / bx) * ((sy + 4 / bx - 1) / (4 / bx)); };
+    const int64_t col = blocks(1), sq = blocks(2), row = blocks(4);
+    shape = 3;
+    if (sq < col) shape = 1;
+    if (row < col && row < sq) shape = 2;
+  }
+  *bwx = shape == 1 ? 2 : (shape == 2 ? 4 : 1);
   *bwy = 4 / *bwx;
 }
 
 void raster_geometry(RasterQuery& a, int shape) {
-  raster_block_shape(shape, &a.bwx, &a.bwy);
+  raster_block_shape(shape, a.W, a.H, &a.bwx, &a.bwy);
   a.tiles_x = (a.W + kSub * a.bwx - 1) / (kSub * a.bwx);
   a.tiles = a.tiles_x * ((a.H + kSub * a.bwy - 1) / (kSub * a.bwy));
   a.subs_x = (a.W + kSub - 1) / kSub;
@@ -569,7 +641,7 @@ void raster_geometry(RasterQuery& a, int shape) {
 
 size_t raster_lds_bytes(int D, int S) {
   return (size_t)raster_table_slots(D) * sizeof(float4) +
-         (size_t)S * 4 * kQuadStride * sizeof(float) + (size_t)(D + 1) * sizeof(float);
+         (size_t)4 * kFlush * 16 * sizeof(float) + (size_t)(D + 1) * sizeof(float);
 }
 
 int raster_max_samples() { return kMaxS; }
