@@ -81,7 +81,9 @@ typedef struct {
   int antithetic;       /* 1 (default): pair tau with -tau; 0: single draws             */
   double hvp_rel_step;  /* HVP central-difference step h = hvp_rel_step * sigma (0.1) */
   int accum_fp64;       /* 0 (default): compensated-FP32 lobe sums; 1: FP64 sums        */
-  int samples_per_block;/* renders per raster/path-tracer block; 0 = library choice     */
+  int samples_per_block;/* renders per raster/path-tracer block (raster: at most 256);
+                           0 = library choice (raster: the largest of 128, 64
+                           and 32 that still gives at least 128 * S blocks)   */
   int raster_tile;      /* raster block of 16x16 wave tiles: 1 = 32x32,
                            2 = 64x16, 3 = 16x64; 0 = library choice: the shape
                            that covers the image with the fewest blocks, ties
@@ -333,12 +335,13 @@ typedef struct {
 
 typedef struct {
   int use_graph;            /* 1 (default): replay the launches as a hipGraph   */
-  int autotune;             /* 1: before a batch, time samples-per-block and
-                               block shape for every not yet tuned class of
-                               disk scene (channels, disk count, image size
-                               buckets) and keep the fastest in the context;
-                               0 (default): 64 renders per block of the
-                               library's shape (raster_tile 0)                 */
+  int autotune;             /* 1: before a batch, time samples-per-block
+                               (32, 64, 128) and block shape (the three) for
+                               every not yet tuned class of disk scene
+                               (channels, disk count, image size buckets) and
+                               keep the fastest in the context; 0 (default):
+                               the library's choices (samples_per_block and
+                               raster_tile 0)                                   */
 } hr_batch_opts;
 
 typedef struct {

@@ -121,8 +121,8 @@ hr_status BatchSlot::reserve_table(size_t bytes) {
 
 // The raster configuration a query runs with: explicit options first, then
 // the autotuner's choice for its class, then the defaults.
-static void raster_config(hr_ctx* ctx, const hr_scene* sc, const hr_opts& o, int* S,
-                          int* shape) {
+static void raster_config(hr_ctx* ctx, const hr_scene* sc, const hr_opts& o, uint64_t R,
+                          int* S, int* shape) {
   *S = o.samples_per_block;
   *shape = o.raster_tile;
   {
@@ -133,7 +133,8 @@ static void raster_config(hr_ctx* ctx, const hr_scene* sc, const hr_opts& o, int
       if (*shape <= 0) *shape = it->second.second;
     }
   }
-  if (*S <= 0 || *S > raster_max_samples()) *S = raster_max_samples();
+  if (*S <= 0) *S = raster_auto_samples(sc->W, sc->H, R);
+  if (*S > raster_max_samples()) *S = raster_max_samples();
   if (*shape < 0 || *shape > 3) *shape = 0;
 }
 
@@ -159,7 +160,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
     const QueryPlan& p = items[q].plan;
     const hr_scene* sc = p.sc;
     if (sc->kind == kDisks) {
-      raster_config(ctx, sc, p.o, &qS[q], &qshape[q]);
+      raster_config(ctx, sc, p.o, p.e.R, &qS[q], &qshape[q]);
       cost[q] = (double)qS[q] * (double)(sc->D + 16);
       lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
     } else if (sc->kind == kPT) {
@@ -466,7 +467,7 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
       classes[tune_key(sc)].push_back(i);
     }
   }
-  const int Ss[] = {16, 32, 64};
+  const int Ss[] = {32, 64, 128};
   const int shapes[] = {1, 2, 3};
   hipEvent_t a, b;
   HR_HIP(hipEventCreate(&a));
@@ -480,7 +481,7 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
       sub.push_back(it);
     }
     double best = 1e300;
-    std::pair<int, int> pick{raster_max_samples(), 1};
+    std::pair<int, int> pick{0, 0};
     for (int S : Ss) {
       for (int shape : shapes) {
         for (auto& it : sub) {

@@ -38,7 +38,7 @@ namespace {
 typedef const RasterExact __attribute__((address_space(4))) ConstExact;
 constexpr int kSub = 16;         // wave tile side (pixels)
 constexpr int kRows = 4;         // rows per lane
-constexpr int kMaxS = 64;        // renders per block (upper bound)
+constexpr int kMaxS = 256;       // renders per block (upper bound)
 constexpr int kFlush = 16;       // renders whose quad partials a wave holds in LDS
 constexpr float kFar = 1.0e18f;  // centre of pixels outside the image
 
@@ -646,9 +646,25 @@ size_t raster_lds_bytes(int D, int S) {
 
 int raster_max_samples() { return kMaxS; }
 
+// S = 0 (the library's choice): the largest of 128, 64 and 32 renders per
+// block that still gives the launch at least 128 * S blocks (about nine
+// rounds of the blocks the chip holds at once).  Longer render runs per
+// block amortise the per-block set-up (colour tables, target, cull
+// rectangle); shorter ones keep small queries spread over all CUs.
+int raster_auto_samples(int W, int H, uint64_t R) {
+  int bwx, bwy;
+  raster_block_shape(0, W, H, &bwx, &bwy);
+  const uint64_t tiles = (uint64_t)((W + kSub * bwx - 1) / (kSub * bwx)) *
+                         (uint64_t)((H + kSub * bwy - 1) / (kSub * bwy));
+  for (int S = 128; S > 32; S /= 2)
+    if (tiles * ((R + S - 1) / S) >= 128ull * (uint64_t)S) return S;
+  return 32;
+}
+
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
                         int S, int shape, const RasterExact& ex, float* partial) {
-  if (S <= 0 || S > kMaxS) S = kMaxS;
+  if (S <= 0) S = raster_auto_samples(s.W, s.H, R);
+  if (S > kMaxS) S = kMaxS;
   RasterQuery a;
   a.W = s.W; a.H = s.H; a.C = s.C; a.D = s.D; a.S = S;
   raster_geometry(a, shape);

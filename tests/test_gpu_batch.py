@@ -154,13 +154,13 @@ def test_raster_tiles_and_samples_do_not_change_bits(P, ctx, scenes, name):
     w, sc = scenes[name]
     base = P.estimate("grad", sc, w.theta0, w.sigma, 200, 5)
     for tile in (1, 2, 3):
-        for spb in (1, 7, 16, 64):
+        for spb in (1, 7, 16, 64, 200, 256):
             say(f"{name} raster_tile={tile} samples_per_block={spb}")
             got = P.estimate("grad", sc, w.theta0, w.sigma, 200, 5, samples_per_block=spb,
                              raster_tile=tile)
             assert np.array_equal(got, base)
     qs = [dict(scene=sc, kind="grad", theta=w.theta0, sigma=w.sigma, N=200, seed=5,
-               samples_per_block=spb, raster_tile=t) for t in (1, 2, 3) for spb in (5, 64)]
+               samples_per_block=spb, raster_tile=t) for t in (1, 2, 3) for spb in (5, 64, 256)]
     for got in P.Batch(ctx).run(qs):
         assert np.array_equal(got, base)
 
