@@ -252,7 +252,7 @@ __device__ __forceinline__ uint64_t park_and_cull(const float4 q, uint32_t rec_s
 // 16x16 wave tiles (2x2, 4x1 or 1x4).
 // Shared by the per-query kernel and the persistent batch kernel, so a render's
 // tile partial is the same bits whichever launch computes it.
-template <int C, bool kOneGroup, bool kBufLoad, class Query>
+template <int C, bool kOneGroup, class Query>
 __device__ __forceinline__ void raster_block(const Query& a, const ConstExact* exq, int tile,
                                              uint64_t r0, int nr, float4* smem) {
   const int W = a.W, H = a.H, D = a.D, tiles_x = a.tiles_x, bwx = a.bwx;
@@ -368,33 +368,19 @@ __device__ __forceinline__ void raster_block(const Query& a, const ConstExact* e
       const uint32_t colw = col0 + (uint32_t)(wave * G * (D + 1)) * 32u;
       const uint32_t colb = colw + (uint32_t)(D + 1) * 32u;
       const uint32_t rec_slot = colw + (uint32_t)(half * (D + 1) + lane_d + 1) * 32u;
-      // kBufLoad: the block's records as one buffer of nr * D records, the
-      // lane's byte offset in a vector register and the pass's in a scalar one
-      // (no address arithmetic on the vector unit; descriptor word 3 is the
-      // gfx9 raw buffer format, 32-bit data); lanes past the buffer's end read
-      // zeros.  Otherwise a global load from the pass's base address in scalar
-      // registers: the persistent batch kernel has no scalar registers to spare
-      // for a block-wide descriptor.
+      // the block's records as one buffer of nr * D records, the lane's byte
+      // offset in a vector register and the pass's in a scalar one (no
+      // address arithmetic on the vector unit; descriptor word 3 is the gfx9
+      // raw buffer format, 32-bit data); lanes past the buffer's end read
+      // zeros
       typedef float g_f4 __attribute__((ext_vector_type(4)));
       const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
           (void*)rb, (short)0, (int)((uint64_t)nr * rstride), 0x00020000);
       auto lane_rec = [&](int rr) {
         const uint32_t r1 = (uint32_t)min(rr, nr - 1);
-        g_f4 v;
-        if constexpr (kBufLoad) {
-          v = __builtin_bit_cast(g_f4, __builtin_amdgcn_raw_buffer_load_b128(
-                                           rsrc, (int)loff, (int)(r1 * (uint32_t)rstride), 0));
-        } else {
-          // a descriptor of this pass's records only, built where it is used
-          const uint64_t base = (uint64_t)rb + (uint64_t)r1 * rstride;
-          const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-          const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-          const int len = (int)((uint32_t)min(G, nr - (int)r1) * (uint32_t)rstride);
-          const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
-              (void*)(((uint64_t)hi << 32) | lo), (short)0, len, 0x00020000);
-          v = __builtin_bit_cast(g_f4,
-                                 __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)loff, 0, 0));
-        }
+        const g_f4 v = __builtin_bit_cast(
+            g_f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)loff,
+                                                         (int)(r1 * (uint32_t)rstride), 0));
         return make_float4(v.x, v.y, v.z, v.w);
       };
       // lanes that take part in the cull of the pass starting at render rr
@@ -485,8 +471,12 @@ __device__ __forceinline__ void raster_block(const Query& a, const ConstExact* e
   }
 }
 
+// At least 7 waves per SIMD: caps the kernel at 72 VGPRs.  Left to itself the
+// scheduler spends more registers on loads in flight in the loss fold and the
+// occupancy drops to 5-6 waves, which costs more than those loads gain.
 template <int C, bool kOneGroup>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_raster_loss(RasterQuery a, uint64_t chunks) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
+void k_raster_loss(RasterQuery a, uint64_t chunks) {
   extern __shared__ float4 smem[];
   // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
   // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
@@ -502,7 +492,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
   const ConstExact* exq = (const ConstExact*)((const __attribute__((address_space(4))) char*)
                                                   __builtin_amdgcn_kernarg_segment_ptr() +
                                               offsetof(RasterQuery, ex));
-  raster_block<C, kOneGroup, true, RasterQuery>(a, exq, tile, r0, nr, smem);
+  raster_block<C, kOneGroup, RasterQuery>(a, exq, tile, r0, nr, smem);
 }
 
 // single render at theta, coverage in FP64 (the definition)
@@ -549,8 +539,10 @@ __global__ __launch_bounds__(256) void k_batch_records(const BatchTable* __restr
 // and move on to the other queues when theirs is empty.  Every item is
 // claimed by exactly one atomic increment; a block leaves after seeing all
 // eight queues exhausted.
+// At least 7 waves per SIMD, as k_raster_loss.
 template <int C, bool kOneGroup>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_batch_raster(const BatchTable* __restrict__ T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
+void k_batch_raster(const BatchTable* __restrict__ T) {
   extern __shared__ float4 smem[];
   __shared__ unsigned long long s_item;
   const WorkQueues& W = T->raster[raster_class(C, kOneGroup ? 1 : 65)];
@@ -586,7 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
       const int tile = (int)(l % (uint64_t)sg.tiles);
       const uint64_t r0 = chunk * (uint64_t)a.S;
       const int nr = (int)min((uint64_t)a.S, a.R - r0);
-      raster_block<C, kOneGroup, false, ConstRasterQuery>(a, &a.ex, tile, r0, nr, smem);
+      raster_block<C, kOneGroup, ConstRasterQuery>(a, &a.ex, tile, r0, nr, smem);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
