@@ -52,8 +52,8 @@ FLOP_PER_PIXEL = 12.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this SHA-256; reported as null once the source has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 467551414
-TRAFFIC_SOURCE_SHA256 = "8c2fe34896d7cd5378ace775a1fc33f2ed145cef019c8552fa21ad900f91e794"
+TRAFFIC_BYTES_PER_LAUNCH = 489972313
+TRAFFIC_SOURCE_SHA256 = "c04fb59f20d09ad755d563350db13ad7932f08379f9f28e10bc2c85b32ba1059"
 
 
 def raster_traffic():

@@ -33,14 +33,14 @@ constexpr uint64_t kDefaultServerMemory = 8ull << 30;
 constexpr size_t kTableReserve = 4u << 20;
 
 // Predicted device milliseconds of one query (batch formation only; results
-// never depend on it): rasterised pixel-renders at ~2 per ps, path-traced
-// pixel samples at ~60 per ns, lobe-sum terms at ~200 per ns, plus a fixed
+// never depend on it): rasterised pixel-renders at ~3.3 per ps, path-traced
+// pixel samples at ~80 per ns, lobe-sum terms at ~200 per ns, plus a fixed
 // 20 us of small launches.
 double predict_ms(const QueryPlan& p) {
   const hr_scene* sc = p.sc;
   const double R = (double)p.e.R;
   double ms = 0.02;
-  if (sc->kind == kDisks) ms += R * sc->W * sc->H / 2.5e9;
+  if (sc->kind == kDisks) ms += R * sc->W * sc->H / 3.3e9;
   else if (sc->kind == kPT) ms += R * sc->W * sc->H * sc->spp / 8.0e7;
   else ms += R * p.e.n * p.e.n / 1.0e9;
   ms += (double)p.e.streams * (double)p.e.N * (double)p.e.nout / 2.0e8;
