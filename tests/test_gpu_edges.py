@@ -1,7 +1,8 @@
 """Edge cases of the disk path against the oracle on the same draws: a 1x1
-image, the maximum disk count, a 4096x4096 image, wavefront-group
-boundaries (64 / 65 disks), nothing covered (disks outside the image or with
-non-positive radii), and extreme sigma.  Bar as in the parity suite: 1e-4
+image, the maximum disk count, a 4096x4096 image, the rasteriser's disk-count
+boundaries (32 / 33: two renders per cull or one; 64 / 65: one wavefront of
+disks or several), odd render counts, nothing covered (disks outside the
+image or with non-positive radii), and extreme sigma.  Bar as in the parity suite: 1e-4
 relative (infinity norm) on estimates, per-render losses to FP32 rounding."""
 import sys
 
@@ -48,16 +49,22 @@ def make(W, H, D, C=3, seed=0, centre=(0.0, 1.0), radius=(0.03, 0.3), sigma=0.02
                            sigma=sigma, N=64, seed=seed + 100, v=v / np.linalg.norm(v))
 
 
-def check(P, ctx, w, kinds=("grad", "hess", "hvp"), N=None, sampler=0, loss_tol=1e-6):
+def check(P, ctx, w, kinds=("grad", "hess", "hvp"), N=None, sampler=0, loss_tol=1e-6,
+          antithetic=True, spbs=()):
     tgt = disk_target(w)
     osc, gsc = oracle_disks(w, tgt), gpu_disks(ctx, w, tgt)
     N = N or w.N
     for kind in kinds:
-        say(f"{w.name} {kind} N={N} sigma={w.sigma}")
+        say(f"{w.name} {kind} N={N} sigma={w.sigma} antithetic={antithetic}")
         ref, lref = O.estimate(kind, osc, w.theta0, w.sigma, N, w.seed, v=w.v, sampler=sampler,
-                               return_losses=True)
+                               antithetic=antithetic, return_losses=True)
         got, lgot = P.estimate(kind, gsc, w.theta0, w.sigma, N, w.seed, v=w.v, sampler=sampler,
-                               return_losses=True)
+                               antithetic=antithetic, return_losses=True)
+        for spb in spbs:
+            say(f"  samples_per_block={spb}")
+            again = P.estimate(kind, gsc, w.theta0, w.sigma, N, w.seed, v=w.v, sampler=sampler,
+                               antithetic=antithetic, samples_per_block=spb)
+            assert np.array_equal(again, got)
         assert np.abs(lgot - lref).max() <= loss_tol * max(np.abs(lref).max(), 1e-30)
         if np.abs(ref).max() == 0.0:
             assert np.abs(got).max() == 0.0
@@ -71,10 +78,18 @@ def test_one_pixel_image(P, ctx):
     check(P, ctx, w)
 
 
-@pytest.mark.parametrize("D", [64, 65])
+@pytest.mark.parametrize("D", [31, 32, 33, 64, 65])
 def test_wavefront_group_boundary(P, ctx, D):
     w = make(40, 24, D, seed=D, radius=(0.02, 0.08))
     check(P, ctx, w, N=48)
+
+
+def test_odd_render_counts(P, ctx):
+    """Single draws (no antithetic pair) and an odd N: the last block's render
+    count is odd, so the last cull pass of two renders holds one; the same
+    bits for 7 and 256 renders per block."""
+    w = make(48, 40, 20, seed=9, radius=(0.05, 0.2))
+    check(P, ctx, w, N=37, antithetic=False, spbs=(7, 256))
 
 
 def test_maximum_disk_count(P, ctx):
