@@ -82,8 +82,9 @@ typedef struct {
   double hvp_rel_step;  /* HVP central-difference step h = hvp_rel_step * sigma (0.1) */
   int accum_fp64;       /* 0 (default): compensated-FP32 lobe sums; 1: FP64 sums        */
   int samples_per_block;/* renders per raster/path-tracer block (raster: at most 256);
-                           0 = library choice (raster: the largest of 128, 64
-                           and 32 that still gives at least 128 * S blocks)   */
+                           0 = library choice (raster: the largest of 256,
+                           128, 64 and 32 that still gives at least 128 * S
+                           blocks)                                            */
   int raster_tile;      /* raster block of 16x16 wave tiles: 1 = 32x32,
                            2 = 64x16, 3 = 16x64; 0 = library choice: the shape
                            that covers the image with the fewest blocks, ties
@@ -336,7 +337,7 @@ typedef struct {
 typedef struct {
   int use_graph;            /* 1 (default): replay the launches as a hipGraph   */
   int autotune;             /* 1: before a batch, time samples-per-block
-                               (32, 64, 128) and block shape (the three) for
+                               (32-256) and block shape (the three) for
                                every not yet tuned class of disk scene
                                (channels, disk count, image size buckets) and
                                keep the fastest in the context; 0 (default):

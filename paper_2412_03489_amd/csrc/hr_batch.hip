@@ -467,7 +467,7 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
       classes[tune_key(sc)].push_back(i);
     }
   }
-  const int Ss[] = {32, 64, 128};
+  const int Ss[] = {32, 64, 128, 256};
   const int shapes[] = {1, 2, 3};
   hipEvent_t a, b;
   HR_HIP(hipEventCreate(&a));

@@ -40,6 +40,8 @@ constexpr int kSub = 16;         // wave tile side (pixels)
 constexpr int kRows = 4;         // rows per lane
 constexpr int kMaxS = 256;       // renders per block (upper bound)
 constexpr int kFlush = 16;       // renders whose quad partials a wave holds in LDS
+// the flush reads the wave's kFlush x 16 quad partials as one float4 per lane
+static_assert(kFlush * 16 == 64 * 4, "a flush covers exactly one float4 per lane");
 constexpr float kFar = 1.0e18f;  // centre of pixels outside the image
 
 // Half-width of the band around r^2 outside which the FP32 and the FP64
@@ -638,9 +640,9 @@ size_t raster_lds_bytes(int D, int S) {
 
 int raster_max_samples() { return kMaxS; }
 
-// S = 0 (the library's choice): the largest of 128, 64 and 32 renders per
-// block that still gives the launch at least 128 * S blocks (about nine
-// rounds of the blocks the chip holds at once).  Longer render runs per
+// S = 0 (the library's choice): the largest of 256, 128, 64 and 32 renders
+// per block that still gives the launch at least 128 * S blocks (at 32
+// renders per block, about two rounds of the blocks the chip holds at once).  Longer render runs per
 // block amortise the per-block set-up (colour tables, target, cull
 // rectangle); shorter ones keep small queries spread over all CUs.
 int raster_auto_samples(int W, int H, uint64_t R) {
@@ -648,7 +650,7 @@ int raster_auto_samples(int W, int H, uint64_t R) {
   raster_block_shape(0, W, H, &bwx, &bwy);
   const uint64_t tiles = (uint64_t)((W + kSub * bwx - 1) / (kSub * bwx)) *
                          (uint64_t)((H + kSub * bwy - 1) / (kSub * bwy));
-  for (int S = 128; S > 32; S /= 2)
+  for (int S = 256; S > 32; S /= 2)
     if (tiles * ((R + S - 1) / S) >= 128ull * (uint64_t)S) return S;
   return 32;
 }
