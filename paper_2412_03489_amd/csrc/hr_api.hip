@@ -140,7 +140,7 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
   p->b_tau = align256(e.streams * N * (uint64_t)e.n * 8);
   p->b_u = align256((size_t)e.n * 8 + 8);
   p->b_rec = sc->kind == kDisks ? align256(e.R * (uint64_t)sc->D * 16) : 0;
-  p->b_part = p->stride ? align256(e.R * (uint64_t)p->stride * 4) : 0;
+  p->b_part = p->stride ? align256(part_floats(e.R, (uint64_t)p->stride) * 4) : 0;
   p->b_f = align256(e.R * 8);
   p->b_Fq = align256(e.streams * N * 8);
   p->b_vt = align256(N * 8);

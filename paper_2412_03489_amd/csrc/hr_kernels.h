@@ -53,8 +53,17 @@ struct RasterExact {
 // One query's raster work: records of renders [0, R) (r_base = global index
 // of render 0 for the exact path).  A block covers bwx x bwy wave tiles of
 // 16x16 pixels and S renders per work item; the loss partial of every wave
-// tile is written to partial[r * subs + wave tile], so neither the block
-// shape nor S changes any result bit.
+// tile is written to partial[part_index(r, wave tile, subs)], so neither the
+// block shape nor S changes any result bit.
+// Loss partials of a query, (render r, tile t) of `tiles` per render: groups
+// of 16 renders, tile-major inside a group, so one tile's partials of 16
+// consecutive renders fill one 64-byte line (a wave writes them at once, and
+// the loss pass reads them coalesced).
+__host__ __device__ inline uint64_t part_index(uint64_t r, uint64_t t, uint64_t tiles) {
+  return ((r >> 4) * tiles + t) * 16u + (r & 15u);
+}
+inline uint64_t part_floats(uint64_t R, uint64_t tiles) { return ((R + 15) / 16) * 16 * tiles; }
+
 struct RasterQuery {
   const float4* rec;
   const float* target;

@@ -274,7 +274,7 @@ __device__ __forceinline__ void pt_block(const Consts& P, const double* __restri
   __syncthreads();
   for (int i = threadIdx.x; i < nd * NR; i += blockDim.x) {
     const float v = ((s_part[i][0] + s_part[i][1]) + s_part[i][2]) + s_part[i][3];
-    partial[(d0 * (uint64_t)NR + (uint64_t)i) * (uint64_t)tiles + tile] = v;
+    partial[part_index(d0 * (uint64_t)NR + (uint64_t)i, (uint64_t)tile, (uint64_t)tiles)] = v;
   }
 }
 

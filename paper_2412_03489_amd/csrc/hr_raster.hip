@@ -350,7 +350,8 @@ __device__ __forceinline__ void raster_block(const Query& a, const ConstExact* e
         s_qw + lane * 4);
     const float acc = dpp_quad_sum(((v.x + v.y) + v.z) + v.w);
     const int j = lane >> 2;
-    if (quad_head && j < cnt) partial[(r0 + (uint64_t)(f0 + j)) * subs + sub_w] = acc;
+    if (quad_head && j < cnt)
+      partial[part_index(r_base + r0 + (uint64_t)(f0 + j), sub_w, subs)] = acc;
   };
   if constexpr (kOneGroup) {
     // Up to 32 disks, lanes 0-31 hold the records of one render and lanes
@@ -676,7 +677,7 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
     a.rec = rec + r_base * (uint64_t)s.D;
     a.target = s.target;
     a.colors = s.colors;
-    a.partial = partial + r_base * (uint64_t)a.subs;
+    a.partial = partial;
     a.R = umin64(R - r_base, sub_chunks * (uint64_t)S);
     a.r_base = r_base;
     a.ex = ex;
