@@ -52,8 +52,8 @@ FLOP_PER_PIXEL = 12.0
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this SHA-256; reported as null once the source has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 489972313
-TRAFFIC_SOURCE_SHA256 = "c04fb59f20d09ad755d563350db13ad7932f08379f9f28e10bc2c85b32ba1059"
+TRAFFIC_BYTES_PER_LAUNCH = 449676017
+TRAFFIC_SOURCE_SHA256 = "73c957d73199553bff89c40ac55c6f9c62040c83f424dc58c3157816e7e14b2e"
 
 
 def raster_traffic():
