@@ -117,3 +117,38 @@ def test_nothing_covered(P, ctx):
 def test_extreme_sigma(P, ctx, sigma):
     w = make(48, 40, 6, seed=5, radius=(0.05, 0.15), sigma=sigma)
     check(P, ctx, w, N=128)
+
+
+def test_pixel_centres_on_disk_edges(P, ctx):
+    """A disk centred on a pixel centre with a 10-pixel radius passes exactly
+    through 12 pixel centres ((6, 8)-type offsets); with sigma = 1e-9 every
+    render leaves them inside the FP32 test's error band, so their coverage is
+    decided by the FP64 path from the unrounded parameters, in every render.
+    Per-render losses against the oracle (the estimates, 1/sigma-scaled
+    differences of near-equal losses, are covered by the other tests), and
+    the batch kernel's bits against the single query's."""
+    W = H = 64
+    c = 32.5 / 64.0
+    ts = np.array([c, c, 10.0 / 64.0, 0.25, 0.7, 0.1], np.float64)
+    col = np.array([[0.9, 0.3, 0.2], [0.1, 0.6, 0.8]], np.float32)
+    w = WL.DiskWorkload(name="edges_on_centres", W=W, H=H, C=3, ppd=3, colors=col, radius=None,
+                        theta_star=np.array([c + 0.01, c - 0.02, 0.15, 0.26, 0.69, 0.11]),
+                        theta0=ts, sigma=1e-9, N=256, seed=21,
+                        v=np.array([0.5, -0.5, 0.5, 0.0, 0.5, 0.0]))
+    tgt = disk_target(w)
+    osc, gsc = oracle_disks(w, tgt), gpu_disks(ctx, w, tgt)
+    for kind in ("grad", "hvp"):
+        say(f"{w.name} {kind}")
+        _, lref = O.estimate(kind, osc, w.theta0, w.sigma, w.N, w.seed, v=w.v,
+                             return_losses=True)
+        single, lgot = P.estimate(kind, gsc, w.theta0, w.sigma, w.N, w.seed, v=w.v,
+                                  return_losses=True)
+        # the edge pixels flip from render to render, and both sides agree on
+        # every flip: a wrong FP64 decision moves a loss by ~1e-4 relative
+        assert np.ptp(lref) > 1e-5 * np.abs(lref).max()
+        assert np.abs(lgot - lref).max() <= 1e-6 * np.abs(lref).max()
+        batched = P.Batch(ctx).run([dict(scene=gsc, kind=kind, theta=w.theta0, sigma=w.sigma,
+                                         N=w.N, seed=w.seed, v=w.v)] * 2)
+        for got in batched:
+            assert np.array_equal(got, single)
+    gsc.close()
