@@ -5,14 +5,16 @@
 // paper's tasks, section "Methods").  Work decomposition:
 //   block (256 threads = 4 wave64) = four 16x16 wave tiles (arranged 2x2,
 //   4x1 or 1x4) x S consecutive renders; each lane owns one pixel column of 4
-//   rows of its wave tile.  The target tile lives in registers for all S renders.  Per render a
-//   wave loads the disk records (one disk per lane, the next render's records
-//   already in flight), culls them against its sub-tile with a conservative
-//   circle/rectangle test, and walks the surviving disks in painter's order as
-//   a wave-uniform bit mask; with at most 64 disks the lanes park the
-//   records next to the disks' colours in LDS and a survivor's record is one
-//   broadcast LDS read, otherwise it comes by lane broadcasts.  Per pixel only
-//   the LDS address of the top disk's colour is kept.
+//   rows of its wave tile, and the target tile lives in registers for all S
+//   renders.  Per pass a wave loads disk records (one disk per lane; up to 32
+//   disks lanes 0-31 and 32-63 hold two renders, so one cull serves both; the
+//   next pass's records already in flight), culls them against its wave tile
+//   with a conservative circle/rectangle test, and walks each render's
+//   surviving disks in painter's order as a wave-uniform bit mask; with at
+//   most 64 disks the lanes park the records next to the disks' colours in
+//   LDS and a survivor's record is one broadcast LDS read, otherwise it comes
+//   by lane broadcasts.  Per pixel only the LDS address of the top disk's
+//   colour is kept.
 //
 // Coverage is decided exactly as the FP64 definition: every record carries
 // r^2 widened and narrowed by the FP32 error band of the test; the FP32 test
@@ -20,10 +22,10 @@
 // pixel inside its band takes a wave-uniform branch that rebuilds that disk's
 // unrounded parameters and decides those pixels in FP64 (rare).
 //
-// A sub-tile that no disk reaches renders as background; its loss is the
-// sub-tile's sum of T^2, computed once per block with the same arithmetic.
-// Per render each wave folds its lanes in quads (two DPP adds) and parks 16
-// partials in LDS; after the S renders the block sums each wave's 16 in a
+// A wave tile that no disk reaches renders as background; its loss is the
+// tile's sum of T^2, computed once per block with the same arithmetic.  Per
+// render each wave folds its lanes in quads (two DPP adds) and parks the 16
+// quad sums in LDS; every 16 renders the wave sums each render's 16 in a
 // fixed order, giving one FP32 partial per (render, wave tile) -- the same
 // bits for any block shape and any S.
 #include <type_traits>
