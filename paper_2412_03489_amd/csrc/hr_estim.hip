@@ -523,10 +523,16 @@ void launch_prep(hipStream_t st, const EstShape& e, const double* f, const doubl
                      vnorm, v, Fq, vt);
 }
 
+// Draws per accumulation chunk: as many as LDS holds (at most 256), but for
+// few outputs (a block's threads are its outputs, each summing its chunk's
+// draws in one dependent chain) no more than max(16, N / 512), so that short
+// chains over many blocks replace long chains over a few.
 int accum_chunk(const EstShape& e) {
   if (per_element(e.sampler)) return 256;
   int c = kLdsDoubles / e.n;
   if (c > 256) c = 256;
+  const uint64_t lim = e.N / 512 > 16 ? e.N / 512 : 16;
+  if ((uint64_t)c > lim) c = (int)lim;
   if (c < 1) c = 1;
   return c;
 }
