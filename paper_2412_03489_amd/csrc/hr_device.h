@@ -82,7 +82,10 @@ __device__ inline double lambert_w(double z, bool lower) {
   } else {
     w = z;
   }
-  for (int it = 0; it < 64; ++it) {
+  // Halley's step is cubically convergent: once it falls to a few ulp of w,
+  // w is exact to the last ulp (a tighter test can stall on rounding noise
+  // and run every iteration)
+  for (int it = 0; it < 32; ++it) {
     double ew = exp(w);
     double f = w * ew - z;
     double w1 = w + 1.0;
@@ -91,7 +94,7 @@ __device__ inline double lambert_w(double z, bool lower) {
     if (den == 0.0) break;
     double dw = f / den;
     w -= dw;
-    if (fabs(dw) <= 1e-16 * (1.0 + fabs(w))) break;
+    if (fabs(dw) <= 0x1p-50 * (1.0 + fabs(w))) break;
   }
   return w;
 }
