@@ -62,10 +62,22 @@ __device__ __forceinline__ void sample_one(int n, int K, int hessk, int mix_n2, 
     else lg = (j == i || j == jj);
   }
   double t;
-  if (ld) t = hdiag_lobe(w.z, sg);
-  else if (lg) t = grad_lobe(w.z, sg);
-  else if (sampler == kFR22) t = 0.0;   // only the differentiated dimension is blurred
-  else t = sg * sqrt(-2.0 * log(u01_d(w.x))) * cos(2.0 * kPi * u01_d(w.y));
+  if (ld) {
+    t = hdiag_lobe(w.z, sg);
+  } else if (sampler == kFR22 && !lg) {
+    t = 0.0;   // only the differentiated dimension is blurred
+  } else {
+    // the gradient lobe's Rayleigh magnitude and the Box-Muller radius share
+    // one sqrt(-2 log x), so the lobe's lane does not run its own copy while
+    // the rest of the wave waits: the same operations on the same operands as
+    // grad_lobe and the Gaussian below
+    const uint32_t wz = w.z;
+    const bool lo = wz < 0x80000000u;
+    const double x = lg ? fma((double)(lo ? wz : 0xFFFFFFFFu - wz), 0x1p-31, 0x1p-32)
+                        : u01_d(w.x);
+    const double rad = sqrt(-2.0 * log(x));
+    t = lg ? (lo ? -sg : sg) * rad : sg * rad * cos(2.0 * kPi * u01_d(w.y));
+  }
   tau[gid] = t;
 }
 
