@@ -62,12 +62,22 @@ __device__ __forceinline__ void record_one(const double* __restrict__ theta,
                                            const float* __restrict__ radius, int n, int D, int ppd,
                                            int A, int NH, double h, uint64_t gid,
                                            float4* __restrict__ rec) {
-  const int k = (int)(gid % (uint64_t)D);
-  const uint64_t r = gid / (uint64_t)D;
-  const int sh = (int)(r % (uint64_t)NH);
-  const uint64_t rem = r / (uint64_t)NH;
-  const int ai = (int)(rem % (uint64_t)A);
-  const uint64_t sidx = rem / (uint64_t)A;
+  // render r = (draw * A + a) * NH + shift with A, NH in {1, 2}: one division
+  // (32-bit while the index fits) and bit operations
+  int k;
+  uint64_t r;
+  if (gid >> 32 == 0) {
+    const uint32_t r32 = (uint32_t)gid / (uint32_t)D;
+    k = (int)((uint32_t)gid - r32 * (uint32_t)D);
+    r = r32;
+  } else {
+    r = gid / (uint64_t)D;
+    k = (int)(gid - r * (uint64_t)D);
+  }
+  const int sh = NH == 2 ? (int)(r & 1u) : 0;
+  const uint64_t rem = NH == 2 ? r >> 1 : r;
+  const int ai = A == 2 ? (int)(rem & 1u) : 0;
+  const uint64_t sidx = A == 2 ? rem >> 1 : rem;
   const double* t = tau + sidx * (uint64_t)n;
   const double a = ai == 0 ? 1.0 : -1.0;
   const double shift = sh == 0 ? h : -h;
