@@ -281,7 +281,21 @@ __device__ __forceinline__ void accum_block(const EstShape& e, const double* __r
   __syncthreads();   // the previous task's readers of LDS are done
   const uint64_t s0 = c * (uint64_t)chunk;
   const int ns = (int)min((uint64_t)chunk, e.N - s0);
-  for (int i = threadIdx.x; i < ns * e.n; i += blockDim.x) s_tau[i] = tau[s0 * e.n + i];
+  {
+    // eight loads in flight per thread before their LDS stores (a plain loop
+    // waits for every load before the next one is issued)
+    const double* __restrict__ src = tau + s0 * (uint64_t)e.n;
+    const int tot = ns * e.n, st = (int)blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * st < tot; i += 8 * st) {
+      double r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = src[i + u * st];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s_tau[i + u * st] = r[u];
+    }
+    for (; i < tot; i += st) s_tau[i] = src[i];
+  }
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
     s_F[i] = Fq[s0 + i];
     s_vt[i] = e.what == kHvpLimit ? vt[s0 + i] : 0.0;
