@@ -212,7 +212,7 @@ void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBu
     AnalyticScene as{sc->kind == kQuad ? 0 : 1, sc->n, sc->A, sc->b, sc->c, sc->s1};
     launch_analytic(s, e, as, d_theta, tau, u, f);
   }
-  launch_prep(s, e, f, tau, vnorm, d_v, Fq, vt);
+  T("prep", [&] { launch_prep(s, e, f, tau, vnorm, d_v, Fq, vt); });
   T("accumulate", [&] { launch_accum(s, e, tau, Fq, vt, d_v, o.accum_fp64, acc, chunk); });
   launch_finalize(s, e, acc, o.accum_fp64, chunk, d_out);
 }

@@ -214,15 +214,33 @@ __device__ __forceinline__ void prep_one(const EstShape& e, const double* __rest
       if (!e.hessk) {
         // q = 1/K sum_k |d_k| / Z_G with |d_k| = |t_k| / sigma^2
         const double c = iv.is2 / z_grad(sg);
-        for (int k = 0; k < e.n; ++k) q += fabs(t[k]) * c;
+        // loads eight ahead of the (ordered) additions
+        int k = 0;
+        for (; k + 8 <= e.n; k += 8) {
+          double tk[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) tk[u] = t[k + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) q += fabs(tk[u]) * c;
+        }
+        for (; k < e.n; ++k) q += fabs(t[k]) * c;
       } else {
         const double izd = 1.0 / z_diag(sg), izo = 1.0 / (z_grad(sg) * z_grad(sg));
         double l1 = 0.0, l2 = 0.0, qd = 0.0;
-        for (int k = 0; k < e.n; ++k) {
-          qd += fabs(t[k] * t[k] * iv.is4 - iv.is2) * izd;
-          l1 += fabs(t[k]);
-          l2 += t[k] * t[k];
+        auto add = [&](double tk) {
+          qd += fabs(tk * tk * iv.is4 - iv.is2) * izd;
+          l1 += fabs(tk);
+          l2 += tk * tk;
+        };
+        int k = 0;
+        for (; k + 8 <= e.n; k += 8) {
+          double tk[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) tk[u] = t[k + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) add(tk[u]);
         }
+        for (; k < e.n; ++k) add(t[k]);
         // sum_{i<j} |t_i t_j| = ((sum |t_i|)^2 - sum t_i^2) / 2; the n^2 mixture
         // counts each off-diagonal pair twice and divides by n^2
         const double off = 0.5 * (l1 * l1 - l2) * iv.is4 * izo;
