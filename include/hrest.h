@@ -386,12 +386,15 @@ hr_status hr_batch_tuned(hr_ctx* ctx, const hr_scene* sc, int* samples_per_block
 typedef struct {
   int slots;                /* batches in flight (default 4)                    */
   int max_batch;            /* queries per batch (default 64)                   */
-  double max_batch_ms;      /* predicted device time per batch (default 4 ms;
+  double max_batch_ms;      /* predicted device time per batch (default 2 ms;
                                <= 0: no limit).  The prediction is a static
                                cost model (renders x pixels for the
                                rasteriser, x samples per pixel for the path
                                tracer, draws x elements for the lobe sums);
-                               a query is always admitted into an empty batch */
+                               a query is always admitted into an empty batch.
+                               A query that fills the cap alone runs as a
+                               one-query batch on the per-query kernels;
+                               smaller ones share the batch's launches.      */
   uint64_t memory_bytes;    /* device workspace across all slots
                                (default: the context's memory budget)           */
   int use_graph;            /* as in hr_batch_opts (default 1)                  */

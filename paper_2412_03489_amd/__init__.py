@@ -551,7 +551,7 @@ def tuned(ctx, scene):
 class Server:
     """Continuous-batching server (hr_server)."""
 
-    def __init__(self, ctx, slots=4, max_batch=64, max_batch_ms=4.0, memory_bytes=0,
+    def __init__(self, ctx, slots=4, max_batch=64, max_batch_ms=2.0, memory_bytes=0,
                  use_graph=True, autotune=False):
         o = ServerOpts(int(slots), int(max_batch), float(max_batch_ms), int(memory_bytes),
                        1 if use_graph else 0, 1 if autotune else 0)

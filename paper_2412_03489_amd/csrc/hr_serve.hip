@@ -177,7 +177,7 @@ void hr_server_opts_default(hr_server_opts* o) {
   if (!o) return;
   o->slots = 4;
   o->max_batch = 64;
-  o->max_batch_ms = 4.0;
+  o->max_batch_ms = 2.0;
   o->memory_bytes = 0;
   o->use_graph = 1;
   o->autotune = 0;

@@ -156,7 +156,7 @@ def _first_ready(clients, think_ms, window_s=None):
     return ev
 
 
-def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=4.0, memory_bytes=16 << 30,
+def run_served(ctx, clients, slots=4, max_batch=64, max_batch_ms=2.0, memory_bytes=16 << 30,
                use_graph=True, think_ms=None, window_s=None):
     """All clients through one continuous-batching server.  think_ms None: open
     loop (queries back to back after the client's arrival); else closed loop
