@@ -53,8 +53,8 @@ FLOP_PER_PIXEL = 12.0
 # (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
 # this code digest (code_digest: comments and blank lines left out); reported
 # as null once the code has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 450663578
-TRAFFIC_SOURCE_DIGEST = "83996c219627d979a173e29bf651cafa2a7d7c79d1acb868953713a5d7a0391c"
+TRAFFIC_BYTES_PER_LAUNCH = 448712664
+TRAFFIC_SOURCE_DIGEST = "ba57068a32b5120e10a9182d6bd231d55a69d65793b3fd7ae4c9c0652832a36f"
 
 
 def code_digest(path):

@@ -133,9 +133,9 @@ static void raster_config(hr_ctx* ctx, const hr_scene* sc, const hr_opts& o, uin
       if (*shape <= 0) *shape = it->second.second;
     }
   }
-  if (*S <= 0) *S = raster_auto_samples(sc->W, sc->H, R);
-  if (*S > raster_max_samples()) *S = raster_max_samples();
   if (*shape < 0 || *shape > 3) *shape = 0;
+  if (*S <= 0) *S = raster_auto_samples(sc->W, sc->H, R, *shape);
+  if (*S > raster_max_samples()) *S = raster_max_samples();
 }
 
 hr_status BatchSlot::build(std::vector<BatchItem>& items) {

@@ -82,7 +82,7 @@ struct RasterQuery {
 void raster_block_shape(int shape, int W, int H, int* bwx, int* bwy);
 size_t raster_lds_bytes(int D, int S);
 int raster_max_samples();
-int raster_auto_samples(int W, int H, uint64_t R);
+int raster_auto_samples(int W, int H, uint64_t R, int shape);
 // fills the geometry fields of a RasterQuery (W, H must be set)
 void raster_geometry(RasterQuery& a, int shape);
 void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,

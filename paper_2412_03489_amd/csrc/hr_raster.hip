@@ -654,13 +654,14 @@ size_t raster_lds_bytes(int D, int S) {
 int raster_max_samples() { return kMaxS; }
 
 // S = 0 (the library's choice): the largest of 256, 128, 64 and 32 renders
-// per block that still gives the launch at least 128 * S blocks (at 32
+// per block that still gives the launch (with the given block shape) at least
+// 128 * S blocks (at 32
 // renders per block, about two rounds of the blocks the chip holds at once).  Longer render runs per
 // block amortise the per-block set-up (colour tables, target, cull
 // rectangle); shorter ones keep small queries spread over all CUs.
-int raster_auto_samples(int W, int H, uint64_t R) {
+int raster_auto_samples(int W, int H, uint64_t R, int shape) {
   int bwx, bwy;
-  raster_block_shape(0, W, H, &bwx, &bwy);
+  raster_block_shape(shape, W, H, &bwx, &bwy);
   const uint64_t tiles = (uint64_t)((W + kSub * bwx - 1) / (kSub * bwx)) *
                          (uint64_t)((H + kSub * bwy - 1) / (kSub * bwy));
   for (int S = 256; S > 32; S /= 2)
@@ -670,7 +671,7 @@ int raster_auto_samples(int W, int H, uint64_t R) {
 
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
                         int S, int shape, const RasterExact& ex, float* partial) {
-  if (S <= 0) S = raster_auto_samples(s.W, s.H, R);
+  if (S <= 0) S = raster_auto_samples(s.W, s.H, R, shape);
   if (S > kMaxS) S = kMaxS;
   RasterQuery a;
   a.W = s.W; a.H = s.H; a.C = s.C; a.D = s.D; a.S = S;
