@@ -1,0 +1,41 @@
+"""Host logic of bench.py (no GPU): the measured raster traffic stays valid
+across comment edits of the kernel source and lapses when its code changes;
+more than one GPU is refused with a message."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_code_digest_ignores_comments_and_blank_lines(tmp_path):
+    B = _bench()
+    a = tmp_path / "a.hip"
+    a.write_text("int f(int x) {  // doubles\n  return 2 * x;\n}\n")
+    b = tmp_path / "b.hip"
+    b.write_text("// a header comment\n\nint f(int x) {\n  return 2 * x;   // twice\n}\n\n")
+    c = tmp_path / "c.hip"
+    c.write_text("int f(int x) {\n  return 3 * x;\n}\n")
+    assert B.code_digest(str(a)) == B.code_digest(str(b))
+    assert B.code_digest(str(a)) != B.code_digest(str(c))
+
+
+def test_traffic_constant_matches_the_committed_raster_source():
+    """The traffic figure reported by the bench belongs to this kernel source."""
+    B = _bench()
+    assert B.raster_traffic() == B.TRAFFIC_BYTES_PER_LAUNCH
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
