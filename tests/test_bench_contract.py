@@ -1,6 +1,6 @@
 """Host logic of bench.py (no GPU): the measured raster traffic stays valid
-across comment edits of the kernel source and lapses when its code changes;
-more than one GPU is refused with a message."""
+across comment edits of the kernel source and is reported as null once its
+code changes; more than one GPU is refused with a message."""
 import importlib.util
 import os
 import subprocess
@@ -28,9 +28,15 @@ def test_code_digest_ignores_comments_and_blank_lines(tmp_path):
     assert B.code_digest(str(a)) != B.code_digest(str(c))
 
 
-def test_traffic_constant_matches_the_committed_raster_source():
-    """The traffic figure reported by the bench belongs to this kernel source."""
+def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch):
+    """A changed kernel source makes the bench report traffic as null."""
     B = _bench()
+    src = tmp_path / "paper_2412_03489_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "hr_raster.hip").write_text("int g() { return 1; }\n")
+    monkeypatch.setattr(B, "ROOT", str(tmp_path))
+    assert B.raster_traffic() is None
+    monkeypatch.setattr(B, "TRAFFIC_SOURCE_DIGEST", B.code_digest(str(src / "hr_raster.hip")))
     assert B.raster_traffic() == B.TRAFFIC_BYTES_PER_LAUNCH
 
 
