@@ -1,6 +1,7 @@
 // hr_kernels.h -- launch interface between the host runtime (hr_api.hip) and
 // the device kernels (hr_raster.hip, hr_estim.hip, hr_pt.hip, hr_solve.hip).
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -77,6 +78,8 @@ struct RasterQuery {
   uint64_t R, r_base;
   RasterExact ex;
 };
+// the per-query raster kernel finds `ex` in its kernel arguments by offsetof
+static_assert(std::is_standard_layout<RasterQuery>::value, "RasterQuery is read by offsetof");
 // block shapes: 1 = 32x32, 2 = 64x16, 3 = 16x64, 0 = the fewest blocks for a
 // W x H image (ties: 16x64, then 32x32)
 void raster_block_shape(int shape, int W, int H, int* bwx, int* bwy);
