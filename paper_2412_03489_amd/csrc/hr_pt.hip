@@ -284,13 +284,17 @@ typedef const PTConst __attribute__((address_space(4))) ConstPT;
 // address space: scalar loads on use, and no private copy (a by-value
 // argument passed by reference to the tracing routines would be copied to
 // scratch).
+// Two renders per draw (a Hessian or gradient with antithetic pairs): at least
+// 6 waves per SIMD (80 VGPRs, a few bytes of spills outside the path loop)
+// are 3% faster than the 5 the compiler picks by itself; 7 spill too much.
 template <int NR>
-__global__ __launch_bounds__(256) void k_pt_loss(const PTConst* ptc, const double* __restrict__ theta,
-                                                 const double* __restrict__ tau,
-                                                 const double* __restrict__ u,
-                                                 const float* __restrict__ target, EstShape e,
-                                                 int S, int tiles_x, int tiles, uint64_t draw0,
-                                                 uint64_t chunks, float* __restrict__ partial) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NR == 2 ? 6 : 1)))
+void k_pt_loss(const PTConst* ptc, const double* __restrict__ theta,
+               const double* __restrict__ tau,
+               const double* __restrict__ u,
+               const float* __restrict__ target, EstShape e,
+               int S, int tiles_x, int tiles, uint64_t draw0,
+               uint64_t chunks, float* __restrict__ partial) {
   __shared__ float s_part[kPtMaxS * NR][4];
   // XCD-aware order as in the rasteriser
   const uint64_t b = blockIdx.x;
