@@ -280,7 +280,7 @@ __device__ __forceinline__ double kfac(const EstShape& e, const InvSigma& iv, in
 struct Lobes32 { fsum2 pos, neg; };
 
 // aggregate / Gaussian / limit HVP: block = chunk of draws, threads = elements
-constexpr int kLdsDoubles = 6144;   // 48 KiB of draws per chunk
+constexpr int kLdsDoubles = 3072;   // 24 KiB of draws per chunk (six blocks per CU)
 
 struct AccumLds {
   double tau[kLdsDoubles];
