@@ -110,7 +110,7 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
   if (what == kHess && o.sampler == kFR22)
     return fail(HR_EUNSUPPORTED, "the FR22 comparator estimates gradients and HVPs only");
   if (what == kHvp && !(o.hvp_rel_step > 0.0)) return fail(HR_EINVAL, "hvp_rel_step must be positive");
-  if (sc->n < 1 || sc->n > 6144) return fail(HR_EINVAL, "parameter count out of range");
+  if (sc->n < 1 || sc->n > kMaxParams) return fail(HR_EINVAL, "parameter count out of range");
 
   EstShape& e = p->e;
   e = EstShape{};

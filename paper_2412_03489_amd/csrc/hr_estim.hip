@@ -281,6 +281,7 @@ struct Lobes32 { fsum2 pos, neg; };
 
 // aggregate / Gaussian / limit HVP: block = chunk of draws, threads = elements
 constexpr int kLdsDoubles = 3072;   // 24 KiB of draws per chunk (six blocks per CU)
+static_assert(kLdsDoubles >= kMaxParams, "a chunk holds at least one draw of every scene");
 
 struct AccumLds {
   double tau[kLdsDoubles];

@@ -56,6 +56,10 @@ struct RasterExact {
 // 16x16 pixels and S renders per work item; the loss partial of every wave
 // tile is written to partial[part_index(r, wave tile, subs)], so neither the
 // block shape nor S changes any result bit.
+// Largest parameter count of any scene (1024 disks x 3); the lobe
+// accumulation stages at least one draw of that many doubles in LDS.
+constexpr int kMaxParams = 3072;
+
 // Loss partials of a query, (render r, tile t) of `tiles` per render: groups
 // of 16 renders, tile-major inside a group, so one tile's partials of 16
 // consecutive renders fill one 64-byte line (a wave writes them at once, and
