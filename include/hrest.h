@@ -56,7 +56,8 @@ typedef enum {
   HR_ENOMEM = -2,
   HR_EDEVICE = -3,
   HR_EUNSUPPORTED = -4,
-  HR_EBUSY = -5,          /* nothing completed within the wait's time limit */
+  HR_EBUSY = -5,          /* nothing completed within the wait's time limit, or
+                             another thread already waits on the ticket       */
 } hr_status;
 
 /* Sampler (section "Aggregate", table of evaluations per draw).
@@ -170,7 +171,9 @@ hr_status hr_scene_quad(hr_ctx* ctx, int n, const double* A, const double* b, do
 hr_status hr_scene_neggauss(hr_ctx* ctx, int n, double s1, hr_scene** out);
 /* Frees a scene.  A scene belongs to its context: destroying the context
  * first releases the scene's device memory and orphans it -- every later call
- * with it returns HR_EINVAL, and hr_scene_destroy still frees the handle. */
+ * with it returns HR_EINVAL, and hr_scene_destroy still frees the handle.
+ * Queries a server holds on the scene (submitted, not yet finished) complete
+ * first: the call blocks until they have. */
 void hr_scene_destroy(hr_scene* sc);
 int hr_scene_nparams(const hr_scene* sc);
 
@@ -382,7 +385,8 @@ hr_status hr_batch_tuned(hr_ctx* ctx, const hr_scene* sc, int* samples_per_block
  * memory_bytes, and launches it at once -- so queries arriving while others
  * are on the GPU start in the next free slot and their work overlaps with the
  * batches in flight.  Results are the same bits as the single-query entry
- * points give.  Scenes must outlive the queries submitted on them. */
+ * points give.  hr_scene_destroy on a scene with queries still held by a
+ * server blocks until they have finished. */
 typedef struct {
   int slots;                /* batches in flight (default 4)                    */
   int max_batch;            /* queries per batch (default 64)                   */
@@ -426,7 +430,9 @@ void hr_server_destroy(hr_server* s);
 hr_status hr_submit(hr_server* s, const hr_query* q, uint64_t* ticket);
 /* Blocks until the query is done, copies its result to `out` (sized as in
  * hr_query_kind) and its timings to `stats` (either may be NULL), and retires
- * the ticket.  Returns the query's status; HR_EINVAL for unknown tickets. */
+ * the ticket.  Returns the query's status; HR_EINVAL for unknown or retired
+ * tickets; HR_EBUSY if another thread is already waiting on the ticket (one
+ * waiter per ticket). */
 hr_status hr_wait(hr_server* s, uint64_t ticket, double* out, hr_query_stats* stats);
 /* Waits up to timeout_ms (< 0: no limit) for any completed, not yet retired
  * query and returns its ticket; HR_EBUSY if none completed in time. */

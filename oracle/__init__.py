@@ -78,6 +78,8 @@ def lib():
         L.orc_scene_nparams.argtypes = [vp]; L.orc_scene_nparams.restype = i
         L.orc_render.argtypes = [vp, vp, u64, u32, i, vp]; L.orc_render.restype = i
         L.orc_loss.argtypes = [vp, vp, u64, u32]; L.orc_loss.restype = d
+        L.orc_pt_trace.argtypes = [vp, vp, vp, vp, vp]; L.orc_pt_trace.restype = i
+        L.orc_pt_path.argtypes = [vp, vp, vp, vp, vp, vp]; L.orc_pt_path.restype = i
         L.orc_draw_tau.argtypes = [i, i, d, u64, u32, i, i, i, vp, vp]; L.orc_draw_tau.restype = i
         for nm in ("orc_est_grad", "orc_est_hessian"):
             getattr(L, nm).argtypes = [vp, vp, d, u64, u64, C.POINTER(Opts), vp]
@@ -196,6 +198,29 @@ def render(scene, theta, H, W, C_, seed=0, s=0, spp=0):
     if st:
         raise ValueError(f"orc_render failed ({st})")
     return out.reshape(H, W, C_)
+
+
+def pt_trace(scene, theta, o, d):
+    """(object id, distance) of the path tracer's closest hit along o + t d:
+    id -1 none, 0..ns-1 sphere, ns ground plane, ns+1 light."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    oo = np.ascontiguousarray(o, dtype=np.float64)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    t = C.c_double(0.0)
+    hit = lib().orc_pt_trace(scene.h, _p(th), _p(oo), _p(dd), C.byref(t))
+    return hit, t.value
+
+
+def pt_path(scene, theta, o, d, u):
+    """Radiance (3 doubles) of one path from o along unit d with uniforms u[8]."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    oo = np.ascontiguousarray(o, dtype=np.float64)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    L = np.zeros(3)
+    if lib().orc_pt_path(scene.h, _p(th), _p(oo), _p(dd), _p(uu), _p(L)):
+        raise ValueError("orc_pt_path rejected its arguments")
+    return L
 
 
 def loss(scene, theta, seed=0, s=0):

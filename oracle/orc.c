@@ -10,12 +10,15 @@
  * paper is silent or garbled, the reading taken is stated next to the code.
  *
  * Parity pins (what checks this file against something other than itself) live
- * in tests/test_oracle_*.py: quadrature of lobe masses, CDF anchors, KS tests,
- * closed forms for quadratic, negated-Gaussian, half-plane and corner scenes,
- * and exact smoothed derivatives of the one-disk scene by contour quadrature.
- * Parity unpinned: the exact output bits of Philox4x32-10 (statistically
- * pinned only) and the path tracer's estimator beyond invariants and the
- * polygon-light irradiance of its direct term.
+ * in tests/test_oracle_*.py: Philox4x32-10 known-answer vectors and an
+ * independent implementation, quadrature of lobe masses, CDF anchors, KS
+ * tests, closed forms for quadratic, negated-Gaussian, half-plane and corner
+ * scenes, exact smoothed derivatives of the one-disk scene by contour
+ * quadrature, hand-built disk images (painter's order, colours, radius from
+ * theta, r <= 0, strict edges), the exact smoothed loss of overlapping RGB
+ * disks with radius parameters, and the path tracer's ray hits, shadows,
+ * direct light (Lambert's polygon formula) and one-bounce indirect light
+ * (quadrature over the sphere's surface).
  */
 #include "orc.h"
 
@@ -471,6 +474,35 @@ static void render_pt(const orc_scene* sc, const double* th, uint64_t seed, uint
       for (int ch = 0; ch < 3; ++ch) out[(size_t)pix * 3 + ch] = acc[ch] / spp;
     }
   }
+}
+
+/* Hooks of the path tracer for the tests' pins: the closest hit along a ray
+ * (object id as pt_intersect: -1 none, 0..ns-1 sphere, ns plane, ns+1 light;
+ * *t its distance), and the radiance of one path from o along the unit
+ * direction d with the eight uniforms u (2-3: light point at the first hit,
+ * 4-5: bounce, 6-7: light point at the second hit; 0-1 are the pixel jitter
+ * and unused here). */
+static pt_ctx pt_ctx_of(const orc_scene* sc, const double* th) {
+  pt_ctx c;
+  c.sc = sc;
+  c.light = mk(th[0], th[1], th[2]);
+  c.s0 = mk(th[3], th[4], th[5]);
+  return c;
+}
+
+int orc_pt_trace(const orc_scene* sc, const double* theta, const double* o, const double* d,
+                 double* t) {
+  if (!sc || sc->kind != SC_PT || !theta || !o || !d || !t) return -2;
+  pt_ctx c = pt_ctx_of(sc, theta);
+  return pt_intersect(&c, mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]), t);
+}
+
+int orc_pt_path(const orc_scene* sc, const double* theta, const double* o, const double* d,
+                const double* u, double* L) {
+  if (!sc || sc->kind != SC_PT || !theta || !o || !d || !u || !L) return -1;
+  pt_ctx c = pt_ctx_of(sc, theta);
+  pt_radiance(&c, mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]), u, L);
+  return 0;
 }
 
 int orc_render(const orc_scene* sc, const double* theta, uint64_t seed, uint32_t s,

@@ -67,6 +67,15 @@ int orc_scene_nparams(const orc_scene* sc);
  * pixel randomness of the path tracer (ignored by the rasterizer). */
 int orc_render(const orc_scene* sc, const double* theta, uint64_t seed, uint32_t s,
                int spp_override, double* out);
+/* path tracer hooks for the pins: closest hit along the ray o + t d (returns
+ * -1 none, 0..ns-1 sphere, ns ground plane, ns+1 light; *t its distance), and
+ * the radiance of one path from o along unit d with uniforms u[8] (u[2..3]
+ * light point at the first hit, u[4..5] bounce, u[6..7] light point at the
+ * second hit) into L[3]. */
+int orc_pt_trace(const orc_scene* sc, const double* theta, const double* o, const double* d,
+                 double* t);
+int orc_pt_path(const orc_scene* sc, const double* theta, const double* o, const double* d,
+                const double* u, double* L);
 /* the loss f(theta) = mean over H*W*C of (I - T)^2, or the analytic function */
 double orc_loss(const orc_scene* sc, const double* theta, uint64_t seed, uint32_t s);
 

@@ -568,6 +568,11 @@ hr_status hr_scene_neggauss(hr_ctx* ctx, int n, double s1, hr_scene** out) {
 
 void hr_scene_destroy(hr_scene* sc) {
   if (!sc) return;
+  {
+    // a server may still hold queries on the scene: they finish first
+    std::unique_lock<std::mutex> lk(sc->hold_mu);
+    sc->hold_cv.wait(lk, [&] { return sc->held == 0; });
+  }
   if (sc->ctx) {   // an orphaned scene (context destroyed first) holds no memory
     (void)hipSetDevice(sc->ctx->device);
     (void)hipStreamSynchronize(sc->ctx->stream);

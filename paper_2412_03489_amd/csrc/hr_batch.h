@@ -59,8 +59,9 @@ struct BatchSlot {
   hr_status reserve_table(size_t bytes);
   // lays out the table for `items` in the pinned mirror (sets ws_off/out_off)
   hr_status build(std::vector<BatchItem>& items);
-  // upload, launch (graph replay or eager), download, record `done`
-  hr_status enqueue(bool use_graph);
+  // upload, launch (graph replay or eager), download, record `done`; with
+  // timing_ok false the launches are never timed, whatever the context says
+  hr_status enqueue(bool use_graph, bool timing_ok = true);
   // copies each item's result from the pinned mirror to its destination
   void scatter(const std::vector<BatchItem>& items) const;
   void launches(hipStream_t st, bool time_phases);

@@ -399,7 +399,7 @@ unsigned BatchSlot::classes() const {
   return m;
 }
 
-hr_status BatchSlot::enqueue(bool use_graph) {
+hr_status BatchSlot::enqueue(bool use_graph, bool timing_ok) {
   HR_HIP(hipSetDevice(ctx->device));
   (void)hipGetLastError();
   const unsigned cl = classes();
@@ -407,7 +407,7 @@ hr_status BatchSlot::enqueue(bool use_graph) {
     if (cl & (1u << c)) raster_blocks[c] = cus * batch_raster_blocks_per_cu(c, lds);
   HR_HIP(hipMemcpyAsync(dev, host, upload_bytes_, hipMemcpyHostToDevice, stream));
   graph_used = false;
-  const bool timing = allow_timing && ctx->timing;
+  const bool timing = allow_timing && timing_ok && ctx->timing;
   // a one-query batch launches its per-query kernels directly: their launch
   // parameters are the query's own, so a captured sequence would not be reusable
   if (use_graph && !timing && !single_) {
@@ -450,12 +450,6 @@ void BatchSlot::scatter(const std::vector<BatchItem>& items) const {
 // ---------------------------------------------------------------- autotuner
 hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) {
   hr_ctx* ctx = slot.ctx;
-  struct KeepTiming {   // the tuning launches are not part of the kernel stats
-    hr_ctx* c;
-    bool was;
-    ~KeepTiming() { c->timing = was; }
-  } keep{ctx, ctx->timing};
-  ctx->timing = false;
   // classes present and not yet tuned
   std::map<uint64_t, std::vector<int>> classes;
   {
@@ -490,7 +484,9 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
         }
         st = slot.build(sub);
         if (st) break;
-        st = slot.enqueue(false);   // prepare draws and records (first pass)
+        // prepare draws and records (first pass); the tuning launches are
+        // never timed into the context's kernel stats
+        st = slot.enqueue(false, false);
         if (st) break;
         // time the raster kernel alone, twice, on the prepared records
         const BatchTable* T = (const BatchTable*)slot.dev;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <condition_variable>
 #include <map>
 #include <mutex>
 #include <set>
@@ -54,6 +55,11 @@ struct hr_scene {
   double* A = nullptr;
   double* b = nullptr;
   double c = 0.0, s1 = 1.0;
+  // queries a server holds on this scene (waiting or on the device);
+  // hr_scene_destroy waits for them to finish
+  std::mutex hold_mu;
+  std::condition_variable hold_cv;
+  int held = 0;
 };
 
 namespace hr {

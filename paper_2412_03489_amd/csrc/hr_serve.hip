@@ -54,6 +54,7 @@ struct Ticket {
   std::vector<double> theta, v, result;
   hr_query_stats stats{};
   int state = 0;   // 0 waiting, 1 on the device, 2 done
+  bool waited = false;   // a thread is blocked in hr_wait on this ticket
 };
 
 struct Flight {
@@ -61,6 +62,17 @@ struct Flight {
   std::vector<BatchItem> items;
   std::vector<Ticket*> tickets;
 };
+
+// A query held by a server (waiting or on the device) pins its scene:
+// hr_scene_destroy waits until the count drops to zero.
+void scene_hold(hr_scene* sc) {
+  std::lock_guard<std::mutex> lk(sc->hold_mu);
+  ++sc->held;
+}
+void scene_release(hr_scene* sc) {
+  std::lock_guard<std::mutex> lk(sc->hold_mu);
+  if (--sc->held == 0) sc->hold_cv.notify_all();
+}
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -97,6 +109,7 @@ struct hr_server {
       t->stats.end_ms = now;
       t->stats.status = status;
       completed.push_back(t->id);
+      scene_release(t->item.plan.sc);
     }
     st.completed += f.tickets.size();
     f.items.clear();
@@ -106,7 +119,11 @@ struct hr_server {
     cv_done.notify_all();
   }
 
-  void launch(int i) {
+  // Forms slot i's batch from the waiting queries (under the lock held by
+  // `lk`), then releases the lock while the batch is tuned, laid out and
+  // enqueued: the flight is the worker's alone once marked busy, and callers
+  // of hr_submit / hr_wait / hr_wait_any are never held up by that host work.
+  void launch(int i, std::unique_lock<std::mutex>& lk) {
     Flight& f = flights[i];
     size_t ws = 0;
     double work = 0.0;
@@ -132,14 +149,14 @@ struct hr_server {
     if (busy_slots++ == 0) busy_since = now;
     st.batches += 1;
     launched += f.items.size();
+    lk.unlock();
     hr_status s = HR_OK;
     if (opts.autotune) s = autotune_raster(slots[i], f.items);
     if (!s) s = slots[i].build(f.items);
-    if (!s) s = slots[i].enqueue(opts.use_graph != 0);
-    if (s) {
-      (void)hipStreamSynchronize(slots[i].stream);
-      finish_flight(i, s);
-    }
+    if (!s) s = slots[i].enqueue(opts.use_graph != 0, false);
+    if (s) (void)hipStreamSynchronize(slots[i].stream);
+    lk.lock();
+    if (s) finish_flight(i, s);
   }
 
   void run() {
@@ -161,7 +178,7 @@ struct hr_server {
       }
       for (int i = 0; i < (int)slots.size() && !waiting.empty(); ++i)
         if (!flights[i].busy) {
-          launch(i);
+          launch(i, lk);
           any_busy = any_busy || flights[i].busy;
         }
       if (stop && waiting.empty() && !any_busy) break;
@@ -268,6 +285,7 @@ hr_status hr_submit(hr_server* s, const hr_query* q, uint64_t* ticket) {
     s->cv_done.notify_all();
     return HR_OK;
   }
+  scene_hold(raw->item.plan.sc);
   s->waiting.push_back(raw);
   s->cv_work.notify_one();
   return HR_OK;
@@ -279,6 +297,9 @@ hr_status hr_wait(hr_server* s, uint64_t ticket, double* out, hr_query_stats* st
   auto it = s->tickets.find(ticket);
   if (it == s->tickets.end()) return fail(HR_EINVAL, "unknown or retired ticket");
   Ticket* t = it->second.get();
+  // one waiter per ticket: the waiter retires (frees) it when done
+  if (t->waited) return fail(HR_EBUSY, "another thread is already waiting on this ticket");
+  t->waited = true;
   s->cv_done.wait(lk, [&] { return t->state == 2; });
   if (out) memcpy(out, t->result.data(), t->result.size() * 8);
   if (stats) *stats = t->stats;

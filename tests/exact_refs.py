@@ -133,3 +133,84 @@ def corner_fr22_grad(theta, theta_star, W, H_, sigma):
     g0 = np.mean(sgn * stats.norm.pdf(a) / sigma * iny)
     g1 = np.mean(sgn * inx * stats.norm.pdf(b) / sigma)
     return np.array([g0, g1])
+
+
+# ------------------------------------------------- disks with radius parameters
+def disk_cover_prob_r(c, r, W, H_, sigma, nodes=64):
+    """Coverage probability of every pixel centre (row-major) by one disk whose
+    centre c and radius r are all perturbed by independent N(0, sigma^2)
+    offsets: pixel p is covered iff r - t > 0 and |c - x_p - tau| < r - t, so
+        q_p = int phi_sigma(t) ncx2.cdf(((r - t)_+)^2 / sigma^2, 2, |c - x_p|^2 / sigma^2) dt
+    (the radius offset t is independent of the centre offset tau).  The t
+    integral runs over [-9 sigma, min(r, 9 sigma)] by Gauss-Legendre (above r
+    the radius is not positive and nothing is covered)."""
+    xs = (np.arange(W) + 0.5) / W
+    ys = (np.arange(H_) + 0.5) / H_
+    X, Y = np.meshgrid(xs, ys)
+    lam = (((c[0] - X) ** 2 + (c[1] - Y) ** 2) / sigma**2).ravel()
+    lo, hi = -9.0 * sigma, min(r, 9.0 * sigma)
+    if hi <= lo:
+        return np.zeros(lam.size)
+    z, wz = np.polynomial.legendre.leggauss(nodes)
+    t = lo + (hi - lo) * (z + 1) / 2
+    wt = wz * (hi - lo) / 2 * np.exp(-t * t / (2 * sigma**2)) / (sigma * math.sqrt(2 * math.pi))
+    cdf = stats.ncx2.cdf(((r - t) ** 2 / sigma**2)[None, :], 2, lam[:, None])
+    return cdf @ wt
+
+
+def disks_smoothed_loss(q, colors, target):
+    """Exact smoothed MSE of a disk scene in painter's order from per-disk
+    coverage probabilities q[k] (P x 1 each) of independently perturbed disks:
+    disk k is the top one with probability q_k prod_{j > k} (1 - q_j) and no
+    disk covers with probability prod_j (1 - q_j); then
+        F = mean over pixels and channels of
+            sum_k P(top = k) (c_k - T)^2 + P(none) T^2."""
+    T = np.asarray(target, float).reshape(-1, colors.shape[1])
+    D = len(q)
+    acc = np.zeros(T.shape[0])
+    above = np.ones(T.shape[0])   # prod over disks above k of (1 - q_j)
+    for k in range(D - 1, -1, -1):
+        err = ((colors[k][None, :] - T) ** 2).sum(1)
+        acc += q[k] * above * err
+        above = above * (1.0 - q[k])
+    acc += above * (T * T).sum(1)
+    return acc.sum() / T.size
+
+
+def disks_exact_fd(theta, colors, target, W, H_, sigma, h):
+    """F, and g and H by central differences of the exact smoothed loss of a
+    scene of disks with (cx, cy, r) parameters (theta interleaved).  A change
+    of one disk's parameters changes only that disk's coverage probabilities,
+    so each difference recomputes one disk."""
+    theta = np.asarray(theta, float)
+    D = theta.size // 3
+    base = [disk_cover_prob_r(theta[3 * k:3 * k + 2], theta[3 * k + 2], W, H_, sigma)
+            for k in range(D)]
+    F0 = disks_smoothed_loss(base, colors, target)
+
+    def F_with(changes):
+        # changes: {disk: parameter triple}
+        q = list(base)
+        for k, p in changes.items():
+            q[k] = disk_cover_prob_r(p[:2], p[2], W, H_, sigma)
+        return disks_smoothed_loss(q, colors, target)
+
+    def shifted(delta):
+        ch = {}
+        for i, di in delta.items():
+            k = i // 3
+            p = ch.get(k, theta[3 * k:3 * k + 3].copy())
+            p = p.copy()
+            p[i % 3] += di
+            ch[k] = p
+        return F_with(ch)
+
+    n = theta.size
+    g = np.array([(shifted({i: h}) - shifted({i: -h})) / (2 * h) for i in range(n)])
+    Hm = np.zeros((n, n))
+    for i in range(n):
+        Hm[i, i] = (shifted({i: h}) - 2 * F0 + shifted({i: -h})) / (h * h)
+        for j in range(i + 1, n):
+            Hm[i, j] = Hm[j, i] = (shifted({i: h, j: h}) - shifted({i: h, j: -h})
+                                   - shifted({i: -h, j: h}) + shifted({i: -h, j: -h})) / (4 * h * h)
+    return F0, g, Hm

@@ -199,7 +199,9 @@ def test_autotuner_keeps_results(P, ctx, scenes):
     say("autotune ragged")
     got = b.run([q, dict(q, seed=10)])
     S, tile = P.tuned(ctx, sc)
-    assert S in (16, 32, 64) and tile in (1, 2, 3)
+    # the autotuner times S in {32, 64, 128, 256}; which one wins depends on
+    # the GPU's timing, the result bits must not
+    assert S in (32, 64, 128, 256) and tile in (1, 2, 3)
     assert np.array_equal(got[0], base)
 
 
@@ -312,3 +314,39 @@ def test_server_concurrent_clients(P, ctx, scenes):
     s = srv.stats()
     assert s["submitted"] == s["completed"]
     srv.close()
+
+
+def test_server_second_waiter_and_scene_destroy(P, ctx, scenes):
+    """One waiter per ticket: a second concurrent hr_wait on the same ticket
+    is refused (HR_EBUSY) or finds it retired (HR_EINVAL), never a freed
+    ticket.  A scene destroyed while the server still holds queries on it
+    waits for them; their results are those of the queries run alone."""
+    import ctypes as C
+    import threading
+    w, _ = scenes["ragged"]
+    sc = gpu_disks(ctx, w, disk_target(w))
+    srv = P.Server(ctx, slots=2, max_batch=4, memory_bytes=1 << 30)
+    t = srv.submit(sc, "grad", w.theta0, w.sigma, 20000, 31)
+    first = {}
+
+    def waiter():
+        first["out"], first["st"] = srv.wait(t)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    out = np.zeros(w.n)
+    st = P.QueryStats()
+    code = P.lib().hr_wait(srv.h, C.c_uint64(t), out.ctypes.data_as(C.c_void_p), C.byref(st))
+    th.join(timeout=60)
+    assert not th.is_alive()
+    assert code in (-5, -1), code
+    assert first["st"]["status"] == 0
+    say("server: scene destroyed with queries held")
+    ts = [srv.submit(sc, "grad", w.theta0, w.sigma, 4000, 40 + i) for i in range(6)]
+    sc.close()   # blocks until the server has finished the six queries
+    got = [srv.wait(x)[0] for x in ts]
+    srv.close()
+    ref_scene = gpu_disks(ctx, w, disk_target(w))
+    for i, g in enumerate(got):
+        assert np.array_equal(g, P.estimate("grad", ref_scene, w.theta0, w.sigma, 4000, 40 + i))
+    ref_scene.close()

@@ -3,8 +3,9 @@
 The direct-lighting term is checked against Lambert's closed-form irradiance
 from a uniformly emitting polygon; the scene removes every other light path
 (spheres parked far away and tiny, so bounce rays from the ground see only the
-black sky or the light, which ends the path).  The estimator on this scene is
-"parity unpinned" beyond the invariants checked here.
+black sky or the light, which ends the path).  Ray hits, shadows and the
+one-bounce indirect term are pinned in test_oracle_renderer.py; the estimator
+on path-traced scenes is checked here through its invariants.
 """
 import math
 
