@@ -50,7 +50,8 @@ class Opts(C.Structure):
     _fields_ = [("sampler", C.c_int), ("antithetic", C.c_int), ("hvp_rel_step", C.c_double),
                 ("accum_fp64", C.c_int), ("samples_per_block", C.c_int),
                 ("raster_tile", C.c_int), ("dbg_loss", C.POINTER(C.c_double)),
-                ("dbg_tau", C.POINTER(C.c_double)), ("hess_mix_n2", C.c_int)]
+                ("dbg_tau", C.POINTER(C.c_double)), ("hess_mix_n2", C.c_int),
+                ("hvp_per_render", C.c_int)]
 
 
 class NcgOpts(C.Structure):
@@ -176,7 +177,8 @@ def _p(a):
 
 
 def make_opts(sampler=AIS, antithetic=True, hvp_rel_step=0.1, accum_fp64=False,
-              samples_per_block=0, dbg=None, dbg_tau=None, raster_tile=0, hess_mix_n2=False):
+              samples_per_block=0, dbg=None, dbg_tau=None, raster_tile=0, hess_mix_n2=False,
+              hvp_per_render=False):
     o = Opts()
     lib().hr_opts_default(C.byref(o))
     o.sampler = sampler
@@ -186,6 +188,7 @@ def make_opts(sampler=AIS, antithetic=True, hvp_rel_step=0.1, accum_fp64=False,
     o.samples_per_block = samples_per_block
     o.raster_tile = raster_tile
     o.hess_mix_n2 = 1 if hess_mix_n2 else 0
+    o.hvp_per_render = 1 if hvp_per_render else 0
     o.dbg_loss = dbg.ctypes.data_as(C.POINTER(C.c_double)) if dbg is not None else None
     o.dbg_tau = dbg_tau.ctypes.data_as(C.POINTER(C.c_double)) if dbg_tau is not None else None
     return o
@@ -296,7 +299,9 @@ class Scene:
         h = C.c_void_p()
         _check(lib().hr_scene_disks(ctx.h, W, H, C_, D, ppd, None if rad is None else _p(rad),
                                     _p(colors), _p(target), C.byref(h)))
-        return Scene(ctx, h, D * ppd, (H, W, C_))
+        sc = Scene(ctx, h, D * ppd, (H, W, C_))
+        sc.n_disks = D
+        return sc
 
     @staticmethod
     def pt(ctx, W, H, spp, desc, target, nspheres=4):
@@ -340,19 +345,31 @@ def n_streams(kind, n, sampler=AIS):
     return K if (sampler in (IS, FR22) and kind != "hvp_limit") else 1
 
 
+def hvp_pairs(kind, scene, hvp_per_render=False):
+    """Whether an HVP on this scene renders its +-h scenes as pairs (a disk
+    scene of at most 64 disks, hvp_per_render off): then the per-render loss
+    output holds one loss difference f(+h) - f(-h) per (draw, sign)."""
+    return (kind == "hvp" and getattr(scene, "n_disks", 10 ** 9) <= 64 and not hvp_per_render)
+
+
 def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic=True,
              hvp_rel_step=0.1, accum_fp64=False, samples_per_block=0, return_losses=False,
-             return_draws=False, raster_tile=0, hess_mix_n2=False):
+             return_draws=False, raster_tile=0, hess_mix_n2=False, hvp_per_render=False):
     """kind in {'grad', 'hess', 'hvp', 'hvp_limit'} (host-pointer entry points).
-    With return_losses / return_draws the per-render losses and the draws are
-    returned as well (in that order).  hess_mix_n2: the aggregate Hessian
-    mixture over all n^2 ordered pairs."""
+    With return_losses / return_draws the per-render losses (for paired HVP
+    renders, see hvp_pairs: the loss differences) and the draws are returned
+    as well (in that order).  hess_mix_n2: the aggregate Hessian mixture over
+    all n^2 ordered pairs.  hvp_per_render: render and score each shifted
+    scene of an HVP separately."""
     n = scene.n
     th = np.ascontiguousarray(theta, dtype=np.float64)
-    dbg = np.zeros(n_renders(kind, n, N, sampler, antithetic)) if return_losses else None
+    nl = n_renders(kind, n, N, sampler, antithetic)
+    if hvp_pairs(kind, scene, hvp_per_render):
+        nl //= 2
+    dbg = np.zeros(nl) if return_losses else None
     taus = np.zeros(n_streams(kind, n, sampler) * N * n) if return_draws else None
     o = make_opts(sampler, antithetic, hvp_rel_step, accum_fp64, samples_per_block, dbg, taus,
-                  raster_tile, hess_mix_n2)
+                  raster_tile, hess_mix_n2, hvp_per_render)
     L = lib()
     if kind == "grad":
         out = np.zeros(n)
@@ -481,7 +498,7 @@ def out_shape(kind, n):
 
 
 _OPT_KEYS = ("sampler", "antithetic", "hvp_rel_step", "accum_fp64", "samples_per_block",
-             "raster_tile", "hess_mix_n2")
+             "raster_tile", "hess_mix_n2", "hvp_per_render")
 
 
 def _query(scene, kind, theta, sigma, N, seed, v=None, out=None, **opt):
@@ -494,7 +511,8 @@ def _query(scene, kind, theta, sigma, N, seed, v=None, out=None, **opt):
     o = make_opts(opt.get("sampler", AIS), opt.get("antithetic", True),
                   opt.get("hvp_rel_step", 0.1), opt.get("accum_fp64", False),
                   opt.get("samples_per_block", 0), raster_tile=opt.get("raster_tile", 0),
-                  hess_mix_n2=opt.get("hess_mix_n2", False))
+                  hess_mix_n2=opt.get("hess_mix_n2", False),
+                  hvp_per_render=opt.get("hvp_per_render", False))
     q = Query(scene.h, KIND[kind], float(sigma), int(N), int(seed), _p(th),
               None if vv is None else _p(vv), C.pointer(o), None if out is None else _p(out))
     return q, (th, vv, o, out)

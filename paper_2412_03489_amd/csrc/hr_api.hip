@@ -104,6 +104,8 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
   if (o.sampler < 0 || o.sampler > 3) return fail(HR_EINVAL, "unknown sampler");
   if (o.raster_tile < 0 || o.raster_tile > 3) return fail(HR_EINVAL, "raster_tile must be in [0, 3]");
   if (o.hess_mix_n2 != 0 && o.hess_mix_n2 != 1) return fail(HR_EINVAL, "hess_mix_n2 must be 0 or 1");
+  if (o.hvp_per_render != 0 && o.hvp_per_render != 1)
+    return fail(HR_EINVAL, "hvp_per_render must be 0 or 1");
   if ((what == kHvp || what == kHvpLimit) && !has_v) return fail(HR_EINVAL, "v is NULL");
   if (what == kHvpLimit && per_element(o.sampler))
     return fail(HR_EUNSUPPORTED, "the limit-kernel HVP supports the aggregate and Gaussian samplers");
@@ -126,6 +128,11 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
   e.A = o.antithetic ? 2 : 1;
   e.NH = what == kHvp ? 2 : 1;
   e.R = e.streams * N * (uint64_t)e.A * (uint64_t)e.NH;
+  // an HVP on a disk scene of at most 64 disks renders its +-h scenes as
+  // pairs and yields one loss difference per (draw, a)
+  e.pair = (what == kHvp && sc->kind == kDisks && sc->D <= raster_pair_max_disks() &&
+            !o.hvp_per_render) ? 1 : 0;
+  e.L = e.pair ? e.R / 2 : e.R;
   e.sigma = sigma;
   e.h = what == kHvp ? o.hvp_rel_step * sigma : 0.0;
   e.seed = seed;
@@ -139,9 +146,9 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
                                  : 0;
   p->b_tau = align256(e.streams * N * (uint64_t)e.n * 8);
   p->b_u = align256((size_t)e.n * 8 + 8);
-  p->b_rec = sc->kind == kDisks ? align256(e.R * (uint64_t)sc->D * 16) : 0;
-  p->b_part = p->stride ? align256(part_floats(e.R, (uint64_t)p->stride) * 4) : 0;
-  p->b_f = align256(e.R * 8);
+  p->b_rec = sc->kind == kDisks ? align256(e.L * (uint64_t)sc->D * 16) : 0;
+  p->b_part = p->stride ? align256(part_floats(e.L, (uint64_t)p->stride) * 4) : 0;
+  p->b_f = align256(e.L * 8);
   p->b_Fq = align256(e.streams * N * 8);
   p->b_vt = align256(N * 8);
   p->b_acc = align256(p->nchunks * (uint64_t)e.nout * 16);
@@ -196,11 +203,18 @@ void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBu
   const int spb = S;
   if (sc->kind == kDisks) {
     DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};
-    T("records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
     RasterExact ex{d_theta, tau, u, sc->radius, e.n, sc->ppd, e.A, e.NH, e.h};
-    T("raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, shape, ex, partial); });
+    if (e.pair) {
+      T("records", [&] { launch_pair_records(s, e, ds, d_theta, tau, u, rec); });
+      T("raster_dloss", [&] {
+        launch_raster_dloss(s, ds, rec, e.L, spb > 0 ? spb / 2 : 0, shape, ex, partial);
+      });
+    } else {
+      T("records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
+      T("raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, shape, ex, partial); });
+    }
     T("tile_reduce", [&] {
-      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
+      launch_tile_reduce(s, partial, e.L, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
     });
   } else if (sc->kind == kPT) {
     PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
@@ -259,7 +273,7 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
   double* tau = qb.tau;
   double* f = qb.f;
   HR_HIP(hipGetLastError());
-  if (h_dbg) HR_HIP(hipMemcpyAsync(h_dbg, f, e.R * 8, hipMemcpyDeviceToHost, s));
+  if (h_dbg) HR_HIP(hipMemcpyAsync(h_dbg, f, e.L * 8, hipMemcpyDeviceToHost, s));
   if (h_tau) HR_HIP(hipMemcpyAsync(h_tau, tau, e.streams * N * (uint64_t)e.n * 8, hipMemcpyDeviceToHost, s));
   if (h_dbg || h_tau) HR_HIP(hipStreamSynchronize(s));
   return HR_OK;
@@ -326,6 +340,7 @@ void hr_opts_default(hr_opts* o) {
   o->dbg_loss = nullptr;
   o->dbg_tau = nullptr;
   o->hess_mix_n2 = 0;
+  o->hvp_per_render = 0;
 }
 
 void hr_ncg_opts_default(hr_ncg_opts* o) {

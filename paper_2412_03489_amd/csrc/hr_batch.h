@@ -65,7 +65,7 @@ struct BatchSlot {
   // copies each item's result from the pinned mirror to its destination
   void scatter(const std::vector<BatchItem>& items) const;
   void launches(hipStream_t st, bool time_phases);
-  // render classes with work: raster classes in bits 0-7, path-traced in 8-10
+  // render classes with work: raster classes in bits 0-11, path-traced in 16-18
   unsigned classes() const;
 };
 

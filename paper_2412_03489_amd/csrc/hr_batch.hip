@@ -162,7 +162,13 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
     if (sc->kind == kDisks) {
       raster_config(ctx, sc, p.o, p.e.R, &qS[q], &qshape[q]);
       cost[q] = (double)qS[q] * (double)(sc->D + 16);
-      lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
+      if (p.e.pair) {
+        // pairs per block: half the renders, whole flush groups of 16
+        qS[q] = std::max(16, (qS[q] / 2 / 16) * 16);
+        lds = std::max(lds, raster_pair_lds_bytes(sc->D));
+      } else {
+        lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
+      }
     } else if (sc->kind == kPT) {
       qS[q] = p.o.samples_per_block > 0 && p.o.samples_per_block <= pt_max_samples()
                   ? p.o.samples_per_block : kDefaultPtSamples;
@@ -196,8 +202,8 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       a = RasterQuery{};
       a.W = sc->W; a.H = sc->H; a.C = sc->C; a.D = sc->D; a.S = qS[q];
       raster_geometry(a, qshape[q]);
-      const int cls = raster_class(sc->C, sc->D);
-      add_segments(rq[cls], rchunks[cls], q, (p.e.R + qS[q] - 1) / qS[q], a.tiles);
+      const int cls = p.e.pair ? raster_pair_class(sc->C) : raster_class(sc->C, sc->D);
+      add_segments(rq[cls], rchunks[cls], q, (p.e.L + qS[q] - 1) / qS[q], a.tiles);
     } else if (sc->kind == kPT) {
       const uint64_t draws = p.e.streams * p.e.N;
       const int nr = p.e.A * p.e.NH;
@@ -313,7 +319,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       a.target = sc->target;
       a.colors = sc->colors;
       a.partial = qb.partial;
-      a.R = p.e.R;
+      a.R = p.e.L;
       a.r_base = 0;
       a.ex = RasterExact{b.theta, qb.tau, qb.u, sc->radius, n, sc->ppd, p.e.A, p.e.NH, p.e.h};
       b.rq = a;
@@ -334,7 +340,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
     single_theta_ = HQ[0].theta;
     single_v_ = HQ[0].v;
     single_out_ = HQ[0].out;
-    single_S_ = qS[0];
+    single_S_ = single_plan_.e.pair ? 2 * qS[0] : qS[0];   // renders per block
     single_shape_ = qshape[0];
   }
   uint64_t* ho = (uint64_t*)(H + o_off);
@@ -382,7 +388,7 @@ void BatchSlot::launches(hipStream_t st, bool time_phases) {
   });
   run("batch_pt", [&] {
     for (int c = 0; c < 3; ++c)
-      if (cl & (1u << (8 + c))) launch_batch_pt(st, T, 1 << c, pt_blocks[c]);
+      if (cl & (1u << (16 + c))) launch_batch_pt(st, T, 1 << c, pt_blocks[c]);
   });
   run("batch_reduce", [&] { launch_batch_reduce(st, T, phase_blocks); });
   run("batch_prep", [&] { launch_batch_prep(st, T, phase_blocks); });
@@ -395,7 +401,7 @@ unsigned BatchSlot::classes() const {
   for (int c = 0; c < kRasterClasses; ++c)
     if (raster_class_items[c]) m |= 1u << c;
   for (int c = 0; c < 3; ++c)
-    if (pt_class_items[c]) m |= 1u << (8 + c);
+    if (pt_class_items[c]) m |= 1u << (16 + c);
   return m;
 }
 

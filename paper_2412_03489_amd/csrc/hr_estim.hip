@@ -195,7 +195,13 @@ __device__ __forceinline__ void prep_one(const EstShape& e, const double* __rest
   {
     const uint64_t r0 = sidx * (uint64_t)(e.A * e.NH);
     double F0, F1 = 0.0;
-    if (e.what == kHvp) {
+    if (e.what == kHvp && e.pair) {
+      // the loss differences f(+h) - f(-h) of the draw's pairs
+      const double vn = *vnorm;
+      const uint64_t p0 = sidx * (uint64_t)e.A;
+      F0 = vn * f[p0] / (2.0 * e.h);
+      if (e.A == 2) F1 = vn * f[p0 + 1] / (2.0 * e.h);
+    } else if (e.what == kHvp) {
       const double vn = *vnorm;
       F0 = vn * (f[r0 + 0] - f[r0 + 1]) / (2.0 * e.h);
       if (e.A == 2) F1 = vn * (f[r0 + 2] - f[r0 + 3]) / (2.0 * e.h);
@@ -610,11 +616,11 @@ uint64_t batch_tasks(const BatchQuery& q, int phase) {
       return ((e.what == kHvp || e.what == kHvpLimit) ? 1 : 0) +
              ceil_div(e.streams * e.N * (uint64_t)e.n, kBatchElems);
     case kPhRecords:
-      return q.scene == kDisks ? ceil_div(e.R * (uint64_t)q.ds.D, kBatchElems) : 0;
+      return q.scene == kDisks ? ceil_div(e.L * (uint64_t)q.ds.D, kBatchElems) : 0;
     case kPhAnalytic:
       return render ? 0 : ceil_div(e.R, kBatchHeavyElems);
     case kPhReduce:
-      return render ? ceil_div(e.R, kBatchRenders) : 0;
+      return render ? ceil_div(e.L, kBatchRenders) : 0;
     case kPhPrep:
       return ceil_div(e.streams * e.N, kBatchHeavyElems);
     case kPhAccum:

@@ -24,6 +24,10 @@ struct EstShape {
   uint64_t N, streams;               // streams = K for per-element IS, else 1
   int A, NH;                         // antithetic factor, shifts per render group
   uint64_t R;                        // renders = streams * N * A * NH
+  int pair;                          // 1: an HVP on a disk scene whose +-h renders come as
+                                     //    pairs, one loss difference per (draw, a)
+  int pad_;
+  uint64_t L;                        // loss outputs: R / 2 pairs (pair), else R
   double sigma, h;                   // h: HVP step (0 if none)
   uint64_t seed;
 };
@@ -94,6 +98,15 @@ int raster_auto_samples(int W, int H, uint64_t R, int shape);
 void raster_geometry(RasterQuery& a, int shape);
 void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
                     const double* tau, const double* u, float4* rec);
+// HVP render pairs (e.pair): records of the midpoint disks (e.L x D) and the
+// loss difference f(+h) - f(-h) per pair as wave-tile partials
+void launch_pair_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
+                         const double* tau, const double* u, float4* rec);
+void launch_raster_dloss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t P,
+                         int pairs_per_block, int shape, const RasterExact& ex, float* partial);
+size_t raster_pair_lds_bytes(int D);
+// largest disk count of the pair path (more disks render the HVP per render)
+int raster_pair_max_disks();
 // number of 16x16 wave tiles of the image: the partial stride per render
 int raster_subtiles(int W, int H);
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
@@ -190,8 +203,10 @@ enum BatchPhase { kPhSample = 0, kPhRecords, kPhAnalytic, kPhReduce, kPhPrep, kP
 // Raster items are queued by class -- channel count and whether all disks
 // fit one wavefront -- and each class has its own persistent kernel, which
 // holds only that variant's registers.
-constexpr int kRasterClasses = 8;
+constexpr int kRasterClasses = 12;
 __host__ __device__ inline int raster_class(int C, int D) { return (C - 1) * 2 + (D > 64 ? 1 : 0); }
+// HVP render pairs (at most 64 disks) by channel count
+__host__ __device__ inline int raster_pair_class(int C) { return 8 + (C - 1); }
 constexpr int kWorkCounters = 8 * (kRasterClasses + 3);   // 8 per queue set
 
 struct BatchTable {

@@ -59,9 +59,9 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchTable* __restri
     const int q = batch_find(off, nq, t);
     const BatchQuery& Q = T->q[q];
     const uint64_t b = (t - off[q]) * (uint64_t)kBatchRenders;
-    const uint64_t end = umin64(Q.e.R, b + kBatchRenders);
+    const uint64_t end = umin64(Q.e.L, b + kBatchRenders);
     for (uint64_t g = b / 16 + (threadIdx.x >> 6); g * 16 < end; g += (blockDim.x >> 6))
-      reduce_group(Q.partial, Q.part_stride, Q.inv_count, g, Q.e.R, Q.f);
+      reduce_group(Q.partial, Q.part_stride, Q.inv_count, g, Q.e.L, Q.f);
   }
 }
 

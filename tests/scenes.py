@@ -51,3 +51,21 @@ def small_disks(W=50, H=37, D=70, C=3, seed=21):
     return WL.DiskWorkload(name="ragged", W=W, H=H, C=C, ppd=3, colors=col, radius=None,
                            theta_star=ts.astype(np.float64), theta0=t0, sigma=0.02, N=96,
                            seed=17, v=g.standard_normal(D * 3))
+
+
+def assert_losses_match(lgot, lref, tol=1e-6):
+    """The library's per-render losses against the oracle's (same draws).
+    Paired HVP renders (half as many outputs, see hvp_pairs) hold the loss
+    differences f(+h) - f(-h): they are held to 1e-5 of the largest oracle
+    difference (plus 1e-12 of the loss scale), the others to `tol` of the
+    largest loss."""
+    lgot = np.asarray(lgot, float)
+    lref = np.asarray(lref, float)
+    if lgot.size * 2 == lref.size:
+        dref = lref[0::2] - lref[1::2]
+        bound = 1e-5 * np.abs(dref).max() + 1e-12 * np.abs(lref).max()
+        err = np.abs(lgot - dref).max()
+        assert err <= bound, (err, bound)
+    else:
+        assert lgot.size == lref.size
+        assert np.abs(lgot - lref).max() <= tol * max(np.abs(lref).max(), 1e-30)

@@ -95,6 +95,15 @@ def mixed_queries(scenes):
         dict(scene=sp, kind="hvp_limit", theta=wp.theta0, sigma=wp.sigma, N=16, seed=14, v=vp,
              hess_mix_n2=True),
         dict(scene=s2, kind="grad", theta=w2.theta0, sigma=0.02, N=150, seed=15),
+        # HVPs rendered as +-h pairs (at most 64 disks), one per channel count
+        dict(scene=s4, kind="hvp", theta=w4.theta0, sigma=0.03, N=77, seed=16,
+             v=w4.v / np.linalg.norm(w4.v)),
+        dict(scene=s2, kind="hvp", theta=w2.theta0, sigma=0.02, N=40, seed=17, v=w2.v,
+             accum_fp64=True),
+        dict(scene=s1, kind="hvp", theta=w1.theta0, sigma=w1.sigma, N=333, seed=18,
+             v=np.array([0.6, -0.8])),
+        dict(scene=s4, kind="hvp", theta=w4.theta0, sigma=0.03, N=20, seed=19, v=w4.v,
+             hvp_per_render=True),
     ]
 
 

@@ -14,7 +14,8 @@ import pytest
 
 import oracle as O
 import workloads as WL
-from scenes import (disk_target, gpu_disks, oracle_disks, pt_target, rel_inf, small_disks)
+from scenes import (assert_losses_match, disk_target, gpu_disks, oracle_disks, pt_target, rel_inf,
+                    small_disks)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -151,8 +152,14 @@ def test_disks32_parity_reduced_n(P, disks32, kind):
     say(f"disks32 {kind} N={N}")
     ref, lref = O.estimate(kind, osc, w.theta0, w.sigma, N, w.seed, v=w.v, return_losses=True)
     got, lgot = P.estimate(kind, gsc, w.theta0, w.sigma, N, w.seed, v=w.v, return_losses=True)
-    assert np.abs(lgot - lref).max() <= 1e-6 * np.abs(lref).max()
+    assert_losses_match(lgot, lref)
     assert rel_inf(got, ref) < TOL
+    if kind == "hvp":
+        # the same HVP with every shifted scene rendered and scored separately
+        sep, lsep = P.estimate(kind, gsc, w.theta0, w.sigma, N, w.seed, v=w.v,
+                               return_losses=True, hvp_per_render=True)
+        assert_losses_match(lsep, lref)
+        assert rel_inf(sep, ref) < TOL
 
 
 def test_disks32_full_size_sampled_renders(P, disks32):
@@ -163,18 +170,19 @@ def test_disks32_full_size_sampled_renders(P, disks32):
     say(f"disks32 full N={w.N}")
     est, lgot = P.estimate("hvp", gsc, w.theta0, w.sigma, w.N, w.seed, v=w.v, return_losses=True)
     assert np.isfinite(est).all()
+    # paired renders: one loss difference f(+h) - f(-h) per (draw, sign)
+    assert lgot.size == 2 * w.N
     h = 0.1 * w.sigma
     u = w.v / np.linalg.norm(w.v)
     rng = np.random.default_rng(0)
     idx = np.concatenate([[0, 1, 2, 3, lgot.size - 1], rng.integers(0, lgot.size, 40)])
-    for r in idx:
-        sh, rem = r % 2, r // 2
-        ai, s = rem % 2, rem // 2
+    for p in idx:
+        ai, s = p % 2, p // 2
         tau, _ = O.draw_tau(0, w.n, w.sigma, w.seed, int(s), O.AIS)
         a = 1.0 if ai == 0 else -1.0
-        base = w.theta0 + (h if sh == 0 else -h) * u
-        f = O.loss(osc, base - a * tau)
-        assert abs(lgot[r] - f) <= 1e-6 * f, (r, lgot[r], f)
+        fp = O.loss(osc, (w.theta0 + h * u) - a * tau)
+        fm = O.loss(osc, (w.theta0 + (-h) * u) - a * tau)
+        assert abs(lgot[p] - (fp - fm)) <= 1e-5 * abs(fp - fm) + 1e-12 * fp, (p, lgot[p], fp - fm)
     _, lshort = P.estimate("hvp", gsc, w.theta0, w.sigma, 64, w.seed, v=w.v, return_losses=True)
     assert np.array_equal(lshort, lgot[: lshort.size])
 
@@ -193,7 +201,7 @@ def test_ragged_scene_parity(P, ctx):
                                    return_losses=True)
             got, lgot = P.estimate(kind, gsc, w.theta0, w.sigma, N, w.seed, v=w.v,
                                    return_losses=True)
-            assert np.abs(lgot - lref).max() <= 1e-6 * np.abs(lref).max()
+            assert_losses_match(lgot, lref)
             assert rel_inf(got, ref) < TOL
 
 
