@@ -48,13 +48,12 @@ PT_FLOP_PER_PATH = 434.0
 # 9 FLOP for the 3-channel squared error, 5 FLOP per disk test times the
 # 0.593 disks whose bounding box holds an average pixel (32 disks, E[r^2]).
 FLOP_PER_PIXEL = 12.0
-# HBM bytes per k_raster_loss launch (mean over a step's launches) from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy
-# (profiles/raster_loss_disks32_traffic.md), valid for the kernel source with
-# this code digest (code_digest: comments and blank lines left out); reported
-# as null once the code has changed.
-TRAFFIC_BYTES_PER_LAUNCH = 448712664
-TRAFFIC_SOURCE_DIGEST = "ba57068a32b5120e10a9182d6bd231d55a69d65793b3fd7ae4c9c0652832a36f"
+# HBM bytes per k_raster_dloss launch (an HVP's render pairs) from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy, valid for the kernel
+# source with this code digest (code_digest: comments and blank lines left
+# out); reported as null once the code has changed (or before it is measured).
+TRAFFIC_BYTES_PER_LAUNCH = None
+TRAFFIC_SOURCE_DIGEST = ""
 
 
 def code_digest(path):
@@ -75,6 +74,29 @@ def raster_traffic():
     return TRAFFIC_BYTES_PER_LAUNCH if code_digest(src) == TRAFFIC_SOURCE_DIGEST else None
 
 
+def golden(name):
+    """Expected values written by tests/golden/make_golden.py with the CPU FP64
+    oracle alone (None if the file is absent)."""
+    path = os.path.join(ROOT, "tests", "golden", f"full_{name}.npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "affinity": avail, "model": model}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -89,23 +111,44 @@ def render_target_on_gpu(P, ctx, w):
     return tgt
 
 
-def cpu_baseline(w, draws):
-    """The oracle, untuned, on the first `draws` draws of the same HVP query."""
+def cpu_baseline(w, draws, single_draws, reps, gpu_hvp):
+    """The oracle, untuned, on the first `draws` draws of the same HVP query:
+    the median of `reps` runs on the host threads a GPU's share allows, one
+    run on a single thread (first `single_draws` draws), and the GPU's result
+    on the same draws against it."""
     import oracle as O
     O.build(force=False)
     blank = np.zeros((w.H, w.W, w.C), np.float32)
     sc0 = O.Scene.disks(w.W, w.H, w.C, w.colors, blank, radius=w.radius, ppd=w.ppd)
     tgt = O.render(sc0, w.theta_star, w.H, w.W, w.C).astype(np.float32)
     osc = O.Scene.disks(w.W, w.H, w.C, w.colors, tgt, radius=w.radius, ppd=w.ppd)
-    cores = min(os.cpu_count() or 1, 16)
+    info = cpu_info()
+    # one GPU's share of a box's host is 16 threads (the worker-pool size the
+    # boxes set); the oracle uses all of them when the host has that many
+    share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    cores = max(1, min(info["affinity"], share))
+    times = []
+    ref = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ref = O.estimate("hvp", osc, w.theta0, w.sigma, draws, w.seed, v=w.v, nthreads=cores)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     t0 = time.perf_counter()
-    O.estimate("hvp", osc, w.theta0, w.sigma, draws, w.seed, v=w.v, nthreads=cores)
-    dt = time.perf_counter() - t0
+    O.estimate("hvp", osc, w.theta0, w.sigma, single_draws, w.seed, v=w.v, nthreads=1)
+    dt1 = time.perf_counter() - t0
     renders = 4 * draws
-    return {"value": renders * w.pixels / dt / 1e6, "unit": "Mpix/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"one AIS HVP query of the same workload at N={draws} draws "
-                      f"({renders} renders of 256x256x3), {dt:.2f} s wall"}
+    out = {"value": renders * w.pixels / dt / 1e6, "unit": "Mpix/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"one AIS HVP query of the same workload at N={draws} draws "
+                     f"({renders} renders of 256x256x3), median of {reps} runs "
+                     f"({', '.join(f'{t:.2f}' for t in times)} s)",
+           "single_core_Mpix_per_s": 4 * single_draws * w.pixels / dt1 / 1e6,
+           "single_core_sample": f"N={single_draws} draws on 1 thread, {dt1:.2f} s",
+           "host": info}
+    if gpu_hvp is not None:
+        out["gpu_vs_oracle_rel_inf"] = rel_inf(gpu_hvp, ref)
+    return out
 
 
 def rel_inf(x, ref):
@@ -300,10 +343,15 @@ def main_section(P, ctx, args):
         renders += 2 * w.N + rep["iters_done"] * 4 * w.N
     ctx.synchronize()
     dt = time.perf_counter() - t0
-    launches, raster_ms = ctx.kernel_stats("raster_loss")
+    # the HVPs' render pairs (k_raster_dloss) and the gradient's renders
+    # (k_raster_loss), each timed by HIP events on the launch stream
+    launches, raster_ms = ctx.kernel_stats("raster_dloss")
+    g_launches, g_raster_ms = ctx.kernel_stats("raster_loss")
     red_launches, red_ms = ctx.kernel_stats("tile_reduce")
     ctx.enable_timing(False)
-    log(f"bench: {args.steps} steps in {dt:.3f} s, raster launches {launches}")
+    log(f"bench: {args.steps} steps in {dt:.3f} s, pair raster launches {launches}, "
+        f"gradient raster launches {g_launches}")
+    theta_step = th.download(w.n)
 
     # single-HVP query latency (host wall clock, call to completion)
     lat = []
@@ -322,16 +370,33 @@ def main_section(P, ctx, args):
         dst.free()
         log(f"bench: calibration copy of {nb} bytes done")
 
+    # the error of the benchmarked results against FP64: the timed step, a
+    # full-size HVP and gradient, against the oracle's expected values
+    errors = {}
+    ref = golden("disks32_newton")
+    if ref is not None:
+        errors["newton_step_rel_inf"] = rel_inf(theta_step - w.theta0, ref["theta"] - w.theta0)
+    ref = golden("disks32_hvp")
+    if ref is not None:
+        errors["hvp_rel_inf"] = rel_inf(P.estimate("hvp", sc, w.theta0, w.sigma, w.N, w.seed,
+                                                   v=ref["v"]), ref["out"])
+    ref = golden("disks32_grad")
+    if ref is not None:
+        errors["gradient_rel_inf"] = rel_inf(P.estimate("grad", sc, w.theta0, w.sigma, w.N,
+                                                        w.seed), ref["out"])
+    gpu_hvp_sample = P.estimate("hvp", sc, w.theta0, w.sigma, args.cpu_draws, w.seed, v=w.v)
+
     pix_total = renders * w.pixels
     value = pix_total / dt / 1e6
-    # dominant kernel: raster + MSE; one launch per estimator call, HVP launches
-    # carry 4N renders, the gradient's 2N
+    # dominant kernel: the HVPs' render pairs (4N renders per launch); the
+    # gradient's launch (2N renders) is reported beside it
     steps = args.steps
     hvps = (renders - 2 * w.N * steps) // (4 * w.N)
-    raster_pix = renders * w.pixels
     avg_ms = raster_ms / max(launches, 1)
-    flop_per_launch = FLOP_PER_PIXEL * raster_pix / max(launches, 1)
+    flop_per_launch = FLOP_PER_PIXEL * 4 * w.N * w.pixels
     achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12
+    g_avg_ms = g_raster_ms / max(g_launches, 1)
+    g_achieved = FLOP_PER_PIXEL * 2 * w.N * w.pixels / (g_avg_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -356,15 +421,24 @@ def main_section(P, ctx, args):
                            "queries": int(args.hvp_queries)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": raster_traffic(), "kernel": "k_raster_loss",
+                     "traffic": raster_traffic(), "kernel": "k_raster_dloss",
                      "avg_launch_ms": round(avg_ms, 4), "launches": int(launches),
-                     "flop_per_pixel": FLOP_PER_PIXEL},
+                     "flop_per_pixel": FLOP_PER_PIXEL,
+                     "renders_per_launch": 4 * w.N},
+        "roofline_gradient": {"bound": "alu", "kernel": "k_raster_loss",
+                              "achieved": round(g_achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(g_achieved / PEAK_FP32_TFLOPS, 4),
+                              "avg_launch_ms": round(g_avg_ms, 4), "launches": int(g_launches),
+                              "renders_per_launch": 2 * w.N},
+        "error_vs_fp64": errors,
         "cpu_baseline": None,
     }
-    # the loss pass: per render, its wave-tile partials are read (4 B each)
-    # and one FP64 loss written -- HBM-bound, against the 8 TB/s peak
+    # the loss pass: per loss output -- a render of the gradient, a render
+    # pair of an HVP -- its wave-tile partials are read (4 B each) and one
+    # FP64 value written; HBM-bound, against the 8 TB/s peak
     subs = ((w.W + 15) // 16) * ((w.H + 15) // 16)
-    red_bytes = renders * (subs * 4 + 8)
+    outputs = 2 * w.N * steps + hvps * 2 * w.N
+    red_bytes = outputs * (subs * 4 + 8)
     red_gbs = red_bytes / (red_ms * 1e-3) / 1e9 if red_ms > 0 else None
     line["loss_pass"] = {"bound": "hbm", "kernel": "k_tile_reduce",
                          "achieved": round(red_gbs, 1) if red_gbs else None,
@@ -372,11 +446,12 @@ def main_section(P, ctx, args):
                          "frac": round(red_gbs / PEAK_HBM_GBS, 4) if red_gbs else None,
                          "avg_launch_ms": round(red_ms / max(red_launches, 1), 4),
                          "launches": int(red_launches),
-                         "bytes_per_render": subs * 4 + 8}
+                         "bytes_per_output": subs * 4 + 8,
+                         "outputs": int(outputs)}
     for b in (th0, th, v, out):
         b.free()
     sc.close()
-    return line
+    return line, gpu_hvp_sample
 
 
 def configs_section(P, ctx, reps):
@@ -495,7 +570,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--hvp-queries", type=int, default=30)
-    ap.add_argument("--cpu-draws", type=int, default=24576)
+    ap.add_argument("--cpu-draws", type=int, default=4096,
+                    help="draws of the oracle's timed HVP (median of --cpu-reps runs)")
+    ap.add_argument("--cpu-reps", type=int, default=5)
+    ap.add_argument("--cpu-single-draws", type=int, default=256,
+                    help="draws of the oracle's single-thread run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--samples-per-block", type=int, default=0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -530,8 +609,9 @@ def main():
     if args.no_serving:
         sections.discard("serving")
     ctx = P.Context(0)
+    gpu_hvp_sample = None
     if "main" in sections:
-        line = main_section(P, ctx, args)
+        line, gpu_hvp_sample = main_section(P, ctx, args)
     else:   # a diagnostic run of the other sections only (for profiling)
         line = {"metric": METRIC, "value": None, "unit": "Mpix/s", "n_gpus": 1,
                 "note": "headline section skipped (--sections)"}
@@ -546,7 +626,8 @@ def main():
     ctx.close()
     if not args.no_cpu and "main" in sections:
         log(f"bench: CPU oracle baseline at N={args.cpu_draws}")
-        line["cpu_baseline"] = cpu_baseline(WL.disks32(), args.cpu_draws)
+        line["cpu_baseline"] = cpu_baseline(WL.disks32(), args.cpu_draws, args.cpu_single_draws,
+                                            args.cpu_reps, gpu_hvp_sample)
     print(json.dumps(line), flush=True)
 
 
