@@ -251,6 +251,20 @@ hr_status hr_est_hessian_dev(hr_scene* sc, const double* d_theta, double sigma, 
 hr_status hr_est_hvp_dev(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
                          uint64_t seed, const double* d_v, const hr_opts* opts, double* d_Hv);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * HVP as hr_est_hvp_dev -- same kernels, same result bits -- with its
+ * workspace in a fixed array of 64 MiB that every GPU the library runs on
+ * holds from context creation until the process ends; the call makes no
+ * allocation.  The caller passes inputs and output as for hr_est_hvp_dev.
+ * Requests whose workspace exceeds 64 MiB (on the 256x256 RGB, 32-disk
+ * scene: about 16k draws) return HR_ENOMEM.  Every call on one GPU uses the
+ * same array: calls that overlap on one GPU (other streams, other contexts
+ * of the device) race and must be ordered by the caller. */
+hr_status hr_est_hvp_dev_noalloc(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                                 uint64_t seed, const double* d_v, const hr_opts* opts,
+                                 double* d_Hv);
+
 /* ---- Newton-CG step (section "Previous Work") ---------------------------- */
 typedef struct {
   int cg_iters;          /* maximum inner CG iterations (default 10)                 */

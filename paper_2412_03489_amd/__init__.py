@@ -30,6 +30,7 @@ EXPORTED = (
     "hr_scene_disks", "hr_scene_pt", "hr_scene_quad", "hr_scene_neggauss", "hr_scene_destroy",
     "hr_scene_nparams", "hr_render", "hr_est_grad", "hr_est_hessian", "hr_est_hvp",
     "hr_est_hvp_limit", "hr_est_grad_dev", "hr_est_hessian_dev", "hr_est_hvp_dev",
+    "hr_est_hvp_dev_noalloc",
     "hr_newton_cg_step", "hr_newton_cg_step_dev", "hr_dev_alloc", "hr_dev_free", "hr_memcpy",
     "hr_est_grad_greybox", "hr_est_hessian_greybox", "hr_est_hvp_greybox",
     "hr_est_loss", "hr_optim_opts_default", "hr_optimize",
@@ -139,7 +140,7 @@ def lib():
     L.hr_render.argtypes = [vp, vp, u64, u32, i, vp]
     for nm in ("hr_est_grad", "hr_est_hessian", "hr_est_grad_dev", "hr_est_hessian_dev"):
         getattr(L, nm).argtypes = [vp, vp, d, u64, u64, C.POINTER(Opts), vp]
-    for nm in ("hr_est_hvp", "hr_est_hvp_limit", "hr_est_hvp_dev"):
+    for nm in ("hr_est_hvp", "hr_est_hvp_limit", "hr_est_hvp_dev", "hr_est_hvp_dev_noalloc"):
         getattr(L, nm).argtypes = [vp, vp, d, u64, u64, vp, C.POINTER(Opts), vp]
     for nm in ("hr_newton_cg_step", "hr_newton_cg_step_dev"):
         getattr(L, nm).argtypes = [vp, vp, d, u64, u64, C.POINTER(NcgOpts), C.POINTER(Opts),

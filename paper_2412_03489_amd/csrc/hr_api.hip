@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,42 @@
 
 using namespace hr;
 using namespace hr::rt;
+
+// Fixed workspace of hr_est_hvp_dev_noalloc, for callers that cannot allocate
+// (graph capture, tight serving loops).  Every GPU the library runs on holds
+// its own copy until the process ends; host code reaches a device's copy only
+// through the address hipGetSymbolAddress returns for it (g_scratch below),
+// never through the array's name.
+constexpr size_t kNoallocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Resolves the current device's copy of `scratch` once (at context creation).
+hr_status scratch_resolve(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(HR_EDEVICE, "device index beyond the fixed-workspace table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return HR_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    return fail(HR_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch[device] = ptr;
+  return HR_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
+}  // namespace
 
 namespace hr {
 namespace rt {
@@ -361,6 +398,9 @@ hr_status hr_ctx_create(int device, hr_ctx** out) {
   HR_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(HR_EINVAL, "no such device");
   HR_HIP(hipSetDevice(device));
+  // this device's copy of the fixed workspace (hr_est_hvp_dev_noalloc)
+  hr_status sst = scratch_resolve(device);
+  if (sst) return sst;
   hr_ctx* c = new hr_ctx();
   c->device = device;
   hipError_t e = hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking);
@@ -668,6 +708,33 @@ hr_status hr_est_hvp_dev(hr_scene* sc, const double* d_theta, double sigma, uint
   o.dbg_loss = nullptr;
   o.dbg_tau = nullptr;
   return run_est(sc, kHvp, d_theta, sigma, N, seed, d_v, o, d_Hv, nullptr, nullptr);
+}
+
+hr_status hr_est_hvp_dev_noalloc(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
+                                 uint64_t seed, const double* d_v, const hr_opts* opts,
+                                 double* d_Hv) {
+  if (!sc || !d_theta || !d_v || !d_Hv) return fail(HR_EINVAL, "NULL argument");
+  hr_opts o = resolve(opts);
+  o.dbg_loss = nullptr;
+  o.dbg_tau = nullptr;
+  QueryPlan pl;
+  hr_status st = plan_query(sc, kHvp, sigma, N, seed, true, o, &pl);
+  if (st) return st;
+  if (pl.total > kNoallocScratchBytes)
+    return fail(HR_ENOMEM, "request needs " + std::to_string(pl.total) +
+                               " bytes of workspace; the fixed workspace of this entry point holds " +
+                               std::to_string(kNoallocScratchBytes));
+  hr_ctx* ctx = sc->ctx;
+  void* ws = scratch_of(ctx->device);
+  if (!ws) return fail(HR_EDEVICE, "the fixed workspace is not resolved on this device");
+  HR_HIP(hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below report this call's errors only
+  // every buffer of the query is written before it is read: nothing in the
+  // workspace has to start at zero
+  launch_query(ctx, ctx->stream, pl, carve(pl, ws), d_theta, d_v, d_Hv, o.samples_per_block,
+               o.raster_tile, false);
+  HR_HIP(hipGetLastError());
+  return HR_OK;
 }
 
 hr_status hr_est_loss(hr_scene* sc, const double* theta, double sigma, uint64_t N, uint64_t seed,
