@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -24,6 +25,11 @@ using namespace hr::rt;
 // never through the array's name.
 constexpr size_t kNoallocScratchBytes = 64ull << 20;
 static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+uint64_t next_scene_uid() {
+  static std::atomic<uint64_t> counter{1};
+  return counter.fetch_add(1);
+}
 
 namespace {
 constexpr int kMaxDevices = 64;
@@ -244,20 +250,23 @@ void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBu
     if (e.pair) {
       T("records", [&] { launch_pair_records(s, e, ds, d_theta, tau, u, rec); });
       T("raster_dloss", [&] {
-        launch_raster_dloss(s, ds, rec, e.L, spb > 0 ? spb / 2 : 0, shape, ex, partial);
+        launch_raster_dloss(s, ds, rec, e.L, spb > 0 ? spb / 2 : 0, shape, ex, partial, e.skip);
       });
     } else {
       T("records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
-      T("raster_loss", [&] { launch_raster_loss(s, ds, rec, e.R, spb, shape, ex, partial); });
+      T("raster_loss", [&] {
+        launch_raster_loss(s, ds, rec, e.R, spb, shape, ex, partial, e.skip);
+      });
     }
     T("tile_reduce", [&] {
-      launch_tile_reduce(s, partial, e.L, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f);
+      launch_tile_reduce(s, partial, e.L, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f,
+                         e.skip);
     });
   } else if (sc->kind == kPT) {
     PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
     T("pt_loss", [&] { launch_pt_loss(s, e, ps, d_theta, tau, u, spb, partial); });
     T("tile_reduce", [&] {
-      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f);
+      launch_tile_reduce(s, partial, e.R, tiles, 1.0 / ((double)sc->W * sc->H * 3.0), f, e.skip);
     });
   } else {
     AnalyticScene as{sc->kind == kQuad ? 0 : 1, sc->n, sc->A, sc->b, sc->c, sc->s1};
@@ -285,13 +294,15 @@ void release_scene_memory(hr_scene* sc) {
   sc->ptc = nullptr;
 }
 
-// the estimator pipeline on device pointers
+// the estimator pipeline on device pointers; with `skip` (a device flag) every
+// kernel of the query returns at once when the flag reads nonzero
 hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, uint64_t N,
                   uint64_t seed, const double* d_v, const hr_opts& o_in, double* d_out,
-                  double* h_dbg, double* h_tau) {
+                  double* h_dbg, double* h_tau, const int* skip = nullptr) {
   QueryPlan pl;
   hr_status st = plan_query(sc, what, sigma, N, seed, d_v != nullptr, o_in, &pl);
   if (st) return st;
+  pl.e.skip = skip;
   hr_ctx* ctx = sc->ctx;
   const hr_opts& o = pl.o;
   const EstShape& e = pl.e;
@@ -426,6 +437,7 @@ void hr_ctx_destroy(hr_ctx* ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->stage) (void)hipFree(ctx->stage);
   if (ctx->hstage) (void)hipHostFree(ctx->hstage);
+  if (ctx->newton_graph.exec) (void)hipGraphExecDestroy(ctx->newton_graph.exec);
   if (ctx->cg) (void)hipFree(ctx->cg);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
@@ -828,6 +840,21 @@ hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uin
   const size_t need = 5 * nv + align256((size_t)n * n * 8) * 3 + align256(sizeof(CgState));
   hr_status st = ensure(ctx, &ctx->cg, &ctx->cg_bytes, need);
   if (st) return st;
+  // the estimates' workspace is sized before the step is enqueued, so that
+  // nothing inside the step allocates (or synchronises to free)
+  {
+    const int prod = no.use_full_hessian ? kHess : (no.hvp_limit ? kHvpLimit : kHvp);
+    QueryPlan pg, pp;
+    st = plan_query(sc, kGrad, sigma, N, seed, false, o, &pg);
+    if (!st) st = plan_query(sc, prod, sigma, N, seed, true, o, &pp);
+    if (st) return st;
+    const size_t ws = pg.total > pp.total ? pg.total : pp.total;
+    if (ws > ctx->budget)
+      return fail(HR_ENOMEM, "request needs " + std::to_string(ws) +
+                                 " bytes of workspace, budget is " + std::to_string(ctx->budget));
+    st = ensure(ctx, &ctx->ws, &ctx->ws_bytes, ws);
+    if (st) return st;
+  }
   char* p = (char*)ctx->cg;
   double* g = (double*)p; p += nv;
   double* r = (double*)p; p += nv;
@@ -839,29 +866,90 @@ hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uin
   CgState* cs = (CgState*)p;
   hipStream_t s = ctx->stream;
 
-  st = run_est(sc, kGrad, d_theta, sigma, N, seed, nullptr, o, g, nullptr, nullptr);
-  if (st) return st;
-  CgState h{};
-  if (no.use_full_hessian) {
-    st = run_est(sc, kHess, d_theta, sigma, N, seed, nullptr, o, Hm, nullptr, nullptr);
-    if (st) return st;
-    launch_newton_full(s, n, Hm, g, no.trust_radius, no.eig_floor, work, d, cs);
-  } else {
-    launch_cg_init(s, n, g, no.trust_radius, no.modified, no.eig_floor, r, pv, d, cs);
-    for (int k = 0; k < no.cg_iters; ++k) {
-      HR_HIP(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, s));
-      HR_HIP(hipStreamSynchronize(s));
-      if (h.stop) break;
-      st = run_est(sc, no.hvp_limit ? kHvpLimit : kHvp, d_theta, sigma, N, seed, pv, o, Hp, nullptr, nullptr);
+  // The step is enqueued without a host round trip: every CG product is
+  // launched, and once the inner loop has stopped (the state's stop flag, set
+  // on the device) each later product's kernels and update return at once.
+  auto enqueue_step = [&]() -> hr_status {
+    hr_status e = run_est(sc, kGrad, d_theta, sigma, N, seed, nullptr, o, g, nullptr, nullptr);
+    if (e) return e;
+    if (no.use_full_hessian) {
+      e = run_est(sc, kHess, d_theta, sigma, N, seed, nullptr, o, Hm, nullptr, nullptr);
+      if (e) return e;
+      launch_newton_full(s, n, Hm, g, no.trust_radius, no.eig_floor, work, d, cs);
+    } else {
+      launch_cg_init(s, n, g, no.trust_radius, no.modified, no.eig_floor, r, pv, d, cs);
+      for (int k = 0; k < no.cg_iters; ++k) {
+        e = run_est(sc, no.hvp_limit ? kHvpLimit : kHvp, d_theta, sigma, N, seed, pv, o, Hp,
+                    nullptr, nullptr, &cs->stop);
+        if (e) return e;
+        launch_cg_update(s, n, Hp, r, pv, d, cs);
+      }
+    }
+    launch_cg_apply(s, n, d, d_theta, cs);
+    HR_HIP(hipGetLastError());
+    return HR_OK;
+  };
+
+  // A step repeated with the same arguments and buffers is replayed as one
+  // hipGraph: the first run is eager, the second is captured, later ones
+  // replay it (kernel timers, when on, keep every run eager).
+  std::vector<char> key;
+  auto put = [&](const void* x, size_t b) {
+    key.insert(key.end(), (const char*)x, (const char*)x + b);
+  };
+  put(&sc->uid, sizeof(sc->uid));
+  put(&d_theta, sizeof(d_theta));
+  put(&sigma, sizeof(sigma));
+  put(&N, sizeof(N));
+  put(&seed, sizeof(seed));
+  put(&no, sizeof(no));
+  put(&o, sizeof(o));
+  put(&ctx->ws, sizeof(ctx->ws));
+  put(&ctx->ws_bytes, sizeof(ctx->ws_bytes));
+  put(&ctx->cg, sizeof(ctx->cg));
+  put(&ctx->cg_bytes, sizeof(ctx->cg_bytes));
+  put(&s, sizeof(s));
+  NewtonGraph& G = ctx->newton_graph;
+  const bool same = !ctx->timing && key == G.key;
+  if (same && G.exec) {
+    HR_HIP(hipGraphLaunch(G.exec, s));
+  } else if (same && G.runs >= 1) {
+    hipGraph_t graph = nullptr;
+    HR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const hr_status est = enqueue_step();
+    const hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (est || ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      G.runs = -1;   // this step does not capture: stay eager
+      if (est) return est;
+      st = enqueue_step();
       if (st) return st;
-      launch_cg_update(s, n, Hp, r, pv, d, cs);
+    } else {
+      const hipError_t ie = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        G.exec = nullptr;
+        return fail(HR_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      }
+      HR_HIP(hipGraphLaunch(G.exec, s));
+    }
+  } else {
+    if (G.exec) {
+      (void)hipGraphExecDestroy(G.exec);
+      G.exec = nullptr;
+    }
+    st = enqueue_step();
+    if (st) return st;
+    if (!same) {
+      G.key = key;
+      G.runs = ctx->timing ? 0 : 1;
     }
   }
-  launch_cg_apply(s, n, d, d_theta, cs);
-  HR_HIP(hipGetLastError());
-  HR_HIP(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, s));
-  HR_HIP(hipStreamSynchronize(s));
   if (report) {
+    CgState h{};
+    HR_HIP(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    HR_HIP(hipStreamSynchronize(s));
     report->iters_done = h.iters;
     report->hit_trust = h.hit_trust;
     report->neg_curv = h.neg_curv;

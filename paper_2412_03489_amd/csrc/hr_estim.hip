@@ -83,7 +83,9 @@ __device__ __forceinline__ void sample_one(int n, int K, int hessk, int mix_n2, 
 
 // one thread per (stream, draw, dimension)
 __global__ void k_sample(int n, int K, int hessk, int mix_n2, int sampler, uint64_t N,
-                         uint64_t seed, double sg, uint64_t total, double* __restrict__ tau) {
+                         uint64_t seed, double sg, uint64_t total, double* __restrict__ tau,
+                         const int* skip) {
+  if (skip && *skip) return;
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
        gid += (uint64_t)gridDim.x * blockDim.x)
     sample_one(n, K, hessk, mix_n2, sampler, N, seed, sg, gid, tau);
@@ -114,8 +116,10 @@ __global__ __launch_bounds__(256) void k_sample_vnorm(int n, int K, int hessk, i
                                                       double* __restrict__ tau,
                                                       const double* __restrict__ v,
                                                       double* __restrict__ u,
-                                                      double* __restrict__ vnorm) {
+                                                      double* __restrict__ vnorm,
+                                                      const int* skip) {
   __shared__ double s_acc[256];
+  if (skip && *skip) return;
   if (blockIdx.x == 0) vnorm_block(n, v, u, vnorm, s_acc);
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
        gid += (uint64_t)gridDim.x * blockDim.x)
@@ -164,7 +168,8 @@ __global__ void k_analytic(int kind, int n, const double* __restrict__ A,
                            const double* __restrict__ b, double c, double s1,
                            const double* __restrict__ theta, const double* __restrict__ tau,
                            const double* __restrict__ u, int Aa, int NH, double h, uint64_t R,
-                           double* __restrict__ f) {
+                           double* __restrict__ f, const int* skip) {
+  if (skip && *skip) return;
   for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < R;
        r += (uint64_t)gridDim.x * blockDim.x)
     analytic_one(kind, n, A, b, c, s1, theta, tau, u, Aa, NH, h, r, f);
@@ -267,6 +272,7 @@ __device__ __forceinline__ void prep_one(const EstShape& e, const double* __rest
 __global__ void k_prep(EstShape e, const double* __restrict__ f, const double* __restrict__ tau,
                        const double* __restrict__ vnorm, const double* __restrict__ v,
                        double* __restrict__ Fq, double* __restrict__ vt) {
+  if (e.skip && *e.skip) return;
   const uint64_t total = e.streams * e.N;
   for (uint64_t sidx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; sidx < total;
        sidx += (uint64_t)gridDim.x * blockDim.x)
@@ -354,6 +360,7 @@ __global__ __launch_bounds__(256) void k_accum(EstShape e, const double* __restr
                                                const double* __restrict__ v, int fp64,
                                                int chunk, void* __restrict__ part) {
   __shared__ AccumLds lds;
+  if (e.skip && *e.skip) return;
   accum_block(e, tau, Fq, vt, v, fp64, chunk, blockIdx.x, part, lds);
 }
 
@@ -391,6 +398,7 @@ __device__ __forceinline__ void accum_is_one(const EstShape& e, const double* __
 __global__ void k_accum_is(EstShape e, const double* __restrict__ tau,
                            const double* __restrict__ Fq, int fp64, int chunk, uint64_t nchunks,
                            void* __restrict__ part) {
+  if (e.skip && *e.skip) return;
   const uint64_t total = nchunks * (uint64_t)e.nout;
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
        gid += (uint64_t)gridDim.x * blockDim.x)
@@ -443,6 +451,7 @@ __global__ __launch_bounds__(256) void k_finalize(EstShape e, const void* __rest
                                                   int fp64, uint64_t nchunks,
                                                   double* __restrict__ out) {
   __shared__ double s_pos[256], s_neg[256];
+  if (e.skip && *e.skip) return;
   finalize_block(e, part, fp64, nchunks, blockIdx.x, out, s_pos, s_neg);
 }
 
@@ -551,21 +560,22 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const BatchTable* __rest
 void launch_sample(hipStream_t st, const EstShape& e, double* tau) {
   const uint64_t total = e.streams * e.N * (uint64_t)e.n;
   hipLaunchKernelGGL(k_sample, dim3(grid_for(total, 256)), dim3(256), 0, st, e.n, e.K, e.hessk,
-                     e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau);
+                     e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau, e.skip);
 }
 
 void launch_sample_vnorm(hipStream_t st, const EstShape& e, double* tau, const double* v,
                          double* u, double* vnorm) {
   const uint64_t total = e.streams * e.N * (uint64_t)e.n;
   hipLaunchKernelGGL(k_sample_vnorm, dim3(grid_for(total, 256)), dim3(256), 0, st, e.n, e.K,
-                     e.hessk, e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau, v, u, vnorm);
+                     e.hessk, e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau, v, u, vnorm,
+                     e.skip);
 }
 
 
 void launch_analytic(hipStream_t st, const EstShape& e, const AnalyticScene& s,
                      const double* theta, const double* tau, const double* u, double* f) {
   hipLaunchKernelGGL(k_analytic, dim3(grid_for(e.R, 128)), dim3(128), 0, st, s.kind, s.n, s.A, s.b,
-                     s.c, s.s1, theta, tau, u, e.A, e.NH, e.h, e.R, f);
+                     s.c, s.s1, theta, tau, u, e.A, e.NH, e.h, e.R, f, e.skip);
 }
 
 void launch_prep(hipStream_t st, const EstShape& e, const double* f, const double* tau,

@@ -28,6 +28,10 @@ struct EstShape {
                                      //    pairs, one loss difference per (draw, a)
   int pad_;
   uint64_t L;                        // loss outputs: R / 2 pairs (pair), else R
+  // device flag: when it reads nonzero at launch, every kernel of the query
+  // returns at once (a Newton-CG product after the inner loop stopped);
+  // nullptr: never
+  const int* skip;
   double sigma, h;                   // h: HVP step (0 if none)
   uint64_t seed;
 };
@@ -85,6 +89,7 @@ struct RasterQuery {
   int pad;
   uint64_t R, r_base;
   RasterExact ex;
+  const int* skip;       // as EstShape::skip
 };
 // the per-query raster kernel finds `ex` in its kernel arguments by offsetof
 static_assert(std::is_standard_layout<RasterQuery>::value, "RasterQuery is read by offsetof");
@@ -103,16 +108,18 @@ void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const
 void launch_pair_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
                          const double* tau, const double* u, float4* rec);
 void launch_raster_dloss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t P,
-                         int pairs_per_block, int shape, const RasterExact& ex, float* partial);
+                         int pairs_per_block, int shape, const RasterExact& ex, float* partial,
+                         const int* skip = nullptr);
 size_t raster_pair_lds_bytes(int D);
 // largest disk count of the pair path (more disks render the HVP per render)
 int raster_pair_max_disks();
 // number of 16x16 wave tiles of the image: the partial stride per render
 int raster_subtiles(int W, int H);
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
-                        int samples_per_block, int shape, const RasterExact& ex, float* partial);
+                        int samples_per_block, int shape, const RasterExact& ex, float* partial,
+                        const int* skip = nullptr);
 void launch_tile_reduce(hipStream_t st, const float* partial, uint64_t R, int tiles,
-                        double inv_count, double* f);
+                        double inv_count, double* f, const int* skip = nullptr);
 void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& ex, float* image);
 
 struct PTScene {

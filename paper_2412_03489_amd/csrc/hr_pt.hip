@@ -296,6 +296,7 @@ void k_pt_loss(const PTConst* ptc, const double* __restrict__ theta,
                int S, int tiles_x, int tiles, uint64_t draw0,
                uint64_t chunks, float* __restrict__ partial) {
   __shared__ float s_part[kPtMaxS * NR][4];
+  if (e.skip && *e.skip) return;
   // XCD-aware order as in the rasteriser
   const uint64_t b = blockIdx.x;
   const uint64_t xcd = b & 7u, j = b >> 3;

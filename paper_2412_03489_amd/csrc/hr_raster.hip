@@ -104,7 +104,8 @@ __device__ __forceinline__ void record_one(const double* __restrict__ theta,
 __global__ void k_records(const double* __restrict__ theta, const double* __restrict__ tau,
                           const double* __restrict__ u, const float* __restrict__ radius,
                           int n, int D, int ppd, int A, int NH, double h, uint64_t total,
-                          float4* __restrict__ rec) {
+                          float4* __restrict__ rec, const int* skip) {
+  if (skip && *skip) return;
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
        gid += (uint64_t)gridDim.x * blockDim.x)
     record_one(theta, tau, u, radius, n, D, ppd, A, NH, h, gid, rec);
@@ -493,6 +494,7 @@ template <int C, bool kOneGroup>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
 void k_raster_loss(RasterQuery a, uint64_t chunks) {
   extern __shared__ float4 smem[];
+  if (a.skip && *a.skip) return;
   // XCD-aware order: consecutive blocks on one XCD (block id mod 8) sweep all
   // tiles of one render chunk, so a chunk's records stay in that XCD's L2.
   const uint64_t b = blockIdx.x;
@@ -568,7 +570,8 @@ __device__ __forceinline__ void pair_record_one(const double* __restrict__ theta
 __global__ void k_pair_records(const double* __restrict__ theta, const double* __restrict__ tau,
                                const double* __restrict__ u, const float* __restrict__ radius,
                                int n, int D, int ppd, int A, double h, uint64_t total,
-                               float4* __restrict__ rec) {
+                               float4* __restrict__ rec, const int* skip) {
+  if (skip && *skip) return;
   for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
        gid += (uint64_t)gridDim.x * blockDim.x)
     pair_record_one(theta, tau, u, radius, n, D, ppd, A, h, gid, rec);
@@ -870,6 +873,7 @@ template <int C>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HR_DLOSS_WAVES)))
 void k_raster_dloss(RasterQuery a, uint64_t chunks) {
   extern __shared__ float4 smem[];
+  if (a.skip && *a.skip) return;
   const uint64_t b = blockIdx.x;
   const uint64_t xcd = b & 7u, j = b >> 3;
   const uint64_t chunk = (j / (uint64_t)a.tiles) * 8u + xcd;
@@ -996,7 +1000,7 @@ void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const
                     const double* tau, const double* u, float4* rec) {
   const uint64_t total = e.R * (uint64_t)s.D;
   hipLaunchKernelGGL(k_records, dim3(grid_for(total, 256)), dim3(256), 0, st, theta, tau, u,
-                     s.radius, e.n, s.D, s.ppd, e.A, e.NH, e.h, total, rec);
+                     s.radius, e.n, s.D, s.ppd, e.A, e.NH, e.h, total, rec, e.skip);
 }
 
 int raster_subtiles(int W, int H) { return ((W + kSub - 1) / kSub) * ((H + kSub - 1) / kSub); }
@@ -1053,7 +1057,7 @@ int raster_auto_samples(int W, int H, uint64_t R, int shape) {
 }
 
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
-                        int S, int shape, const RasterExact& ex, float* partial) {
+                        int S, int shape, const RasterExact& ex, float* partial, const int* skip) {
   if (S <= 0) S = raster_auto_samples(s.W, s.H, R, shape);
   if (S > kMaxS) S = kMaxS;
   RasterQuery a;
@@ -1077,6 +1081,7 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
     a.R = umin64(R - r_base, sub_chunks * (uint64_t)S);
     a.r_base = r_base;
     a.ex = ex;
+    a.skip = skip;
     const dim3 grid((unsigned)(8 * tiles * rows));
 #define HR_RASTER(CC, ONE) \
   hipLaunchKernelGGL((k_raster_loss<CC, ONE>), grid, dim3(256), lds, st, a, sub_chunks)
@@ -1095,7 +1100,7 @@ void launch_pair_records(hipStream_t st, const EstShape& e, const DiskScene& s, 
                          const double* tau, const double* u, float4* rec) {
   const uint64_t total = e.L * (uint64_t)s.D;
   hipLaunchKernelGGL(k_pair_records, dim3(grid_for(total, 256)), dim3(256), 0, st, theta, tau, u,
-                     s.radius, e.n, s.D, s.ppd, e.A, e.h, total, rec);
+                     s.radius, e.n, s.D, s.ppd, e.A, e.h, total, rec, e.skip);
 }
 
 size_t raster_pair_lds_bytes(int D) {
@@ -1105,7 +1110,7 @@ size_t raster_pair_lds_bytes(int D) {
 int raster_pair_max_disks() { return 64; }
 
 void launch_raster_dloss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t P, int S,
-                         int shape, const RasterExact& ex, float* partial) {
+                         int shape, const RasterExact& ex, float* partial, const int* skip) {
   // S counts pairs per block (two renders each): the library's choice is half
   // the renders-per-block rule's, at least one flush group
   if (S <= 0) S = raster_auto_samples(s.W, s.H, 2 * P, shape) / 2;
@@ -1130,6 +1135,7 @@ void launch_raster_dloss(hipStream_t st, const DiskScene& s, const float4* rec, 
     a.R = umin64(P - r_base, sub_chunks * (uint64_t)S);
     a.r_base = r_base;
     a.ex = ex;
+    a.skip = skip;
     const dim3 grid((unsigned)(8 * tiles * rows));
     switch (s.C) {
       case 1: hipLaunchKernelGGL(k_raster_dloss<1>, grid, dim3(256), lds, st, a, sub_chunks); break;

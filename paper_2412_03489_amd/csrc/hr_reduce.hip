@@ -40,7 +40,8 @@ __device__ __forceinline__ void reduce_group(const float* __restrict__ partial, 
 
 // one wave per group of 16 renders
 __global__ void k_tile_reduce(const float* __restrict__ partial, uint64_t R, int tiles,
-                              double inv_count, double* __restrict__ f) {
+                              double inv_count, double* __restrict__ f, const int* skip) {
+  if (skip && *skip) return;
   const uint64_t groups = (R + 15) / 16;
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t g = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g < groups;
@@ -68,10 +69,10 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchTable* __restri
 }  // namespace
 
 void launch_tile_reduce(hipStream_t st, const float* partial, uint64_t R, int tiles,
-                        double inv_count, double* f) {
+                        double inv_count, double* f, const int* skip) {
   const uint64_t blocks = ((R + 15) / 16 + 3) / 4;
   hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)umin64(blocks, 1u << 20)), dim3(256), 0, st,
-                     partial, R, tiles, inv_count, f);
+                     partial, R, tiles, inv_count, f, skip);
 }
 
 void launch_batch_reduce(hipStream_t st, const BatchTable* T, int blocks) {

@@ -16,6 +16,14 @@
 #include "hrest.h"
 #include "hr_kernels.h"
 
+// The captured launch sequence of a repeated Newton-CG step and the
+// arguments it was captured for.
+struct NewtonGraph {
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> key;
+  int runs = 0;              // eager runs with this key (-1: does not capture)
+};
+
 struct hr_ctx {
   int device = 0;
   hipStream_t own = nullptr;
@@ -37,10 +45,14 @@ struct hr_ctx {
   // samples-per-block / block-shape choices of the raster autotuner, by class
   std::map<uint64_t, std::pair<int, int>> tuned;
   std::mutex tuned_mu;   // a server's worker and the caller's thread share it
+  NewtonGraph newton_graph;
 };
+
+uint64_t next_scene_uid();
 
 struct hr_scene {
   hr_ctx* ctx = nullptr;
+  uint64_t uid = next_scene_uid();   // distinct for every scene of the process
   int kind = hr::kDisks;
   int n = 0;
   int W = 0, H = 0, C = 0;

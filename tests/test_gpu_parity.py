@@ -500,3 +500,43 @@ def test_errors_and_edge_cases(P, ctx, quad_pair):
         P.estimate("grad", s3, th, 0.1, 10, 1)
     s3.close()
     assert np.isfinite(P.estimate("grad", gsc, th, 0.1, 10, 1)).all()
+
+
+def test_newton_step_device_resident_and_graph_replays(P, ctx, disks32):
+    """The Newton-CG step runs without a host round trip: after the inner
+    loop stops on the device (here a trust-region truncation) the remaining
+    products' kernels return at once.  Repeating the step with the same
+    arguments runs it eagerly, then captured as a hipGraph, then as replays;
+    every run (with eager work between the replays) gives the same bits, and
+    the step equals the oracle's."""
+    w, osc, gsc = disks32
+    N, kw = 4096, dict(cg_iters=6, trust_radius=0.02)
+    th0, th = ctx.alloc(8 * w.n), ctx.alloc(8 * w.n)
+    th0.upload(w.theta0)
+    runs = []
+    for k in range(5):
+        say(f"newton step run {k}")
+        th.copy_from(th0)
+        rep = P.newton_cg_step_dev(gsc, th.ptr, w.sigma, N, w.seed, **kw)
+        runs.append((th.download(w.n), rep))
+        if k >= 2:
+            P.estimate("grad", gsc, w.theta0, w.sigma, 512, 7)
+    for got, rep in runs[1:]:
+        assert np.array_equal(got, runs[0][0])
+        assert rep == runs[0][1]
+    assert runs[0][1]["hit_trust"] == 1 and runs[0][1]["iters_done"] < kw["cg_iters"]
+    ref, rr = O.newton_cg_step(osc, w.theta0, w.sigma, N, w.seed, **kw)
+    assert rr["iters_done"] == runs[0][1]["iters_done"]
+    err = rel_inf(runs[0][0] - w.theta0, ref - w.theta0)
+    say(f"  step error vs FP64 oracle: rel_inf = {err:.3e}")
+    assert err < TOL
+    # other arguments: a fresh eager run, then the new step is captured
+    th.copy_from(th0)
+    P.newton_cg_step_dev(gsc, th.ptr, w.sigma, N, w.seed + 1, **kw)
+    other = th.download(w.n)
+    th.copy_from(th0)
+    P.newton_cg_step_dev(gsc, th.ptr, w.sigma, N, w.seed + 1, **kw)
+    assert np.array_equal(th.download(w.n), other)
+    assert not np.array_equal(other, runs[0][0])
+    th0.free()
+    th.free()
