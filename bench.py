@@ -233,13 +233,19 @@ def uneven_section(P, ctx, reps):
 def serving_section(P, ctx, args):
     """Newton optimisations over the raster and path-traced scenes:
     continuous-batching server vs plain per-query calls served one at a time
-    in the order queries become ready.  An open-loop saturating run first
-    (Poisson arrivals of 256 optimisations of one step each), then 256
-    closed-loop clients: with no think time (the plain capacity of their query
-    mix), and with think times offering 0.5, 0.8, 1.0 and 1.5 x that
-    capacity."""
+    in the order queries become ready.  Two regimes:
+      * the workloads' own sample budgets (raster HVPs and gradients at
+        N = 65536, path-traced gradients and 6x6 Hessians at N = 8192): an
+        open-loop saturating run (Poisson arrivals of optimisations of one
+        step each), then closed-loop clients with no think time (the plain
+        capacity of their query mix) and with think times offering 0.5, 0.8,
+        1.0 and 1.5 x that capacity;
+      * the paper's per-iteration budgets (appendix "Hyperparameters": a few
+        antithetic draws per estimate; here 6), where a query is a few
+        microseconds of GPU work: closed-loop clients with no think time and
+        an open-loop Poisson stream."""
     import workloads as WL
-    from paper_2412_03489_amd import serving as SV
+    import bench_serving as SV
     wr = WL.disks32()
     wp = WL.pt_spheres()
     sr = P.Scene.disks(ctx, wr.W, wr.H, wr.C, wr.colors, render_target_on_gpu(P, ctx, wr),
@@ -250,57 +256,67 @@ def serving_section(P, ctx, args):
     sp = P.Scene.pt(ctx, wp.W, wp.H, wp.spp, wp.desc, tp)
     scenes = {"raster": sr, "pt": sp}
     sigma = {"raster": wr.sigma, "pt": wp.sigma}
-    N = {"raster": args.serving_n_raster, "pt": args.serving_n_pt}
     cg = args.serving_cg
+    rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+    keep = ("queries", "queries_per_s", "p50_ms", "p99_ms", "by_kind")
+    keep_srv = keep + ("batches", "mean_batch")
 
-    def clients(specs, steps=1):
+    def clients(specs, N, steps=1):
         return SV.make_clients(specs, scenes, sigma, N, cg, steps=steps, full_cg=True)
 
-    # warm both paths
-    warm = WL.serving_clients(4, rate=1e6, base_seed=99)
-    SV.run_plain(ctx, clients(warm))
-    SV.run_served(ctx, clients(warm))
-    rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
-    out = {"clients": args.serving_clients,
-           "client": f"raster: 1 gradient + {cg} HVPs (N={N['raster']}); "
-                     f"path-traced: gradient + 6x6 Hessian (N={N['pt']})"}
-    specs = WL.serving_clients(args.serving_clients, rate=args.serving_rate)
-    log(f"bench: serving {len(specs)} clients at {args.serving_rate}/s, plain")
-    plain = SV.run_plain(ctx, clients(specs))
-    log(f"bench: serving {len(specs)} clients at {args.serving_rate}/s, continuous batching")
-    served = SV.run_served(ctx, clients(specs))
-    out["saturated"] = {"arrival_rate_per_s": args.serving_rate, "plain": rnd(plain),
-                        "served": rnd(served),
-                        "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
-    # closed loop: the clients all start together and keep taking Newton
-    # steps, thinking an exponential time before each query; no query becomes
-    # ready after the measurement window.  Every client issues queries at the
-    # same rate, so path-traced queries are half the mix (a third of the open
-    # loop's share of raster work): the plain capacity of this mix is measured
-    # first, with no think time, and the offered loads are scaled from it
-    # (think mean = clients / (load x capacity)).
-    win = args.serving_window
-    nc = args.serving_sweep_clients
-    keep = ("queries", "queries_per_s", "p50_ms", "p99_ms", "by_kind")
-    specs = WL.serving_clients(nc, rate=1e6, base_seed=3000)
-    log(f"bench: serving closed loop, {nc} clients, no think time (capacity)")
-    pl = SV.run_plain(ctx, clients(specs, 10 ** 6), think_ms=0.0, window_s=win)
-    sv = SV.run_served(ctx, clients(specs, 10 ** 6), think_ms=0.0, window_s=win)
-    cap = pl["queries_per_s"]
-    out["closed_loop_saturated"] = {"clients": nc, "window_s": win,
-                                    "plain": rnd({k: pl[k] for k in keep}),
-                                    "served": rnd({k: sv[k] for k in keep})}
-    sweep = []
-    for rho in (0.5, 0.8, 1.0, 1.5):
-        think_ms = 1e3 * nc / (rho * cap)
-        log(f"bench: serving closed loop, load {rho} x plain capacity (think {think_ms:.0f} ms)")
-        pl = SV.run_plain(ctx, clients(specs, 10 ** 6), think_ms=think_ms, window_s=win)
-        sv = SV.run_served(ctx, clients(specs, 10 ** 6), think_ms=think_ms, window_s=win)
-        sweep.append({"load": rho, "think_ms": round(think_ms, 1), "window_s": win,
-                      "plain": {k: pl[k] for k in keep}, "served": {k: sv[k] for k in keep}})
-    out["closed_loop_sweep"] = [{k: (rnd(v) if isinstance(v, dict) else v) for k, v in x.items()}
-                                for x in sweep]
-    out["closed_loop_plain_capacity_qps"] = round(cap, 2)
+    def regime(N, open_clients, rate, sweep):
+        # warm both paths
+        warm = WL.serving_clients(4, rate=1e6, base_seed=99)
+        SV.run_plain(ctx, clients(warm, N))
+        SV.run_served(ctx, clients(warm, N))
+        out = {"client": f"raster: 1 gradient + {cg} HVPs (N={N['raster']}); "
+                         f"path-traced: gradient + 6x6 Hessian (N={N['pt']})"}
+        specs = WL.serving_clients(open_clients, rate=rate)
+        log(f"bench: serving N={N}, {len(specs)} optimisations arriving at {rate}/s, plain")
+        plain = SV.run_plain(ctx, clients(specs, N))
+        log(f"bench: serving N={N}, {len(specs)} optimisations arriving at {rate}/s, served")
+        served = SV.run_served(ctx, clients(specs, N))
+        out["open_loop"] = {"optimisations": len(specs), "arrival_rate_per_s": rate,
+                            "plain": rnd(plain), "served": rnd(served),
+                            "qps_ratio": round(served["queries_per_s"] / plain["queries_per_s"], 3)}
+        # closed loop: the clients all start together and keep taking Newton
+        # steps, thinking an exponential time before each query; no query
+        # becomes ready after the window.  The plain capacity of the mix is
+        # measured first (no think time) and the offered loads are scaled
+        # from it (think mean = clients / (load x capacity)).
+        win = args.serving_window
+        nc = args.serving_sweep_clients
+        specs = WL.serving_clients(nc, rate=1e6, base_seed=3000)
+        log(f"bench: serving N={N}, closed loop, {nc} clients, no think time")
+        pl = SV.run_plain(ctx, clients(specs, N, 10 ** 6), think_ms=0.0, window_s=win)
+        sv = SV.run_served(ctx, clients(specs, N, 10 ** 6), think_ms=0.0, window_s=win)
+        cap = pl["queries_per_s"]
+        out["closed_loop_saturated"] = {"clients": nc, "window_s": win,
+                                        "plain": rnd({k: pl[k] for k in keep}),
+                                        "served": rnd({k: sv[k] for k in keep_srv}),
+                                        "qps_ratio": round(sv["queries_per_s"] / cap, 3)}
+        out["closed_loop_plain_capacity_qps"] = round(cap, 2)
+        rows = []
+        for rho in sweep:
+            think_ms = 1e3 * nc / (rho * cap)
+            log(f"bench: serving N={N}, closed loop, load {rho} x plain capacity "
+                f"(think {think_ms:.1f} ms)")
+            pl = SV.run_plain(ctx, clients(specs, N, 10 ** 6), think_ms=think_ms, window_s=win)
+            sv = SV.run_served(ctx, clients(specs, N, 10 ** 6), think_ms=think_ms, window_s=win)
+            rows.append({"load": rho, "think_ms": round(think_ms, 2), "window_s": win,
+                         "plain": rnd({k: pl[k] for k in keep}),
+                         "served": rnd({k: sv[k] for k in keep_srv})})
+        if rows:
+            out["closed_loop_sweep"] = rows
+        return out
+
+    out = {"clients": args.serving_clients}
+    out["workload_budgets"] = regime({"raster": args.serving_n_raster, "pt": args.serving_n_pt},
+                                     args.serving_clients, args.serving_rate,
+                                     (0.5, 0.8, 1.0, 1.5))
+    out["paper_budgets"] = regime({"raster": args.serving_small_n, "pt": args.serving_small_n},
+                                  args.serving_small_clients, args.serving_small_rate,
+                                  (0.5, 1.0))
     sr.close()
     sp.close()
     return out
@@ -586,13 +602,17 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--uneven-reps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
-    ap.add_argument("--serving-clients", type=int, default=256)
-    ap.add_argument("--serving-rate", type=float, default=512.0)
+    ap.add_argument("--serving-clients", type=int, default=128)
+    ap.add_argument("--serving-rate", type=float, default=256.0)
     ap.add_argument("--serving-sweep-clients", type=int, default=256)
     ap.add_argument("--serving-window", type=float, default=4.0,
                     help="seconds of closed-loop traffic per offered load")
-    ap.add_argument("--serving-n-raster", type=int, default=16384)
-    ap.add_argument("--serving-n-pt", type=int, default=2048)
+    ap.add_argument("--serving-n-raster", type=int, default=65536)
+    ap.add_argument("--serving-n-pt", type=int, default=8192)
+    ap.add_argument("--serving-small-n", type=int, default=6,
+                    help="draws per estimate of the paper-budget serving regime")
+    ap.add_argument("--serving-small-clients", type=int, default=512)
+    ap.add_argument("--serving-small-rate", type=float, default=8192.0)
     ap.add_argument("--serving-cg", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

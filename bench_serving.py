@@ -23,7 +23,7 @@ import time
 
 import numpy as np
 
-from . import Server, estimate
+from paper_2412_03489_amd import Server, estimate
 
 TRUST = 0.05
 EIG_FLOOR = 1e-3

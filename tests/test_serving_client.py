@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
-from paper_2412_03489_amd import serving as SV
+import bench_serving as SV
 
 
 def _quadratic(n, seed):
