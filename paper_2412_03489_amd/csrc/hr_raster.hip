@@ -866,11 +866,11 @@ __device__ __forceinline__ void dloss_block(const Query& a, const ConstExact* ex
     passes(std::integral_constant<int, 1>{});
 }
 
-#ifndef HR_DLOSS_WAVES
-#define HR_DLOSS_WAVES 7
-#endif
+// seven waves per SIMD (at most 72 VGPRs; two per-wave values spill to
+// scratch and are reloaded once per cull): the fastest of the wave counts
+// timed, the extra waves hiding the record and LDS latency of the cull
 template <int C>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HR_DLOSS_WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
 void k_raster_dloss(RasterQuery a, uint64_t chunks) {
   extern __shared__ float4 smem[];
   if (a.skip && *a.skip) return;
