@@ -405,9 +405,10 @@ const char* hr_last_error(void) { return error_slot().c_str(); }
 
 hr_status hr_ctx_create(int device, hr_ctx** out) {
   if (!out) return fail(HR_EINVAL, "out is NULL");
+  if (device < 0) return fail(HR_EINVAL, "negative device index");
   int count = 0;
   HR_HIP(hipGetDeviceCount(&count));
-  if (device < 0 || device >= count) return fail(HR_EINVAL, "no such device");
+  if (device >= count) return fail(HR_EINVAL, "no such device");
   HR_HIP(hipSetDevice(device));
   // this device's copy of the fixed workspace (hr_est_hvp_dev_noalloc)
   hr_status sst = scratch_resolve(device);
