@@ -427,6 +427,15 @@ typedef struct {
                                (default: the context's memory budget)           */
   int use_graph;            /* as in hr_batch_opts (default 1)                  */
   int autotune;             /* as in hr_batch_opts (default 0)                  */
+  const char* metrics_path; /* per-query metrics as JSON Lines, appended to
+                               this file (default NULL: none): one object per
+                               completed query with ticket, kind, scene, W, H,
+                               params, N, seed, sampler, renders, batch,
+                               batch_size, slot, submit_ms, start_ms, end_ms,
+                               queue_ms, service_ms and status (times in ms
+                               since the server started).  The string is read
+                               at creation only; a file that cannot be opened
+                               is HR_EINVAL.                                    */
 } hr_server_opts;
 
 typedef struct {

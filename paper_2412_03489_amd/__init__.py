@@ -86,7 +86,8 @@ class BatchReport(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("slots", C.c_int), ("max_batch", C.c_int), ("max_batch_ms", C.c_double),
-                ("memory_bytes", C.c_uint64), ("use_graph", C.c_int), ("autotune", C.c_int)]
+                ("memory_bytes", C.c_uint64), ("use_graph", C.c_int), ("autotune", C.c_int),
+                ("metrics_path", C.c_char_p)]
 
 
 class QueryStats(C.Structure):
@@ -571,9 +572,11 @@ class Server:
     """Continuous-batching server (hr_server)."""
 
     def __init__(self, ctx, slots=4, max_batch=64, max_batch_ms=2.0, memory_bytes=0,
-                 use_graph=True, autotune=False):
+                 use_graph=True, autotune=False, metrics_path=None):
+        """metrics_path: append one JSON line per completed query to this file."""
         o = ServerOpts(int(slots), int(max_batch), float(max_batch_ms), int(memory_bytes),
-                       1 if use_graph else 0, 1 if autotune else 0)
+                       1 if use_graph else 0, 1 if autotune else 0,
+                       os.fsencode(metrics_path) if metrics_path else None)
         h = C.c_void_p()
         _check(lib().hr_server_create(ctx.h, C.byref(o), C.byref(h)))
         self.ctx, self.h = ctx, h

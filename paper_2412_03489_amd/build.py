@@ -34,6 +34,10 @@ FLAGS = [
 ]
 
 
+# roctx ranges around the host-side calls (rocprofv3 --marker-trace)
+LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
@@ -56,7 +60,7 @@ def build(verbose: bool = True) -> str:
     tmp = OUT + ".tmp"
     # every symbol resolved at link time: a missing definition fails the build
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp,
-           *objs]
+           *objs, *LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

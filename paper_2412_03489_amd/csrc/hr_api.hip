@@ -296,9 +296,20 @@ void release_scene_memory(hr_scene* sc) {
 
 // the estimator pipeline on device pointers; with `skip` (a device flag) every
 // kernel of the query returns at once when the flag reads nonzero
+const char* est_range(int what) {
+  switch (what) {
+    case kGrad: return "hr_est grad";
+    case kHess: return "hr_est hessian";
+    case kHvp: return "hr_est hvp";
+    case kHvpLimit: return "hr_est hvp_limit";
+    default: return "hr_est loss";
+  }
+}
+
 hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, uint64_t N,
                   uint64_t seed, const double* d_v, const hr_opts& o_in, double* d_out,
                   double* h_dbg, double* h_tau, const int* skip = nullptr) {
+  TraceRange range(est_range(what));
   QueryPlan pl;
   hr_status st = plan_query(sc, what, sigma, N, seed, d_v != nullptr, o_in, &pl);
   if (st) return st;
@@ -657,6 +668,7 @@ hr_status hr_render(hr_scene* sc, const double* theta, uint64_t seed, uint32_t s
   if (!sc || !theta || !image) return fail(HR_EINVAL, "NULL argument");
   if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
   if (sc->kind != kDisks && sc->kind != kPT) return fail(HR_EUNSUPPORTED, "analytic scenes have no image");
+  TraceRange range("hr_render");
   if (!finite_all(theta, sc->n)) return fail(HR_EINVAL, "theta has a non-finite entry");
   hr_ctx* ctx = sc->ctx;
   HR_HIP(hipSetDevice(ctx->device));
@@ -727,6 +739,7 @@ hr_status hr_est_hvp_dev_noalloc(hr_scene* sc, const double* d_theta, double sig
                                  uint64_t seed, const double* d_v, const hr_opts* opts,
                                  double* d_Hv) {
   if (!sc || !d_theta || !d_v || !d_Hv) return fail(HR_EINVAL, "NULL argument");
+  TraceRange range("hr_est hvp noalloc");
   hr_opts o = resolve(opts);
   o.dbg_loss = nullptr;
   o.dbg_tau = nullptr;
@@ -824,6 +837,7 @@ hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uin
                                 hr_ncg_report* report) {
   if (!sc || !d_theta) return fail(HR_EINVAL, "NULL argument");
   if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
+  TraceRange range("hr_newton_cg_step");
   hr_ncg_opts no;
   hr_ncg_opts_default(&no);
   if (ncg) no = *ncg;
@@ -980,6 +994,7 @@ hr_status hr_optimize(hr_scene* sc, double* theta, uint64_t N, uint64_t seed,
                       const hr_optim_opts* oo_in, const hr_opts* opts, double* trace) {
   if (!sc || !theta) return fail(HR_EINVAL, "NULL argument");
   if (!sc->ctx) return fail(HR_EINVAL, "the scene's context has been destroyed");
+  TraceRange range("hr_optimize");
   hr_optim_opts oo;
   hr_optim_opts_default(&oo);
   if (oo_in) oo = *oo_in;

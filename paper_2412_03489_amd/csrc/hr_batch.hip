@@ -599,6 +599,7 @@ void hr_batch_destroy(hr_batch* b) {
 hr_status hr_batch_run(hr_batch* b, const hr_query* queries, int count) {
   if (!b || (!queries && count > 0)) return fail(HR_EINVAL, "NULL argument");
   if (count < 0) return fail(HR_EINVAL, "count must be >= 0");
+  TraceRange range("hr_batch_run");
   hr_ctx* ctx = b->ctx;
   if (!b->slot.ctx) return fail(HR_EINVAL, "batch is not initialised");
   for (int i = 0; i < count; ++i) {

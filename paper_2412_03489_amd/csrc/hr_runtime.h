@@ -4,6 +4,7 @@
 // single-query entry points, the batch executor and the server.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <condition_variable>
@@ -15,6 +16,15 @@
 
 #include "hrest.h"
 #include "hr_kernels.h"
+
+// A roctx range over a host-side call (estimates, solver steps, batches),
+// shown by rocprofv3 --marker-trace; nearly free when no tool listens.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // The captured launch sequence of a repeated Newton-CG step and the
 // arguments it was captured for.

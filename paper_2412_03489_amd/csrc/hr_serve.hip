@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -55,7 +56,47 @@ struct Ticket {
   hr_query_stats stats{};
   int state = 0;   // 0 waiting, 1 on the device, 2 done
   bool waited = false;   // a thread is blocked in hr_wait on this ticket
+  uint64_t batch = 0;    // the batch it ran in (1, 2, ...; 0: none)
+  int slot = -1;         // the slot that ran it
 };
+
+const char* what_name(int w) {
+  switch (w) {
+    case kGrad: return "grad";
+    case kHess: return "hess";
+    case kHvp: return "hvp";
+    case kHvpLimit: return "hvp_limit";
+    default: return "loss";
+  }
+}
+
+const char* scene_name(int k) {
+  switch (k) {
+    case kDisks: return "disks";
+    case kPT: return "pt";
+    case kQuad: return "quad";
+    default: return "neggauss";
+  }
+}
+
+// One JSON line per completed query: what it was, where it ran, its times
+// (ms since the server started) and its status.
+void write_metrics(FILE* f, const Ticket& t) {
+  const QueryPlan& p = t.item.plan;
+  const hr_scene* sc = p.sc;
+  const hr_query_stats& st = t.stats;
+  std::fprintf(f,
+               "{\"ticket\":%llu,\"kind\":\"%s\",\"scene\":\"%s\",\"W\":%d,\"H\":%d,"
+               "\"params\":%d,\"N\":%llu,\"seed\":%llu,\"sampler\":%d,\"renders\":%llu,"
+               "\"batch\":%llu,\"batch_size\":%d,\"slot\":%d,\"submit_ms\":%.4f,"
+               "\"start_ms\":%.4f,\"end_ms\":%.4f,\"queue_ms\":%.4f,\"service_ms\":%.4f,"
+               "\"status\":%d}\n",
+               (unsigned long long)t.id, what_name(p.e.what), scene_name(sc->kind), sc->W, sc->H,
+               sc->n, (unsigned long long)p.e.N, (unsigned long long)p.e.seed, p.e.sampler,
+               (unsigned long long)p.e.R, (unsigned long long)t.batch, st.batch_size, t.slot,
+               st.submit_ms, st.start_ms, st.end_ms, st.start_ms - st.submit_ms,
+               st.end_ms - st.start_ms, (int)st.status);
+}
 
 struct Flight {
   bool busy = false;
@@ -99,6 +140,8 @@ struct hr_server {
   int busy_slots = 0;
   double busy_since = 0.0;
   uint64_t launched = 0;   // queries sent to the device in batches
+  uint64_t batch_seq = 0;  // batches launched so far
+  FILE* metrics = nullptr; // JSON Lines of completed queries (opts.metrics_path)
 
   void finish_flight(int i, hr_status status) {
     Flight& f = flights[i];
@@ -110,7 +153,9 @@ struct hr_server {
       t->stats.status = status;
       completed.push_back(t->id);
       scene_release(t->item.plan.sc);
+      if (metrics) write_metrics(metrics, *t);
     }
+    if (metrics) std::fflush(metrics);
     st.completed += f.tickets.size();
     f.items.clear();
     f.tickets.clear();
@@ -140,16 +185,20 @@ struct hr_server {
     }
     if (f.items.empty()) return;
     const double now = ms_since(t0);
+    ++batch_seq;
     for (Ticket* t : f.tickets) {
       t->state = 1;
       t->stats.start_ms = now;
       t->stats.batch_size = (int)f.tickets.size();
+      t->batch = batch_seq;
+      t->slot = i;
     }
     f.busy = true;
     if (busy_slots++ == 0) busy_since = now;
     st.batches += 1;
     launched += f.items.size();
     lk.unlock();
+    TraceRange range("hr_server batch");
     hr_status s = HR_OK;
     if (opts.autotune) s = autotune_raster(slots[i], f.items);
     if (!s) s = slots[i].build(f.items);
@@ -198,6 +247,7 @@ void hr_server_opts_default(hr_server_opts* o) {
   o->memory_bytes = 0;
   o->use_graph = 1;
   o->autotune = 0;
+  o->metrics_path = nullptr;
 }
 
 hr_status hr_server_create(hr_ctx* ctx, const hr_server_opts* opts, hr_server** out) {
@@ -227,6 +277,14 @@ hr_status hr_server_create(hr_ctx* ctx, const hr_server_opts* opts, hr_server** 
       return st;
     }
   }
+  if (o.metrics_path && o.metrics_path[0]) {
+    s->metrics = std::fopen(o.metrics_path, "a");
+    if (!s->metrics) {
+      for (auto& x : s->slots) x.release();
+      return fail(HR_EINVAL, std::string("cannot open metrics file ") + o.metrics_path);
+    }
+  }
+  s->opts.metrics_path = nullptr;   // the caller's string is not kept
   s->t0 = std::chrono::steady_clock::now();
   hr_server* raw = s.release();
   raw->worker = std::thread([raw] { raw->run(); });
@@ -243,6 +301,7 @@ void hr_server_destroy(hr_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (auto& sl : s->slots) sl.release();
+  if (s->metrics) std::fclose(s->metrics);
   delete s;
 }
 
@@ -280,6 +339,10 @@ hr_status hr_submit(hr_server* s, const hr_query* q, uint64_t* ticket) {
   if (raw->item.zero) {   // Hv = 0: done without device work
     raw->state = 2;
     raw->stats.start_ms = raw->stats.end_ms = raw->stats.submit_ms;
+    if (s->metrics) {
+      write_metrics(s->metrics, *raw);
+      std::fflush(s->metrics);
+    }
     s->completed.push_back(raw->id);
     s->st.completed += 1;
     s->cv_done.notify_all();

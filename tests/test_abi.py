@@ -42,6 +42,20 @@ def test_library_is_gfx950_code_object():
     assert "gfx950" in out.stdout
 
 
+def test_library_links_roctx_for_marker_ranges():
+    """The host-side calls carry roctx ranges (rocprofv3 --marker-trace): the
+    library links the roctx library and exports nothing of it."""
+    import shutil
+    import subprocess
+    if shutil.which("readelf") is None:
+        pytest.skip("readelf not installed")
+    out = subprocess.run(["readelf", "-d", LIB], check=True, capture_output=True, text=True).stdout
+    assert "librocprofiler-sdk-roctx" in out
+    syms = subprocess.run(["readelf", "--dyn-syms", "-W", LIB], check=True, capture_output=True,
+                          text=True).stdout
+    assert "roctxRangePushA" in syms   # imported (undefined here), resolved at load time
+
+
 def test_oracle_and_product_share_no_code():
     pkg = os.path.join(ROOT, "paper_2412_03489_amd")
     for dirpath, _, files in os.walk(pkg):

@@ -265,6 +265,46 @@ def test_server_results_alone_and_in_the_mix(P, ctx, scenes):
     srv.close()
 
 
+def test_server_writes_query_metrics_as_json_lines(P, ctx, scenes, tmp_path):
+    """With metrics_path set, the server appends one JSON object per completed
+    query: the query's identity, the batch and slot it ran in, and its times,
+    consistent with what hr_wait reports."""
+    import json
+    qs = [q for q in mixed_queries(scenes)]
+    path = str(tmp_path / "queries.jsonl")
+    srv = P.Server(ctx, slots=2, max_batch=4, memory_bytes=1 << 30, metrics_path=path)
+    tickets = {}
+    for q in qs:
+        q = dict(q)
+        kind = q.pop("kind")
+        t = srv.submit(q.pop("scene"), kind, q.pop("theta"), q.pop("sigma"), q.pop("N"),
+                       q.pop("seed"), v=q.pop("v", None), **q)
+        tickets[t] = kind
+    stats = {t: srv.wait(t)[1] for t in tickets}
+    srv.close()
+    say(f"server metrics: {len(tickets)} queries")
+    rows = [json.loads(ln) for ln in open(path).read().splitlines()]
+    assert sorted(r["ticket"] for r in rows) == sorted(tickets)
+    per_batch = {}
+    for r in rows:
+        st = stats[r["ticket"]]
+        assert r["kind"] == tickets[r["ticket"]]
+        assert r["status"] == 0 and st["status"] == 0
+        assert r["batch_size"] == st["batch_size"]
+        assert abs(r["submit_ms"] - st["submit_ms"]) < 1e-3
+        assert abs(r["end_ms"] - st["end_ms"]) < 1e-3
+        assert r["submit_ms"] <= r["start_ms"] <= r["end_ms"]
+        assert r["queue_ms"] >= 0 and r["service_ms"] >= 0
+        if r["batch"]:
+            per_batch.setdefault(r["batch"], []).append(r)
+    for b, rs in per_batch.items():   # a batch's queries name it and its size
+        assert all(r["batch_size"] == len(rs) for r in rs), b
+        assert len({r["slot"] for r in rs}) == 1
+    # a file that cannot be opened is refused
+    with pytest.raises(P.HrError):
+        P.Server(ctx, metrics_path=str(tmp_path / "no_such_dir" / "m.jsonl"))
+
+
 def test_server_admission_by_memory(P, ctx, scenes):
     w, sc = scenes["ragged"]
     srv = P.Server(ctx, slots=2, max_batch=64, memory_bytes=64 << 20)

@@ -67,7 +67,7 @@ def test_host_library_under_asan_ubsan(tmp_path):
          "-I", os.path.join(ROOT, "include"), "-c", os.path.join(TESTS, "sanitize_host.c"),
          "-o", drv])
     exe = str(tmp_path / "sanitize_host")
-    run([clang, "-fsanitize=address,undefined", "-o", exe, drv, *objs, "-L/opt/rocm/lib",
-         "-Wl,-rpath,/opt/rocm/lib", "-lamdhip64", "-lpthread"])
+    run([clang, "-fsanitize=address,undefined", "-o", exe, drv, *objs, *B.LIBS, "-lamdhip64",
+         "-lpthread"])
     r = run([exe], env=SAN_ENV, timeout=300)
     assert "sanitize host driver ok" in r.stdout
