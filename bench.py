@@ -38,12 +38,17 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X fp32 vector (published)
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E (published)
 # path tracer, FP32 arithmetic per path of one render (FMA = 2 FLOP): the
 # FMA/ADD/MUL instruction counters of the Hessian launch per path at full
-# lanes.  A path that takes every branch (two closest-hit searches over 4
-# spheres, plane and light, two light samples with shadow tests, frames,
-# bounce, throughput) is ~550 by hand; rays that leave the scene and shadow
-# tests that stop at their first blocker make the average path cheaper.
-# Square roots, reciprocals and sines (one instruction each) are not counted.
+# lanes when every render traced its camera ray alone (the kernel now finds a
+# draw's shared camera-ray hits once, and executes 401 per path).  A path
+# that takes every branch (two closest-hit searches over 4 spheres, plane and
+# light, two light samples with shadow tests, frames, bounce, throughput) is
+# ~550 by hand; rays that leave the scene and shadow tests that stop at their
+# first blocker make the average path cheaper.  Square roots, reciprocals and
+# sines (one instruction each) are not counted.
 PT_FLOP_PER_PATH = 434.0
+# the a-priori count of a path (4 rays x (4 spheres at ~17 FLOP + plane +
+# light quad) + shading), reported beside the counter figure
+PT_FLOP_PER_PATH_ESTIMATE = 520.0
 # algorithmic work per perturbed pixel of the bbox-culled rasteriser + loss:
 # 9 FLOP for the 3-channel squared error, 5 FLOP per disk test times the
 # 0.593 disks whose bounding box holds an average pixel (32 disks, E[r^2]).
@@ -518,13 +523,17 @@ def configs_section(P, ctx, reps):
     renders = P.n_renders("hess", wp.n, wp.N)
     paths = renders * wp.pixels * wp.spp
     tflops = PT_FLOP_PER_PATH * paths / dt / 1e12
+    tflops_est = PT_FLOP_PER_PATH_ESTIMATE * paths / dt / 1e12
     out["pt_spheres_hessian"] = {"ms": round(dt * 1e3, 3), "renders": renders,
                                  "Mpix_per_s": round(renders * wp.pixels / dt / 1e6, 1),
                                  "Mpaths_per_s": round(paths / dt / 1e6, 1),
                                  "roofline": {"bound": "alu", "flop_per_path": PT_FLOP_PER_PATH,
                                               "achieved": round(tflops, 3),
                                               "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                                              "frac": round(tflops / PEAK_FP32_TFLOPS, 4)}}
+                                              "frac": round(tflops / PEAK_FP32_TFLOPS, 4),
+                                              "flop_per_path_estimate": PT_FLOP_PER_PATH_ESTIMATE,
+                                              "achieved_at_estimate": round(tflops_est, 3),
+                                              "frac_at_estimate": round(tflops_est / PEAK_FP32_TFLOPS, 4)}}
     sp.close()
     return out
 

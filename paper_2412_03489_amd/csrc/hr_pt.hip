@@ -98,6 +98,56 @@ __device__ int intersect(const Consts& P, const Placement& pl, V3 o, V3 d, float
   return id;
 }
 
+// The part of a camera ray's closest hit that every render of a draw shares:
+// spheres 1.. and the plane (the renders differ only in sphere 0 and the
+// light).  Scanned in the same order and with the same strict comparisons as
+// intersect(), so that camera_hit() below returns exactly what intersect()
+// would.
+struct CamHit {
+  float t;
+  int id;
+};
+
+template <class Consts>
+__device__ __forceinline__ CamHit camera_common(const Consts& P, V3 o, V3 d) {
+  int id = -1;
+  float best = 3.0e38f;
+  for (int i = 1; i < P.ns; ++i) {
+    const float t = hit_sphere(o, d, v3(P.sph[i][0], P.sph[i][1], P.sph[i][2]), P.sph[i][3]);
+    if (t > 0.0f && t < best) { best = t; id = i; }
+  }
+  if (d.y != 0.0f) {
+    const float t = -o.y * rcp_f(d.y);
+    if (t > kTmin && t < best) { best = t; id = P.ns; }
+  }
+  return {best, id};
+}
+
+// intersect() of a camera ray from the shared part: sphere 0 is scanned first
+// there, so it keeps a tie (a later candidate must be strictly closer); the
+// light is tested last with a strict comparison, as there.
+template <class Consts>
+__device__ __forceinline__ int camera_hit(const Consts& P, const Placement& pl, V3 o, V3 d,
+                                          CamHit c, float& tb) {
+  int id = c.id;
+  float best = c.t;
+  if (P.ns > 0) {
+    const float t0 = hit_sphere(o, d, pl.s0, P.sph[0][3]);
+    if (t0 > 0.0f && t0 <= best) { best = t0; id = 0; }
+  }
+  if (d.y != 0.0f) {
+    const float idy = rcp_f(d.y);
+    const float tl = (pl.light.y - o.y) * idy;
+    if (tl > kTmin && tl < best) {
+      const V3 p = o + d * tl;
+      const float half = 0.5f * P.side;
+      if (fabsf(p.x - pl.light.x) <= half && fabsf(p.z - pl.light.z) <= half) { best = tl; id = P.ns + 1; }
+    }
+  }
+  tb = best;
+  return id;
+}
+
 template <class Consts>
 __device__ bool occluded(const Consts& P, const Placement& pl, V3 o, V3 d, float dist) {
   // every blocker is tested (no per-lane early exit: the wave would run on
@@ -142,12 +192,12 @@ __device__ __forceinline__ void surface(const Consts& P, const Placement& pl, in
   }
 }
 
-// radiance of one path; u[0..1] jitter (used by the caller), u[2..3] light
-// sample at hit 1, u[4..5] bounce, u[6..7] light sample at hit 2
+// radiance of one path whose camera ray from `eye` along d first hits `id` at
+// distance t; u[0..1] jitter (used by the caller), u[2..3] light sample at
+// hit 1, u[4..5] bounce, u[6..7] light sample at hit 2
 template <class Consts>
-__device__ V3 radiance(const Consts& P, const Placement& pl, V3 eye, V3 d, const float* u) {
-  float t;
-  const int id = intersect(P, pl, eye, d, t);
+__device__ V3 radiance_from(const Consts& P, const Placement& pl, V3 eye, V3 d, int id, float t,
+                            const float* u) {
   if (id < 0) return v3(0.f, 0.f, 0.f);
   if (id == P.ns + 1) return d.y > 0.0f ? v3(P.Le, P.Le, P.Le) : v3(0.f, 0.f, 0.f);
   const V3 x = eye + d * t;
@@ -176,6 +226,13 @@ __device__ V3 radiance(const Consts& P, const Placement& pl, V3 eye, V3 d, const
   const float e2 = nee(P, pl, o2, n2, u[6], u[7]);
   L = L + v3(alb.x * alb2.x, alb.y * alb2.y, alb.z * alb2.z) * e2;
   return L;
+}
+
+template <class Consts>
+__device__ V3 radiance(const Consts& P, const Placement& pl, V3 eye, V3 d, const float* u) {
+  float t;
+  const int id = intersect(P, pl, eye, d, t);
+  return radiance_from(P, pl, eye, d, id, t, u);
 }
 
 __device__ __forceinline__ void path_uniforms(uint64_t seed, uint32_t s, uint32_t pix, int k,
@@ -252,9 +309,13 @@ __device__ __forceinline__ void pt_block(const Consts& P, const double* __restri
         float uu[8];
         path_uniforms(e.seed, s, pix, k, uu);
         const V3 d = camera_dir(P, x, y, uu[0], uu[1]);
+        // the camera ray's hits on what the renders share, found once
+        const CamHit ch = camera_common(P, eye, d);
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-          const V3 L = radiance(P, pl[rr], eye, d, uu);
+          float t;
+          const int id = camera_hit(P, pl[rr], eye, d, ch, t);
+          const V3 L = radiance_from(P, pl[rr], eye, d, id, t, uu);
           acc[rr][0] += L.x; acc[rr][1] += L.y; acc[rr][2] += L.z;
         }
       }
