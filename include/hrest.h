@@ -366,10 +366,15 @@ typedef struct {
   int autotune;             /* 1: before a batch, time samples-per-block
                                (32-256) and block shape (the three) for
                                every not yet tuned class of disk scene
-                               (channels, disk count, image size buckets) and
-                               keep the fastest in the context; 0 (default):
-                               the library's choices (samples_per_block and
-                               raster_tile 0)                                   */
+                               (channels, disk count, image size buckets),
+                               and draws per block item (2-32) for every not
+                               yet tuned class of path-traced query (renders
+                               per draw, samples per pixel, sphere count,
+                               image size buckets), and keep the fastest in
+                               the context; 0 (default): the library's
+                               choices (samples_per_block and raster_tile 0;
+                               8 draws per path-traced item).  A query's own
+                               samples_per_block still comes first.            */
 } hr_batch_opts;
 
 typedef struct {
@@ -397,7 +402,10 @@ void hr_batch_destroy(hr_batch* b);
  * memory budget; no query is run then. */
 hr_status hr_batch_run(hr_batch* b, const hr_query* queries, int count);
 hr_status hr_batch_report_get(const hr_batch* b, hr_batch_report* out);
-/* The autotuner's choice for the scene's class (0, 0 if not tuned yet). */
+/* The autotuner's choice for the scene's class (0, 0 if not tuned yet).  For
+ * a path-traced scene: the draws per block item tuned for its queries with two
+ * renders per draw (gradients and Hessians with antithetic pairs), and 0 as
+ * raster_tile. */
 hr_status hr_batch_tuned(hr_ctx* ctx, const hr_scene* sc, int* samples_per_block,
                          int* raster_tile);
 

@@ -34,11 +34,34 @@ namespace {
 constexpr int kPhaseBlocksPerCU = 8;
 constexpr int kDefaultPtSamples = 8;
 
+uint64_t lg2(int v) {
+  uint64_t b = 0;
+  while ((1 << (b + 1)) <= v) ++b;
+  return b;
+}
+
 // class of a raster query for the autotuner: channels, disk-count bucket,
 // image-size buckets
 uint64_t tune_key(const hr_scene* sc) {
-  auto lg = [](int v) { int b = 0; while ((1 << (b + 1)) <= v) ++b; return (uint64_t)b; };
-  return ((uint64_t)sc->C << 24) | (lg(sc->D) << 16) | (lg(sc->W) << 8) | lg(sc->H);
+  return ((uint64_t)sc->C << 24) | (lg2(sc->D) << 16) | (lg2(sc->W) << 8) | lg2(sc->H);
+}
+
+// class of a path-traced query: renders per draw, samples per pixel, sphere
+// count, image-size buckets (bit 40 keeps it apart from the raster classes)
+uint64_t pt_tune_key(const hr_scene* sc, int nr) {
+  return (1ull << 40) | ((uint64_t)nr << 32) | ((uint64_t)sc->spp << 24) |
+         ((uint64_t)sc->nspheres << 16) | (lg2(sc->W) << 8) | lg2(sc->H);
+}
+
+// draws per block item of a path-traced query: the explicit option, then the
+// autotuner's choice for its class, then the default
+int pt_samples(hr_ctx* ctx, const QueryPlan& p) {
+  const hr_scene* sc = p.sc;
+  if (p.o.samples_per_block > 0 && p.o.samples_per_block <= pt_max_samples())
+    return p.o.samples_per_block;
+  std::lock_guard<std::mutex> lk(ctx->tuned_mu);
+  auto it = ctx->tuned.find(pt_tune_key(sc, p.e.A * p.e.NH));
+  return it != ctx->tuned.end() ? it->second.first : kDefaultPtSamples;
 }
 
 }  // namespace
@@ -170,8 +193,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
         lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
       }
     } else if (sc->kind == kPT) {
-      qS[q] = p.o.samples_per_block > 0 && p.o.samples_per_block <= pt_max_samples()
-                  ? p.o.samples_per_block : kDefaultPtSamples;
+      qS[q] = pt_samples(ctx, p);
       cost[q] = (double)qS[q] * p.e.A * p.e.NH * sc->spp;
     }
   }
@@ -457,11 +479,17 @@ void BatchSlot::scatter(const std::vector<BatchItem>& items) const {
 hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) {
   hr_ctx* ctx = slot.ctx;
   // classes present and not yet tuned
-  std::map<uint64_t, std::vector<int>> classes;
+  std::map<uint64_t, std::vector<int>> classes, pt_classes;
   {
     std::lock_guard<std::mutex> lk(ctx->tuned_mu);
     for (int i = 0; i < (int)items.size(); ++i) {
-      const hr_scene* sc = items[i].plan.sc;
+      const QueryPlan& p = items[i].plan;
+      const hr_scene* sc = p.sc;
+      if (sc->kind == kPT) {
+        const uint64_t key = pt_tune_key(sc, p.e.A * p.e.NH);
+        if (!ctx->tuned.count(key)) pt_classes[key].push_back(i);
+        continue;
+      }
       if (sc->kind != kDisks) continue;
       if (ctx->tuned.count(tune_key(sc))) continue;
       classes[tune_key(sc)].push_back(i);
@@ -523,6 +551,49 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
     if (st) break;
     std::lock_guard<std::mutex> lk(ctx->tuned_mu);
     ctx->tuned[kv.first] = pick;
+  }
+  // path-traced classes: draws per block item, timed on the persistent path
+  // tracer of the class's renders per draw
+  const int pSs[] = {2, 4, 8, 16, 32};
+  for (auto& kv : pt_classes) {
+    if (st) break;
+    std::vector<BatchItem> sub;
+    for (int i : kv.second) {
+      BatchItem it = items[i];
+      it.out = nullptr;
+      sub.push_back(it);
+    }
+    const int nr = sub[0].plan.e.A * sub[0].plan.e.NH;
+    const int c = nr == 1 ? 0 : (nr == 2 ? 1 : 2);
+    double best = 1e300;
+    int pick = kDefaultPtSamples;
+    for (int S : pSs) {
+      for (auto& it : sub) it.plan.o.samples_per_block = S;
+      st = slot.build(sub);
+      if (st) break;
+      st = slot.enqueue(false, false);   // draws prepared, never timed into the stats
+      if (st) break;
+      const BatchTable* T = (const BatchTable*)slot.dev;
+      float best_ms = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        launch_batch_sample(slot.stream, T, slot.phase_blocks);   // counters back to zero
+        if (hipEventRecord(a, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }
+        launch_batch_pt(slot.stream, T, nr, slot.pt_blocks[c]);
+        if (hipEventRecord(b, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }
+        if (hipEventSynchronize(b) != hipSuccess) { st = fail(HR_EDEVICE, "event sync"); break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        best_ms = std::min(best_ms, ms);
+      }
+      if (st) break;
+      if (best_ms < best) {
+        best = best_ms;
+        pick = S;
+      }
+    }
+    if (st) break;
+    std::lock_guard<std::mutex> lk(ctx->tuned_mu);
+    ctx->tuned[kv.first] = {pick, 0};
   }
   (void)hipStreamSynchronize(slot.stream);
   (void)hipEventDestroy(a);
@@ -668,7 +739,7 @@ hr_status hr_batch_report_get(const hr_batch* b, hr_batch_report* out) {
 hr_status hr_batch_tuned(hr_ctx* ctx, const hr_scene* sc, int* samples_per_block, int* raster_tile) {
   if (!ctx || !sc || !samples_per_block || !raster_tile) return fail(HR_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(ctx->tuned_mu);
-  auto it = ctx->tuned.find(tune_key(sc));
+  auto it = ctx->tuned.find(sc->kind == kPT ? pt_tune_key(sc, 2) : tune_key(sc));
   if (it == ctx->tuned.end()) {
     *samples_per_block = 0;
     *raster_tile = 0;

@@ -214,6 +214,21 @@ def test_autotuner_keeps_results(P, ctx, scenes):
     assert np.array_equal(got[0], base)
 
 
+def test_autotuner_tunes_path_traced_queries(P, ctx, scenes):
+    """Draws per block item of a path-traced class are timed over 2..32 and
+    kept; the result bits do not depend on them."""
+    wp, sp = scenes["pt"]
+    q = dict(scene=sp, kind="hess", theta=wp.theta0, sigma=wp.sigma, N=40, seed=11)
+    base = P.Batch(ctx).run([q])[0]
+    say("autotune path-traced Hessian")
+    got = P.Batch(ctx, autotune=True).run([q, dict(q, seed=12)])
+    S, tile = P.tuned(ctx, sp)
+    assert S in (2, 4, 8, 16, 32) and tile == 0
+    assert np.array_equal(got[0], base)
+    for s in (2, 32):   # any explicit value gives the same bits
+        assert np.array_equal(P.Batch(ctx).run([dict(q, samples_per_block=s)])[0], base)
+
+
 def test_batch_errors(P, ctx, scenes):
     w, sc = scenes["ragged"]
     b = P.Batch(ctx)
