@@ -189,8 +189,10 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
                                  : 0;
   p->b_tau = align256(e.streams * N * (uint64_t)e.n * 8);
   p->b_u = align256((size_t)e.n * 8 + 8);
-  p->b_rec = sc->kind == kDisks ? align256(e.L * (uint64_t)sc->D * 16) : 0;
-  p->b_part = p->stride ? align256(part_floats(e.L, (uint64_t)p->stride) * 4) : 0;
+  // render pairs build their records in the kernel and write their loss
+  // differences directly: no records, no partials
+  p->b_rec = sc->kind == kDisks && !e.pair ? align256(e.R * (uint64_t)sc->D * 16) : 0;
+  p->b_part = p->stride && !e.pair ? align256(part_floats(e.R, (uint64_t)p->stride) * 4) : 0;
   p->b_f = align256(e.L * 8);
   p->b_Fq = align256(e.streams * N * 8);
   p->b_vt = align256(N * 8);
@@ -247,21 +249,19 @@ void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBu
   if (sc->kind == kDisks) {
     DiskScene ds{sc->W, sc->H, sc->C, sc->D, sc->ppd, sc->target, sc->colors, sc->radius};
     RasterExact ex{d_theta, tau, u, sc->radius, e.n, sc->ppd, e.A, e.NH, e.h};
+    const double scale = 1.0 / ((double)sc->W * sc->H * sc->C);
     if (e.pair) {
-      T("records", [&] { launch_pair_records(s, e, ds, d_theta, tau, u, rec); });
-      T("raster_dloss", [&] {
-        launch_raster_dloss(s, ds, rec, e.L, spb > 0 ? spb / 2 : 0, shape, ex, partial, e.skip);
-      });
+      const PairQuery pq{d_theta, tau, u, sc->radius, sc->colors, sc->target, f,
+                         sc->W, sc->H, sc->C, sc->D, sc->ppd, e.n, e.A, 0,
+                         e.h, scale, e.L, e.skip};
+      T("raster_dloss", [&] { launch_raster_dloss(s, pq); });
     } else {
       T("records", [&] { launch_records(s, e, ds, d_theta, tau, u, rec); });
       T("raster_loss", [&] {
         launch_raster_loss(s, ds, rec, e.R, spb, shape, ex, partial, e.skip);
       });
+      T("tile_reduce", [&] { launch_tile_reduce(s, partial, e.R, tiles, scale, f, e.skip); });
     }
-    T("tile_reduce", [&] {
-      launch_tile_reduce(s, partial, e.L, tiles, 1.0 / ((double)sc->W * sc->H * sc->C), f,
-                         e.skip);
-    });
   } else if (sc->kind == kPT) {
     PTScene ps{sc->W, sc->H, sc->spp, sc->nspheres, sc->target, sc->pt_desc.data(), sc->ptc};
     T("pt_loss", [&] { launch_pt_loss(s, e, ps, d_theta, tau, u, spb, partial); });

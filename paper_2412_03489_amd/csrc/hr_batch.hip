@@ -186,8 +186,9 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       raster_config(ctx, sc, p.o, p.e.R, &qS[q], &qshape[q]);
       cost[q] = (double)qS[q] * (double)(sc->D + 16);
       if (p.e.pair) {
-        // pairs per block: half the renders, whole flush groups of 16
-        qS[q] = std::max(16, (qS[q] / 2 / 16) * 16);
+        // pairs per block item: half the renders (the block's four waves
+        // take one pair each at a time)
+        qS[q] = std::max(4, qS[q] / 2);
         lds = std::max(lds, raster_pair_lds_bytes(sc->D));
       } else {
         lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
@@ -225,7 +226,8 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       a.W = sc->W; a.H = sc->H; a.C = sc->C; a.D = sc->D; a.S = qS[q];
       raster_geometry(a, qshape[q]);
       const int cls = p.e.pair ? raster_pair_class(sc->C) : raster_class(sc->C, sc->D);
-      add_segments(rq[cls], rchunks[cls], q, (p.e.L + qS[q] - 1) / qS[q], a.tiles);
+      // a pair item covers the whole image
+      add_segments(rq[cls], rchunks[cls], q, (p.e.L + qS[q] - 1) / qS[q], p.e.pair ? 1 : a.tiles);
     } else if (sc->kind == kPT) {
       const uint64_t draws = p.e.streams * p.e.N;
       const int nr = p.e.A * p.e.NH;

@@ -1,0 +1,444 @@
+// hr_edges.hip -- the HVP's render pairs on disk scenes: loss differences
+// summed along the disks' edges.
+//
+// The central difference of the HVP (section "Hessian-vector product") needs,
+// per draw s and antithetic sign a, only f(theta + h u - a tau_s) -
+// f(theta - h u - a tau_s).  The two scenes of such a pair differ by the
+// shift 2 h u: with e = h (|u_xy| + |u_r|), the most a shift moves a disk's
+// edge, a pixel at distance d from the midpoint disk's centre (theta - a
+// tau_s) is covered by both shifted disks when d < r - e and by neither when
+// d >= r + e.  Each disk's record carries the squared outer and inner radii
+// (r + e)^2 and (r - e)^2, widened and narrowed by the FP32 error band, so
+// that the FP32 tests d^2 < outer ("maybe") and d^2 < inner ("sure") decide
+// those cases exactly.  A pixel contributes to the difference only if the
+// top disk that may cover it lies above the top disk that surely covers it,
+// and then that top "maybe" disk is not sure there: the pixel lies in that
+// disk's ring inner <= d^2 < outer, and no disk above it may cover it.  So
+// instead of visiting every pixel, a wave walks, for one pair, the rows of
+// every disk's ring and tests only the pixel centres the ring can hold
+// (about 2e wide: a few hundred pixels per pair where the image has 65536);
+// a ring pixel whose disk is the top "maybe" one is decided exactly in FP64
+// from theta, tau and u -- the definition's own arithmetic -- under both
+// shifts, and contributes (I+ - T)^2 - (I- - T)^2 summed over the channels.
+// Every other pixel has the same top disk under both shifts and contributes
+// nothing.  The decisions are those of rendering both scenes pixel by pixel
+// with exact coverage.
+//
+// Work decomposition: one wave per pair.  Lane k builds disk k's record and
+// its FP64 parameters under both shifts in LDS, the disks whose outer boxes
+// meet its own (the only ones that can cover a pixel of its ring), and its
+// ring's rows; the waves then take (disk, row) items 64 at a time, test the
+// few pixel centres of each row's ring spans one step at a time, and queue
+// the ring pixels in LDS; 64 queued pixels are decided at a time, one per
+// lane.  Each lane sums its pixels' contributions in FP32 in queue order and
+// the wave adds the 64 sums in FP64 in a fixed order, so the result does not
+// depend on the launch shape or on the batch a query runs in.
+#include "hr_device.h"
+#include "hr_kernels.h"
+
+namespace hr {
+
+namespace {
+
+constexpr int kEdgeDisks = 64;    // disks of a scene on this path: one per lane
+constexpr int kEdgeQueue = 128;   // queued ring pixels: fewer than 64 + one step's 64
+// Absolute slack, in image units, on every bound derived from a record (row
+// ranges, ring spans, box overlaps): far above the FP32 rounding of the bound
+// computations, far below a pixel.
+constexpr float kEdgeEps = 2e-5f;
+
+// One wave's share of LDS
+struct EdgeWave {
+  float4 rec[kEdgeDisks];             // midpoint disk: cx, cy, outer^2, inner^2 (-1: none)
+  double pp[kEdgeDisks][3];           // the disk under +h: theta + h u - a tau_s
+  double pm[kEdgeDisks][3];           // and under -h (cx, cy[, r])
+  unsigned long long nbr[kEdgeDisks]; // disks whose outer boxes meet this disk's
+  float rad[kEdgeDisks];              // outer radius (-1: none)
+  int y0[kEdgeDisks];                 // first row of the disk's ring
+  int off[kEdgeDisks + 1];            // its first (disk, row) item; off[D] = all items
+  uint32_t q_xy[kEdgeQueue];          // queued ring pixel: x | y << 16
+  uint32_t q_k[kEdgeQueue];           // and the disk whose ring holds it
+};
+
+// Disk k of pair p: its midpoint record and its FP64 parameters under both
+// shifts, with the arithmetic of the per-render records and of the exact
+// coverage test.
+__device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k, EdgeWave& L) {
+  const int ppd = a.ppd;
+  const int ai = a.A == 2 ? (int)(p & 1u) : 0;
+  const uint64_t sidx = a.A == 2 ? p >> 1 : p;
+  const double* t = a.tau + sidx * (uint64_t)a.n;
+  const double sa = ai == 0 ? 1.0 : -1.0;
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < ppd; ++q) {
+    const int j = k * ppd + q;
+    const double th = a.theta[j], uj = a.u[j], tj = t[j];
+    m[q] = th - sa * tj;
+    L.pp[k][q] = (th + a.h * uj) - sa * tj;
+    L.pm[k][q] = (th + (-a.h) * uj) - sa * tj;
+  }
+  const double rad = ppd == 3 ? m[2] : (double)a.radius[k];
+  const double ux = a.u[k * ppd], uy = a.u[k * ppd + 1], ur = ppd == 3 ? a.u[k * ppd + 2] : 0.0;
+  const double e = a.h * (sqrt(ux * ux + uy * uy) + fabs(ur));
+  const double rp = rad + e, rm = rad - e;
+  float4 out = make_float4((float)m[0], (float)m[1], -1.0f, -1.0f);
+  if (rp > 0.0) {
+    // the band at the larger radius also covers the smaller one
+    const double band = ambiguity_band(m[0], m[1], rp);
+    out.z = (float)((rp * rp + band) * 1.00001);
+    if (rm > 0.0) out.w = (float)(rm * rm - band);
+  }
+  L.rec[k] = out;
+  L.rad[k] = out.z > 0.0f ? sqrtf(out.z) : -1.0f;
+}
+
+// One ring pixel of disk k: the top disk under each shift, and the pixel's
+// (I+ - T)^2 - (I- - T)^2 over the channels (0 if the pixel belongs to the
+// ring of a disk above k, which counts it instead).
+template <int C>
+__device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave& L,
+                                            const float4* s_col, int x, int y, int k) {
+  const float pxf = ((float)x + 0.5f) / (float)a.W;
+  const float pyf = ((float)y + 0.5f) / (float)a.H;
+  const unsigned long long nb = L.nbr[k];
+  // a disk above k that may cover the pixel: the pixel is in that disk's ring
+  // or inside it, and is counted there (or contributes nothing)
+  unsigned long long up = k < 63 ? nb & (~0ull << (k + 1)) : 0ull;
+  while (up) {
+    const int j = __builtin_ctzll(up);
+    up &= up - 1;
+    const float4 v = L.rec[j];
+    const float dx = pxf - v.x, dy = pyf - v.y;
+    if (fmaf(dy, dy, dx * dx) < v.z) return 0.0f;
+  }
+  // the top disk below k that surely covers the pixel (-1: the background)
+  const unsigned long long below = nb & ((1ull << k) - 1ull);
+  unsigned long long dn = below;
+  int ks = -1;
+  while (dn) {
+    const int j = 63 - __builtin_clzll(dn);
+    dn &= ~(1ull << j);
+    const float4 v = L.rec[j];
+    const float dx = pxf - v.x, dy = pyf - v.y;
+    if (fmaf(dy, dy, dx * dx) < v.w) { ks = j; break; }
+  }
+  // exact decisions, from k down: k first (it may cover the pixel), then the
+  // disks between ks and k that may (their FP32 test against the outer
+  // radius rules out the others for both shifts)
+  const double pxd = ((double)x + 0.5) / (double)a.W;
+  const double pyd = ((double)y + 0.5) / (double)a.H;
+  int top_p = ks, top_m = ks;
+  bool done_p = false, done_m = false;
+  auto exact = [&](int j) {
+    const double rp = a.ppd == 3 ? L.pp[j][2] : (double)a.radius[j];
+    const double rm = a.ppd == 3 ? L.pm[j][2] : (double)a.radius[j];
+    const double dxp = pxd - L.pp[j][0], dyp = pyd - L.pp[j][1];
+    const double dxm = pxd - L.pm[j][0], dym = pyd - L.pm[j][1];
+    if (!done_p && rp > 0.0 && dxp * dxp + dyp * dyp < rp * rp) { top_p = j; done_p = true; }
+    if (!done_m && rm > 0.0 && dxm * dxm + dym * dym < rm * rm) { top_m = j; done_m = true; }
+  };
+  exact(k);
+  unsigned long long cand = ks < 0 ? below : below & ~((2ull << ks) - 1ull);
+  while (cand != 0ull && !(done_p && done_m)) {
+    const int j = 63 - __builtin_clzll(cand);
+    cand &= ~(1ull << j);
+    const float4 v = L.rec[j];
+    const float dx = pxf - v.x, dy = pyf - v.y;
+    if (!(fmaf(dy, dy, dx * dx) < v.z)) continue;   // neither shift covers
+    exact(j);
+  }
+  if (top_p == top_m) return 0.0f;
+  // colours: entry k + 1 is disk k, entry 0 the background
+  const float4 cp = s_col[top_p + 1], cm = s_col[top_m + 1];
+  const float ap[4] = {cp.x, cp.y, cp.z, cp.w}, am[4] = {cm.x, cm.y, cm.z, cm.w};
+  const float* tg = a.target + ((size_t)y * a.W + x) * C;
+  float acc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float t2 = 2.0f * tg[c];
+    // (cp - T)^2 - (cm - T)^2 = (cp - cm)(cp + cm - 2T)
+    acc = fmaf(ap[c] - am[c], (ap[c] + am[c]) - t2, acc);
+  }
+  return acc;
+}
+
+// Pair p by one wave: f[p] = scale * (sum over the pair's pixels of the
+// squared-error difference).
+template <int C>
+__device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWave& L,
+                                          const float4* s_col) {
+  const int lane = threadIdx.x & 63;
+  const int D = a.D, W = a.W, H = a.H;
+  // lane k: disk k's record, parameters, outer radius and ring rows
+  int cnt = 0;
+  if (lane < D) {
+    edge_disk(a, p, lane, L);
+    const float4 v = L.rec[lane];
+    if (v.z > 0.0f) {
+      const float R = L.rad[lane];
+      const int y0 = max(0, (int)floorf((v.y - R - kEdgeEps) * (float)H - 0.5f));
+      const int y1 = min(H - 1, (int)ceilf((v.y + R + kEdgeEps) * (float)H - 0.5f));
+      cnt = max(0, y1 - y0 + 1);
+      L.y0[lane] = y0;
+    } else {
+      L.y0[lane] = 0;
+    }
+  }
+  // first item of each disk (exclusive prefix sum over the lanes)
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane < D) L.off[lane] = incl - cnt;
+  if (lane == D - 1) L.off[D] = incl;
+  const int total = __shfl(incl, 63, 64);
+  __builtin_amdgcn_wave_barrier();
+  // lane k: the disks whose outer boxes meet disk k's
+  if (lane < D) {
+    const float4 vk = L.rec[lane];
+    const float rk = L.rad[lane];
+    unsigned long long m = 0ull;
+    if (rk > 0.0f)
+      for (int j = 0; j < D; ++j) {
+        const float rj = L.rad[j];
+        const float4 vj = L.rec[j];
+        const float reach = rj + rk + 2.0f * kEdgeEps;
+        const bool meet = j != lane && rj > 0.0f && fabsf(vj.x - vk.x) <= reach &&
+                          fabsf(vj.y - vk.y) <= reach;
+        m |= meet ? (1ull << j) : 0ull;
+      }
+    L.nbr[lane] = m;
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  float sum = 0.0f;           // this lane's contributions, in queue order
+  uint32_t qlen = 0;          // wave-uniform queue length
+  auto process = [&](int cnt_q) {
+    float c = 0.0f;
+    if (lane < cnt_q) {
+      const uint32_t xy = L.q_xy[lane];
+      c = edge_pixel<C>(a, L, s_col, (int)(xy & 0xffffu), (int)(xy >> 16), (int)L.q_k[lane]);
+    }
+    sum += c;
+    // the rest of the queue to the front
+    const int rest = (int)qlen - cnt_q;
+    if (lane < rest) {
+      const uint32_t xy = L.q_xy[cnt_q + lane], kk = L.q_k[cnt_q + lane];
+      __builtin_amdgcn_wave_barrier();
+      L.q_xy[lane] = xy;
+      L.q_k[lane] = kk;
+    }
+    qlen -= (uint32_t)cnt_q;
+    __builtin_amdgcn_wave_barrier();
+  };
+
+  int kcur = 0;   // items are in disk order: a lane's disk only moves up
+  for (int base = 0; base < total; base += 64) {
+    const int it = base + lane;
+    int x = 1, xe = 0, xc = 1, xd = 0, y = 0, k = kcur;
+    float4 v = make_float4(0.f, 0.f, -1.f, -1.f);
+    float dy = 0.0f;
+    if (it < total) {
+      while (L.off[k + 1] <= it) ++k;
+      kcur = k;
+      v = L.rec[k];
+      y = L.y0[k] + (it - L.off[k]);
+      const float py = ((float)y + 0.5f) / (float)H;
+      dy = py - v.y;
+      const float dy2 = dy * dy;
+      // |dx| < ro holds for every pixel with d^2 < outer on this row and
+      // |dx| >= ri for every one with d^2 >= inner (slack: the FP32 rounding
+      // of d^2 and of these bounds)
+      const float slack = 0x1p-22f * (dy2 + v.z);
+      const float ro = sqrtf(fmaxf(v.z - dy2 + slack, 0.0f));
+      const float i2 = v.w - dy2 - slack;
+      const float ri = i2 > 0.0f ? sqrtf(i2) : 0.0f;
+      // centres in [cx - ro, cx - ri] and [cx + ri, cx + ro], each widened
+      x = max(0, (int)ceilf((v.x - ro - kEdgeEps) * (float)W - 0.5f));
+      xe = min(W - 1, (int)floorf((v.x - ri + kEdgeEps) * (float)W - 0.5f));
+      xc = max(0, (int)ceilf((v.x + ri - kEdgeEps) * (float)W - 0.5f));
+      xd = min(W - 1, (int)floorf((v.x + ro + kEdgeEps) * (float)W - 0.5f));
+      if (xc <= xe) xc = xe + 1;   // no pixel is tested twice
+      if (x > xe) { x = xc; xe = xd; xc = 1; xd = 0; }
+    }
+    // one pixel per lane per step, the queue drained 64 at a time
+    for (;;) {
+      const bool act = x <= xe;
+      if (__builtin_amdgcn_ballot_w64(act) == 0ull) break;
+      bool ring = false;
+      if (act) {
+        const float px = ((float)x + 0.5f) / (float)W;
+        const float dx = px - v.x;
+        const float d2 = fmaf(dy, dy, dx * dx);
+        ring = d2 < v.z && !(d2 < v.w);
+      }
+      const uint64_t b = __builtin_amdgcn_ballot_w64(ring);
+      if (ring) {
+        const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)b, qlen));
+        L.q_xy[pos] = (uint32_t)x | ((uint32_t)y << 16);
+        L.q_k[pos] = (uint32_t)k;
+      }
+      qlen += (uint32_t)__builtin_popcountll(b);
+      __builtin_amdgcn_wave_barrier();
+      if (qlen >= 64) process(64);
+      if (act) {
+        ++x;
+        if (x > xe) { x = xc; xe = xd; xc = 1; xd = 0; }
+      }
+    }
+  }
+  if (qlen > 0) process((int)qlen);
+  // the 64 lane sums in FP64, in a fixed order
+  double s = (double)sum;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) a.f[p] = s * a.scale;
+  __builtin_amdgcn_wave_barrier();   // LDS of this pair read before the next pair's writes
+}
+
+// the block's colour table: entry 0 the background, entry k + 1 disk k
+__device__ __forceinline__ void edge_colours(const PairQuery& a, float4* s_col) {
+  for (int t = threadIdx.x; t <= a.D; t += blockDim.x) {
+    float cc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (t > 0)
+      for (int c = 0; c < a.C; ++c) cc[c] = a.colors[(size_t)(t - 1) * a.C + c];
+    s_col[t] = make_float4(cc[0], cc[1], cc[2], cc[3]);
+  }
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_raster_dloss(PairQuery a) {
+  extern __shared__ float4 smem[];
+  if (a.skip && *a.skip) return;
+  float4* s_col = smem;
+  EdgeWave* s_w = (EdgeWave*)(smem + kEdgeDisks + 1);
+  edge_colours(a, s_col);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  for (uint64_t p = (uint64_t)blockIdx.x * 4 + wave; p < a.L; p += (uint64_t)gridDim.x * 4)
+    edge_pair<C>(a, p, s_w[wave], s_col);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Persistent form over the eight work queues of one pair class (channel
+// count): an item is (query, chunk of S pairs); blocks start on the queue of
+// their XCD, claim items by one atomic increment each (the next one before
+// working on the current one), move on to the other queues when theirs is
+// empty, and leave after seeing all eight exhausted.
+template <int C>
+__global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restrict__ T) {
+  extern __shared__ float4 smem[];
+  __shared__ unsigned long long s_item;
+  const WorkQueues& W = T->raster[raster_pair_class(C)];
+  const int home = blockIdx.x & 7;
+  uint64_t all = 0;
+  for (int x = 0; x < 8; ++x) all += W.items[x];
+  if (all == 0) return;   // nothing of this kind in the batch
+  float4* s_col = smem;
+  EdgeWave* s_w = (EdgeWave*)(smem + kEdgeDisks + 1);
+  const int wave = threadIdx.x >> 6;
+  for (int kq = 0; kq < 8; ++kq) {
+    const int x = (home + kq) & 7;
+    const uint64_t nitems = W.items[x];
+    const uint64_t sb = W.seg_off[x], se = W.seg_off[x + 1];
+    if (threadIdx.x == 0) s_item = atomicAdd(&W.ctr[x], 1ull);
+    __syncthreads();
+    uint64_t it = uniform64(s_item);
+    __syncthreads();   // every thread has read s_item before it is reused
+    while (it < nitems) {
+      unsigned long long next = 0;
+      if (threadIdx.x == 0) next = atomicAdd(&W.ctr[x], 1ull);
+      uint64_t lo = sb, hi = se - 1;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (uniform64(W.seg[mid].item0) <= it) lo = mid; else hi = mid - 1;
+      }
+      const WorkSeg sg = uniform_copy(&W.seg[lo]);
+      const BatchQuery& Q = T->q[sg.q];
+      PairQuery a;
+      a.theta = (const double*)uniform64((uint64_t)Q.theta);
+      a.tau = (const double*)uniform64((uint64_t)Q.tau);
+      a.u = (const double*)uniform64((uint64_t)Q.u);
+      a.radius = (const float*)uniform64((uint64_t)Q.ds.radius);
+      a.colors = (const float*)uniform64((uint64_t)Q.ds.colors);
+      a.target = (const float*)uniform64((uint64_t)Q.ds.target);
+      a.f = (double*)uniform64((uint64_t)Q.f);
+      a.W = __builtin_amdgcn_readfirstlane(Q.ds.W);
+      a.H = __builtin_amdgcn_readfirstlane(Q.ds.H);
+      a.C = C;
+      a.D = __builtin_amdgcn_readfirstlane(Q.ds.D);
+      a.ppd = __builtin_amdgcn_readfirstlane(Q.ds.ppd);
+      a.n = __builtin_amdgcn_readfirstlane(Q.e.n);
+      a.A = __builtin_amdgcn_readfirstlane(Q.e.A);
+      a.h = Q.e.h;
+      a.scale = Q.inv_count;
+      a.L = uniform64(Q.e.L);
+      a.S = __builtin_amdgcn_readfirstlane(Q.rq.S);
+      a.skip = nullptr;
+      const uint64_t chunk = (uint64_t)sg.c0 + 8u * (it - sg.item0);
+      const uint64_t p0 = chunk * (uint64_t)a.S;
+      const uint64_t p1 = umin64(p0 + (uint64_t)a.S, a.L);
+      __syncthreads();   // the previous item's readers of the colour table are done
+      edge_colours(a, s_col);
+      __syncthreads();
+      for (uint64_t p = p0 + wave; p < p1; p += 4) edge_pair<C>(a, p, s_w[wave], s_col);
+      if (threadIdx.x == 0) s_item = next;
+      __syncthreads();
+      it = uniform64(s_item);
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace
+
+size_t raster_pair_lds_bytes(int) {
+  return (size_t)(kEdgeDisks + 1) * sizeof(float4) + 4 * sizeof(EdgeWave);
+}
+
+int raster_pair_max_disks() { return kEdgeDisks; }
+
+void launch_raster_dloss(hipStream_t st, const PairQuery& a) {
+  const size_t lds = raster_pair_lds_bytes(a.D);
+  // one wave per pair; the grid strides over the rest
+  const uint64_t blocks = umin64((a.L + 3) / 4, 1ull << 20);
+  const dim3 grid((unsigned)(blocks > 0 ? blocks : 1));
+  switch (a.C) {
+    case 1: hipLaunchKernelGGL(k_raster_dloss<1>, grid, dim3(256), lds, st, a); break;
+    case 2: hipLaunchKernelGGL(k_raster_dloss<2>, grid, dim3(256), lds, st, a); break;
+    case 3: hipLaunchKernelGGL(k_raster_dloss<3>, grid, dim3(256), lds, st, a); break;
+    default: hipLaunchKernelGGL(k_raster_dloss<4>, grid, dim3(256), lds, st, a); break;
+  }
+}
+
+typedef void (*BatchDlossKernel)(const BatchTable*);
+static BatchDlossKernel batch_dloss_kernel(int C) {
+  switch (C) {
+    case 1: return k_batch_dloss<1>;
+    case 2: return k_batch_dloss<2>;
+    case 3: return k_batch_dloss<3>;
+    default: return k_batch_dloss<4>;
+  }
+}
+
+void launch_batch_dloss(hipStream_t st, const BatchTable* T, int C, int blocks, size_t lds) {
+  hipLaunchKernelGGL(batch_dloss_kernel(C), dim3(blocks), dim3(256), lds, st, T);
+}
+
+int batch_dloss_blocks_per_cu(int C, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_dloss_kernel(C), 256, lds) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace hr

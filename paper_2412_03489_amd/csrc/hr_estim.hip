@@ -625,12 +625,12 @@ uint64_t batch_tasks(const BatchQuery& q, int phase) {
     case kPhSample:
       return ((e.what == kHvp || e.what == kHvpLimit) ? 1 : 0) +
              ceil_div(e.streams * e.N * (uint64_t)e.n, kBatchElems);
-    case kPhRecords:
-      return q.scene == kDisks ? ceil_div(e.L * (uint64_t)q.ds.D, kBatchElems) : 0;
+    case kPhRecords:   // render pairs build their records in the raster kernel
+      return q.scene == kDisks && !e.pair ? ceil_div(e.R * (uint64_t)q.ds.D, kBatchElems) : 0;
     case kPhAnalytic:
       return render ? 0 : ceil_div(e.R, kBatchHeavyElems);
-    case kPhReduce:
-      return render ? ceil_div(e.L, kBatchRenders) : 0;
+    case kPhReduce:    // and write their loss differences directly
+      return render && !(q.scene == kDisks && e.pair) ? ceil_div(e.R, kBatchRenders) : 0;
     case kPhPrep:
       return ceil_div(e.streams * e.N, kBatchHeavyElems);
     case kPhAccum:

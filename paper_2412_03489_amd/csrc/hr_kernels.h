@@ -43,6 +43,15 @@ void launch_sample_vnorm(hipStream_t st, const EstShape& e, double* tau, const d
                          double* u, double* vnorm);
 
 // ---- renders ----
+// Half-width of the band around r^2 outside which the FP32 and the FP64
+// decision of (px - cx)^2 + (py - cy)^2 < r^2 provably agree.  FP32 rounding
+// of the pixel centre, of the disk centre and of the products moves
+// d^2 - r^2 by at most about 2^-21 r (1 + |cx| + |cy|) + 2^-22 r^2 near the
+// circle (|dx|, |dy| <= r there); the band is 4-8x that.
+__host__ __device__ inline double ambiguity_band(double cx, double cy, double r) {
+  return 0x1p-19 * (r * (1.0 + fabs(cx) + fabs(cy)) + r * r);
+}
+
 struct DiskScene {
   int W, H, C, D, ppd;
   const float* target;   // H*W*C
@@ -103,13 +112,24 @@ int raster_auto_samples(int W, int H, uint64_t R, int shape);
 void raster_geometry(RasterQuery& a, int shape);
 void launch_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
                     const double* tau, const double* u, float4* rec);
-// HVP render pairs (e.pair): records of the midpoint disks (e.L x D) and the
-// loss difference f(+h) - f(-h) per pair as wave-tile partials
-void launch_pair_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
-                         const double* tau, const double* u, float4* rec);
-void launch_raster_dloss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t P,
-                         int pairs_per_block, int shape, const RasterExact& ex, float* partial,
-                         const int* skip = nullptr);
+// HVP render pairs (e.pair) on a disk scene: pair p = (stream * N + s) * A +
+// a stands for the renders at theta + h u - a tau_s and theta - h u - a tau_s;
+// f[p] = scale * (sum over pixels of (I+ - T)^2 - (I- - T)^2), decided with
+// exact coverage along the disks' edges (hr_edges.hip)
+struct PairQuery {
+  const double* theta;
+  const double* tau;
+  const double* u;           // v / |v|
+  const float* radius;       // D (ppd == 2)
+  const float* colors;       // D x C
+  const float* target;       // H x W x C
+  double* f;                 // L loss differences
+  int W, H, C, D, ppd, n, A, S;   // S: pairs per batch item
+  double h, scale;           // shift; 1 / (W H C)
+  uint64_t L;                // pairs
+  const int* skip;           // as EstShape::skip
+};
+void launch_raster_dloss(hipStream_t st, const PairQuery& a);
 size_t raster_pair_lds_bytes(int D);
 // largest disk count of the pair path (more disks render the HVP per render)
 int raster_pair_max_disks();
@@ -261,6 +281,9 @@ void launch_batch_accum(hipStream_t st, const BatchTable* T, int blocks);
 void launch_batch_finalize(hipStream_t st, const BatchTable* T, int blocks);
 // occupancy of the persistent raster kernel (blocks per CU) for a given LDS size
 int batch_raster_blocks_per_cu(int cls, size_t lds);
+// the persistent form of the render-pair kernel, by channel count C
+void launch_batch_dloss(hipStream_t st, const BatchTable* T, int C, int blocks, size_t lds);
+int batch_dloss_blocks_per_cu(int C, size_t lds);
 int batch_pt_blocks_per_cu(int nr);
 // path tracer constants for device-resident scenes
 size_t pt_const_bytes();

@@ -46,15 +46,6 @@ constexpr int kFlush = 16;       // renders whose quad partials a wave holds in 
 static_assert(kFlush * 16 == 64 * 4, "a flush covers exactly one float4 per lane");
 constexpr float kFar = 1.0e18f;  // centre of pixels outside the image
 
-// Half-width of the band around r^2 outside which the FP32 and the FP64
-// decision of (px - cx)^2 + (py - cy)^2 < r^2 provably agree.  FP32 rounding
-// of the pixel centre, of the disk centre and of the products moves
-// d^2 - r^2 by at most about 2^-21 r (1 + |cx| + |cy|) + 2^-22 r^2 near the
-// circle (|dx|, |dy| <= r there); the band is 4-8x that.
-__host__ __device__ inline double ambiguity_band(double cx, double cy, double r) {
-  return 0x1p-19 * (r * (1.0 + fabs(cx) + fabs(cy)) + r * r);
-}
-
 // record: (cx, cy, (r^2 + band)(1 + 1e-5), r^2 - band) in FP32; r <= 0: never covered
 __device__ __forceinline__ void record_one(const double* __restrict__ theta,
                                            const double* __restrict__ tau,
@@ -512,381 +503,6 @@ void k_raster_loss(RasterQuery a, uint64_t chunks) {
   raster_block<C, kOneGroup, RasterQuery>(a, exq, tile, r0, nr, smem);
 }
 
-// ---- the HVP's render pairs ------------------------------------------------
-// The two renders of one HVP draw and sign, theta + h u - a tau_s and
-// theta - h u - a tau_s, differ only by the shift 2 h u, and the estimator
-// needs only their loss difference f(+h) - f(-h) (section "Hessian-vector
-// product": a central difference of gradient estimates).  Pair p = (stream *
-// N + s) * A + a stands for renders 2p (+h) and 2p + 1 (-h).  Its record per
-// disk is the midpoint disk theta - a tau_s with two squared radii: with e =
-// h (|u_xy| + |u_r|) (the most a shift moves the disk's edge), a pixel at
-// distance d from the midpoint centre is covered by both shifted disks when
-// d < r - e and by neither when d >= r + e; the FP32 test d^2 < lo and
-// d^2 >= hi against lo = (r - e)^2 and hi = (r + e)^2, narrowed and widened
-// by the FP32 error band, decides those cases exactly.  A pixel whose top
-// disk is the same under both shifts contributes nothing to the difference,
-// so only pixels with a "maybe" disk above their top surely covering one
-// (a band of about 2e around each edge) are queued, and each is decided in
-// FP64 from theta, tau and u, the definition's own arithmetic.
-__device__ __forceinline__ void pair_record_one(const double* __restrict__ theta,
-                                                const double* __restrict__ tau,
-                                                const double* __restrict__ u,
-                                                const float* __restrict__ radius, int n, int D,
-                                                int ppd, int A, double h, uint64_t gid,
-                                                float4* __restrict__ rec) {
-  int k;
-  uint64_t p;
-  if (gid >> 32 == 0) {
-    const uint32_t p32 = (uint32_t)gid / (uint32_t)D;
-    k = (int)((uint32_t)gid - p32 * (uint32_t)D);
-    p = p32;
-  } else {
-    p = gid / (uint64_t)D;
-    k = (int)(gid - p * (uint64_t)D);
-  }
-  const int ai = A == 2 ? (int)(p & 1u) : 0;
-  const uint64_t sidx = A == 2 ? p >> 1 : p;
-  const double* t = tau + sidx * (uint64_t)n;
-  const double a = ai == 0 ? 1.0 : -1.0;
-  double m[3];
-  for (int q = 0; q < ppd; ++q) {
-    const int j = k * ppd + q;
-    m[q] = theta[j] - a * t[j];
-  }
-  const double rad = ppd == 3 ? m[2] : (double)radius[k];
-  const double ux = u[k * ppd], uy = u[k * ppd + 1], ur = ppd == 3 ? u[k * ppd + 2] : 0.0;
-  const double e = h * (sqrt(ux * ux + uy * uy) + fabs(ur));
-  const double rp = rad + e, rm = rad - e;
-  float4 out = make_float4((float)m[0], (float)m[1], -1.0f, -1.0f);
-  if (rp > 0.0) {
-    // the band at the larger radius also covers the smaller one
-    const double band = ambiguity_band(m[0], m[1], rp);
-    out.z = (float)((rp * rp + band) * 1.00001);
-    if (rm > 0.0) out.w = (float)(rm * rm - band);
-  }
-  rec[gid] = out;
-}
-
-__global__ void k_pair_records(const double* __restrict__ theta, const double* __restrict__ tau,
-                               const double* __restrict__ u, const float* __restrict__ radius,
-                               int n, int D, int ppd, int A, double h, uint64_t total,
-                               float4* __restrict__ rec, const int* skip) {
-  if (skip && *skip) return;
-  for (uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; gid < total;
-       gid += (uint64_t)gridDim.x * blockDim.x)
-    pair_record_one(theta, tau, u, radius, n, D, ppd, A, h, gid, rec);
-}
-
-constexpr int kQueue = 320;        // queued band pixels per wave
-constexpr int kPairFlush = 16;     // pairs whose partials a wave writes at once
-static_assert(kQueue >= 63 + 64 * kRows, "one pair's band pixels fit behind a part-full pass");
-
-// LDS of one wave of the pair kernel, after the block's colour tables
-struct PairWaveLds {
-  // band pixels in pair order: top sure entry | top maybe entry << 7 | row << 14
-  // | lane << 16 | pair slot << 22 (entries of the pair's table: 0 background,
-  // k + 1 disk k)
-  uint32_t queue[kQueue];
-  float part[64];                  // a pass's per-pixel differences
-  unsigned long long surv[kPairFlush];   // cull survivors of each pair of the flush group
-  float acc[kPairFlush];           // loss-difference partial of each pair
-  double pxd[kSub], pyd[kSub];     // FP64 pixel centres of the wave tile
-  float pxf[kSub], pyf[kSub];      // and FP32 (the walk's values)
-};
-
-__host__ __device__ inline int pair_table_slots(int D) { return raster_table_slots(D); }
-
-// One band pixel decided exactly.  Under each shift the top covering disk is
-// the highest of the pair's cull survivors above the top surely covering one
-// (ks, -1 = background) that covers the pixel; candidates are taken from the
-// top maybe disk ka down, those the midpoint record rules out for both shifts
-// (d^2 >= hi) are skipped, the rest decided in FP64 from theta +- h u - a
-// tau_s with the definition's own arithmetic.  Returns the pixel's
-// (I+ - T)^2 - (I- - T)^2 summed over the channels.
-template <int C>
-__device__ __forceinline__ float resolve_band_pixel(const ConstExact* exq, uint64_t pair,
-                                                    const float4* __restrict__ prec,
-                                                    unsigned long long cand, int ks,
-                                                    float pxf, float pyf, double pxd, double pyd,
-                                                    const float* __restrict__ tgt, uint32_t tb) {
-  uint64_t ex_addr = (uint64_t)exq;
-  __asm__ volatile("" : "+s"(ex_addr));
-  const ConstExact& ex = *(const ConstExact*)ex_addr;
-  const int ai = ex.A == 2 ? (int)(pair & 1u) : 0;
-  const uint64_t sidx = ex.A == 2 ? pair >> 1 : pair;
-  const double a = ai == 0 ? 1.0 : -1.0;
-  const double* ts = ex.tau + sidx * (uint64_t)ex.n;
-  int top_p = ks, top_m = ks;
-  bool done_p = false, done_m = false;
-  // the exact test of disk k under both shifts, (cx, cy[, r]) per disk
-  auto exact = [&](int k, auto ppd_c) {
-    constexpr int ppd = decltype(ppd_c)::value;
-    double pp[3], pm[3];
-#pragma unroll
-    for (int q = 0; q < ppd; ++q) {
-      const int j = k * ppd + q;
-      const double th = ex.theta[j], uj = ex.u[j], tj = ts[j];
-      pp[q] = (th + ex.h * uj) - a * tj;
-      pm[q] = (th + (-ex.h) * uj) - a * tj;
-    }
-    const double rp = ppd == 3 ? pp[2] : (double)ex.radius[k];
-    const double rm = ppd == 3 ? pm[2] : (double)ex.radius[k];
-    const double dxp = pxd - pp[0], dyp = pyd - pp[1];
-    const double dxm = pxd - pm[0], dym = pyd - pm[1];
-    if (!done_p && rp > 0.0 && dxp * dxp + dyp * dyp < rp * rp) { top_p = k; done_p = true; }
-    if (!done_m && rm > 0.0 && dxm * dxm + dym * dym < rm * rm) { top_m = k; done_m = true; }
-  };
-  while (cand != 0ull && !(done_p && done_m)) {
-    const int k = 63 - __builtin_clzll(cand);
-    cand &= ~(1ull << k);
-    const float4 r = prec[k];
-    const float dx = pxf - r.x, dy = pyf - r.y;
-    if (!(fmaf(dy, dy, dx * dx) < r.z)) continue;   // neither shift covers
-    if (ex.ppd == 3) exact(k, std::integral_constant<int, 3>{});
-    else exact(k, std::integral_constant<int, 2>{});
-  }
-  if (top_p == top_m) return 0.0f;
-  // colours from the pair's table (entry k + 1, colour after the record);
-  // entry 0 is the background
-  const lds_f4 cp = *(const LdsF4*)(uintptr_t)(tb + (uint32_t)(top_p + 1) * 32u + 16u);
-  const lds_f4 cm = *(const LdsF4*)(uintptr_t)(tb + (uint32_t)(top_m + 1) * 32u + 16u);
-  const float ap[4] = {cp.x, cp.y, cp.z, cp.w}, am[4] = {cm.x, cm.y, cm.z, cm.w};
-  float acc = 0.0f;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const float t2 = 2.0f * tgt[c];
-    // (cp - T)^2 - (cm - T)^2 = (cp - cm)(cp + cm - 2T)
-    acc = fmaf(ap[c] - am[c], (ap[c] + am[c]) - t2, acc);
-  }
-  return acc;
-}
-
-// One block's pairs [p0, p0 + np) of one query on one block of four 16x16
-// wave tiles; shared by the per-query and the persistent batch kernel (the
-// same bits either way, and for any S or block shape: a wave processes its
-// queue in passes of 64 band pixels whose boundaries depend only on the
-// pixels queued by the aligned groups of kPairFlush pairs, and sums each
-// pair's pixels of a pass in queue order).
-template <int C, class Query>
-__device__ __forceinline__ void dloss_block(const Query& a, const ConstExact* exq, int tile,
-                                            uint64_t p0, int np, float4* smem) {
-  const int W = a.W, H = a.H, D = a.D, tiles_x = a.tiles_x, bwx = a.bwx;
-  const int subs_x = a.subs_x;
-  const uint64_t subs = (uint64_t)a.subs;
-  const float* __restrict__ target = a.target;
-  const float* __restrict__ colors = a.colors;
-  float* __restrict__ partial = a.partial;
-  const uint64_t r_base = a.r_base;
-  float4* s_col = smem;
-  const int tab_slots = pair_table_slots(D);
-  PairWaveLds* s_w = (PairWaveLds*)(smem + tab_slots);
-  __syncthreads();   // the previous work item's readers of LDS are done
-
-  const int ntab = D <= 32 ? 8 : 4;   // tables of the block (two per wave up to 32 disks)
-  for (int t = threadIdx.x; t < ntab * (D + 1); t += blockDim.x) {
-    const int k = t % (D + 1);
-    float cc[4] = {0.f, 0.f, 0.f, 0.f};
-    if (k > 0)
-      for (int c = 0; c < C; ++c) cc[c] = colors[(size_t)(k - 1) * C + c];
-    s_col[2 * t + 1] = make_float4(cc[0], cc[1], cc[2], cc[3]);
-  }
-
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int bx0 = (tile % tiles_x) * (kSub * bwx), by0 = (tile / tiles_x) * (kSub * a.bwy);
-  const int tx0 = bx0 + (wave % bwx) * kSub;
-  const int ty0 = by0 + (wave / bwx) * kSub;
-  const bool live = tx0 < W && ty0 < H;
-  const int x = tx0 + (lane & 15);
-  const int yb = ty0 + (lane >> 4) * kRows;
-  const float px = x < W ? ((float)x + 0.5f) / (float)W : kFar;
-  float py[kRows];
-#pragma unroll
-  for (int i = 0; i < kRows; ++i) py[i] = yb + i < H ? ((float)(yb + i) + 0.5f) / (float)H : kFar;
-  PairWaveLds& L = s_w[wave];
-  if (lane < kSub) {
-    L.pxd[lane] = ((double)(tx0 + lane) + 0.5) / (double)W;
-    L.pyd[lane] = ((double)(ty0 + lane) + 0.5) / (double)H;
-    L.pxf[lane] = ((float)(tx0 + lane) + 0.5f) / (float)W;
-    L.pyf[lane] = ((float)(ty0 + lane) + 0.5f) / (float)H;
-  }
-  if (lane < kPairFlush) L.acc[lane] = 0.0f;
-  const float invW = 1.0f / (float)W, invH = 1.0f / (float)H;
-  const float mx = ((float)tx0 + 0.5f * kSub) * invW, hx = (0.5f * kSub - 0.5f) * invW + 4e-6f;
-  const float my = ((float)ty0 + 0.5f * kSub) * invH, hy = (0.5f * kSub - 0.5f) * invH + 4e-6f;
-  __syncthreads();
-
-  const int np_wave = live ? np : 0;
-  const uint32_t col0 = __builtin_amdgcn_groupstaticsize();
-  const uint64_t sub_w = (uint64_t)(ty0 / kSub) * (uint64_t)subs_x + (uint64_t)(tx0 / kSub);
-  const uint64_t pq = r_base + p0;            // global index of the block's first pair
-  const uint32_t lane_bits = (uint32_t)lane << 16;
-  uint32_t qlen = 0;                          // wave-uniform queue length
-
-  // decides the queue's first cnt band pixels (all of flush group f0), adds
-  // each pair's share to its partial, and moves the rest to the front
-  auto process = [&](int f0, int cnt, uint32_t colw, uint32_t colb) {
-    const bool act = lane < cnt;
-    float contrib = 0.0f;
-    int slot = kPairFlush;
-    if (act) {
-      const uint32_t item = L.queue[lane];
-      const int s_idx = (int)(item & 127u), a_idx = (int)((item >> 7) & 127u);
-      const int row = (int)((item >> 14) & 3u);
-      const int pl = (int)((item >> 16) & 63u);
-      slot = (int)(item >> 22);
-      // pairs alternate between the wave's two tables in a two-pair pass
-      const uint32_t tb = (D <= 32 && (slot & 1)) ? colb : colw;
-      const int ks = s_idx - 1, ka = a_idx - 1;
-      // survivors in (ks, ka]: ka is the top maybe disk of the pixel
-      const unsigned long long below_ka = ((1ull << ka) << 1) - 1ull;
-      const unsigned long long above_ks = ks < 0 ? ~0ull : ~(((1ull << ks) << 1) - 1ull);
-      const unsigned long long cand = L.surv[slot] & below_ka & above_ks;
-      const int xx = pl & 15, yy = (pl >> 4) * kRows + row;
-      const float* tg = target + ((size_t)(ty0 + yy) * W + (tx0 + xx)) * C;
-      const uint64_t pl_pair = p0 + (uint64_t)(f0 + slot);   // within the launch's records
-      contrib = resolve_band_pixel<C>(exq, r_base + pl_pair, a.rec + pl_pair * (uint64_t)D, cand,
-                                      ks, L.pxf[xx], L.pyf[yy], L.pxd[xx], L.pyd[yy], tg, tb);
-    }
-    // a pair's pixels are consecutive: the first lane of each run sums the
-    // run in queue order and adds it to the pair's partial
-    L.part[lane] = contrib;
-    const int prev = __shfl(slot, lane > 0 ? lane - 1 : 0, 64);
-    const bool head = act && (lane == 0 || prev != slot);
-    const uint64_t heads = __builtin_amdgcn_ballot_w64(head);
-    __builtin_amdgcn_wave_barrier();
-    if (head) {
-      const uint64_t later = lane < 63 ? heads & (~0ull << (lane + 1)) : 0ull;
-      const int end = later ? __builtin_ctzll(later) : cnt;
-      float sum = contrib;
-      for (int i = lane + 1; i < end; ++i) sum += L.part[i];
-      L.acc[slot] += sum;
-    }
-    // the rest of the queue to the front
-    const int rest = (int)qlen - cnt;
-    for (int i = lane; i < rest; i += 64) {
-      const uint32_t v = L.queue[cnt + i];
-      __builtin_amdgcn_wave_barrier();
-      L.queue[i] = v;
-    }
-    qlen -= (uint32_t)cnt;
-    __builtin_amdgcn_wave_barrier();
-  };
-
-  // one pair's walk: survivors in painter's order against the midpoint disks
-  // (record x, y, hi, lo); per pixel the table entry of the top surely
-  // covering disk and of the top maybe-covering one; pixels whose top maybe
-  // disk lies above their top sure one are queued
-  auto walk = [&](uint64_t mask, uint32_t colw_p, int slot) {
-    if (lane == 0) L.surv[slot] = mask;
-    __builtin_amdgcn_wave_barrier();
-    if (mask == 0) return;
-    uint32_t sure[kRows], amb[kRows];
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) { sure[i] = 0u; amb[i] = 0u; }
-    while (mask) {
-      const int l = __builtin_ctzll(mask);
-      mask &= mask - 1;
-      const uint32_t id = (uint32_t)(l + 1);
-      const lds_f4 v = *(const LdsF4*)(uintptr_t)(colw_p + id * 32u);
-      const float dx = px - v.x;
-      const float dx2 = dx * dx;
-#pragma unroll
-      for (int i = 0; i < kRows; ++i) {
-        const float dy = py[i] - v.y;
-        const float d2 = fmaf(dy, dy, dx2);
-        amb[i] = d2 < v.z ? id : amb[i];
-        sure[i] = d2 < v.w ? id : sure[i];
-      }
-    }
-    const uint32_t sbits = (uint32_t)slot << 22;
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      const bool band = amb[i] > sure[i];
-      const uint64_t b = __builtin_amdgcn_ballot_w64(band);
-      if (b == 0) continue;
-      if (band) {
-        const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)b, qlen));
-        L.queue[pos] = (sure[i] | (amb[i] << 7)) | (lane_bits | ((uint32_t)i << 14) | sbits);
-      }
-      qlen += (uint32_t)__builtin_popcountll(b);
-    }
-    __builtin_amdgcn_wave_barrier();
-  };
-
-  const float4* rp0 = a.rec + p0 * (uint64_t)D;
-  auto passes = [&](auto g) {
-    constexpr int G = decltype(g)::value;   // pairs per cull
-    const int half = G == 2 ? lane >> 5 : 0;
-    const int lane_d = min(G == 2 ? lane & 31 : lane, D - 1);
-    const uint64_t dm = D < 64 ? (1ull << D) - 1 : ~0ull;
-    const uint64_t rstride = (uint64_t)D * sizeof(float4);
-    const uint32_t loff = (uint32_t)half * (uint32_t)rstride + (uint32_t)lane_d * 16u;
-    const uint32_t colw = col0 + (uint32_t)(wave * G * (D + 1)) * 32u;
-    const uint32_t colb = colw + (uint32_t)(D + 1) * 32u;
-    const uint32_t rec_slot = colw + (uint32_t)(half * (D + 1) + lane_d + 1) * 32u;
-    typedef float g_f4 __attribute__((ext_vector_type(4)));
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)rp0, (short)0, (int)((uint64_t)np * rstride), 0x00020000);
-    auto lane_rec = [&](int rr) {
-      const uint32_t r1 = (uint32_t)min(rr, np - 1);
-      const g_f4 v = __builtin_bit_cast(
-          g_f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)loff, (int)(r1 * (uint32_t)rstride), 0));
-      return make_float4(v.x, v.y, v.z, v.w);
-    };
-    auto pass_mask = [&](int rr) {
-      return G == 2 ? (rr + 1 < np_wave ? dm | (dm << 32) : dm) : dm;
-    };
-    float4 qa = lane_rec(0);
-    for (int f0 = 0; f0 < np_wave; f0 += kPairFlush) {
-      const int fe = min(f0 + kPairFlush, np_wave);
-      for (int rr = f0; rr < fe; rr += G) {
-        const float4 qb = lane_rec(rr + G);
-        const uint64_t m = park_and_cull(qa, rec_slot, pass_mask(rr), mx, my, hx, hy);
-        qa = qb;
-        // every walk starts with fewer than 64 queued pixels and adds at most
-        // 64 * kRows, so the queue never overflows
-        walk(m & dm, colw, rr - f0);
-        while (qlen >= 64) process(f0, 64, colw, colb);
-        if (G == 2 && rr + 1 < fe) {
-          walk(m >> 32, colb, rr + 1 - f0);
-          while (qlen >= 64) process(f0, 64, colw, colb);
-        }
-      }
-      if (qlen > 0) process(f0, (int)qlen, colw, colb);
-      if (lane < fe - f0)
-        partial[part_index(pq + (uint64_t)(f0 + lane), sub_w, subs)] = L.acc[lane];
-      if (lane < kPairFlush) L.acc[lane] = 0.0f;
-    }
-  };
-  if (D <= 32)
-    passes(std::integral_constant<int, 2>{});
-  else
-    passes(std::integral_constant<int, 1>{});
-}
-
-// seven waves per SIMD (at most 72 VGPRs; two per-wave values spill to
-// scratch and are reloaded once per cull): the fastest of the wave counts
-// timed, the extra waves hiding the record and LDS latency of the cull
-template <int C>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
-void k_raster_dloss(RasterQuery a, uint64_t chunks) {
-  extern __shared__ float4 smem[];
-  if (a.skip && *a.skip) return;
-  const uint64_t b = blockIdx.x;
-  const uint64_t xcd = b & 7u, j = b >> 3;
-  const uint64_t chunk = (j / (uint64_t)a.tiles) * 8u + xcd;
-  const int tile = (int)(j % (uint64_t)a.tiles);
-  if (chunk >= chunks) return;
-  const uint64_t p0 = chunk * (uint64_t)a.S;
-  const int np = (int)min((uint64_t)a.S, a.R - p0);
-  const ConstExact* exq = (const ConstExact*)((const __attribute__((address_space(4))) char*)
-                                                  __builtin_amdgcn_kernarg_segment_ptr() +
-                                              offsetof(RasterQuery, ex));
-  dloss_block<C, RasterQuery>(a, exq, tile, p0, np, smem);
-}
-
 // single render at theta, coverage in FP64 (the definition)
 __global__ void k_render_disks(RasterExact ex, const float* __restrict__ colors, int W, int H,
                                int C, int D, float* __restrict__ image) {
@@ -917,16 +533,10 @@ __global__ __launch_bounds__(256) void k_batch_records(const BatchTable* __restr
     const BatchQuery& Q = T->q[q];
     const EstShape& e = Q.e;
     const uint64_t b = (t - off[q]) * (uint64_t)kBatchElems;
-    const uint64_t end = umin64(e.L * (uint64_t)Q.ds.D, b + kBatchElems);
-    if (e.pair) {
-      for (uint64_t g = b + threadIdx.x; g < end; g += blockDim.x)
-        pair_record_one(Q.theta, Q.tau, Q.u, Q.ds.radius, e.n, Q.ds.D, Q.ds.ppd, e.A, e.h, g,
-                        Q.rec);
-    } else {
-      for (uint64_t g = b + threadIdx.x; g < end; g += blockDim.x)
-        record_one(Q.theta, Q.tau, Q.u, Q.ds.radius, e.n, Q.ds.D, Q.ds.ppd, e.A, e.NH, e.h, g,
-                   Q.rec);
-    }
+    const uint64_t end = umin64(e.R * (uint64_t)Q.ds.D, b + kBatchElems);
+    for (uint64_t g = b + threadIdx.x; g < end; g += blockDim.x)
+      record_one(Q.theta, Q.tau, Q.u, Q.ds.radius, e.n, Q.ds.D, Q.ds.ppd, e.A, e.NH, e.h, g,
+                 Q.rec);
   }
 }
 
@@ -939,12 +549,12 @@ __global__ __launch_bounds__(256) void k_batch_records(const BatchTable* __restr
 // claimed by exactly one atomic increment; a block leaves after seeing all
 // eight queues exhausted.
 // At least 7 waves per SIMD, as k_raster_loss.
-template <int C, bool kOneGroup, bool kPair = false>
+template <int C, bool kOneGroup>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
 void k_batch_raster(const BatchTable* __restrict__ T) {
   extern __shared__ float4 smem[];
   __shared__ unsigned long long s_item;
-  const WorkQueues& W = T->raster[kPair ? raster_pair_class(C) : raster_class(C, kOneGroup ? 1 : 65)];
+  const WorkQueues& W = T->raster[raster_class(C, kOneGroup ? 1 : 65)];
   const int home = blockIdx.x & 7;
   uint64_t all = 0;
   for (int x = 0; x < 8; ++x) all += W.items[x];
@@ -977,10 +587,7 @@ void k_batch_raster(const BatchTable* __restrict__ T) {
       const int tile = (int)(l % (uint64_t)sg.tiles);
       const uint64_t r0 = chunk * (uint64_t)a.S;
       const int nr = (int)min((uint64_t)a.S, a.R - r0);
-      if constexpr (kPair)
-        dloss_block<C, ConstRasterQuery>(a, &a.ex, tile, r0, nr, smem);
-      else
-        raster_block<C, kOneGroup, ConstRasterQuery>(a, &a.ex, tile, r0, nr, smem);
+      raster_block<C, kOneGroup, ConstRasterQuery>(a, &a.ex, tile, r0, nr, smem);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
@@ -1096,56 +703,6 @@ void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, u
   }
 }
 
-void launch_pair_records(hipStream_t st, const EstShape& e, const DiskScene& s, const double* theta,
-                         const double* tau, const double* u, float4* rec) {
-  const uint64_t total = e.L * (uint64_t)s.D;
-  hipLaunchKernelGGL(k_pair_records, dim3(grid_for(total, 256)), dim3(256), 0, st, theta, tau, u,
-                     s.radius, e.n, s.D, s.ppd, e.A, e.h, total, rec, e.skip);
-}
-
-size_t raster_pair_lds_bytes(int D) {
-  return (size_t)pair_table_slots(D) * sizeof(float4) + 4 * sizeof(PairWaveLds);
-}
-
-int raster_pair_max_disks() { return 64; }
-
-void launch_raster_dloss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t P, int S,
-                         int shape, const RasterExact& ex, float* partial, const int* skip) {
-  // S counts pairs per block (two renders each): the library's choice is half
-  // the renders-per-block rule's, at least one flush group
-  if (S <= 0) S = raster_auto_samples(s.W, s.H, 2 * P, shape) / 2;
-  S = S < kPairFlush ? kPairFlush : (S / kPairFlush) * kPairFlush;
-  if (S > kMaxS / 2) S = kMaxS / 2;
-  RasterQuery a;
-  a.W = s.W; a.H = s.H; a.C = s.C; a.D = s.D; a.S = S;
-  raster_geometry(a, shape);
-  const int tiles = a.tiles;
-  const uint64_t chunks = (P + S - 1) / S;
-  const size_t lds = raster_pair_lds_bytes(s.D);
-  const uint64_t per_xcd = (chunks + 7) / 8;
-  const uint64_t max_rows = (1ull << 30) / (8ull * (uint64_t)tiles);
-  for (uint64_t row0 = 0; row0 < per_xcd; row0 += max_rows) {
-    const uint64_t rows = umin64(max_rows, per_xcd - row0);
-    const uint64_t sub_chunks = umin64(chunks - row0 * 8, rows * 8);
-    const uint64_t r_base = row0 * 8 * (uint64_t)S;
-    a.rec = rec + r_base * (uint64_t)s.D;
-    a.target = s.target;
-    a.colors = s.colors;
-    a.partial = partial;
-    a.R = umin64(P - r_base, sub_chunks * (uint64_t)S);
-    a.r_base = r_base;
-    a.ex = ex;
-    a.skip = skip;
-    const dim3 grid((unsigned)(8 * tiles * rows));
-    switch (s.C) {
-      case 1: hipLaunchKernelGGL(k_raster_dloss<1>, grid, dim3(256), lds, st, a, sub_chunks); break;
-      case 2: hipLaunchKernelGGL(k_raster_dloss<2>, grid, dim3(256), lds, st, a, sub_chunks); break;
-      case 3: hipLaunchKernelGGL(k_raster_dloss<3>, grid, dim3(256), lds, st, a, sub_chunks); break;
-      default: hipLaunchKernelGGL(k_raster_dloss<4>, grid, dim3(256), lds, st, a, sub_chunks); break;
-    }
-  }
-}
-
 void launch_render_disks(hipStream_t st, const DiskScene& s, const RasterExact& ex, float* image) {
   hipLaunchKernelGGL(k_render_disks, dim3((s.W + 63) / 64, s.H), dim3(64), 0, st, ex, s.colors,
                      s.W, s.H, s.C, s.D, image);
@@ -1164,17 +721,19 @@ static BatchRasterKernel batch_raster_kernel(int cls) {
     case 4: return k_batch_raster<3, true>;
     case 5: return k_batch_raster<3, false>;
     case 6: return k_batch_raster<4, true>;
-    case 7: return k_batch_raster<4, false>;
-    case 8: return k_batch_raster<1, true, true>;
-    case 9: return k_batch_raster<2, true, true>;
-    case 10: return k_batch_raster<3, true, true>;
-    default: return k_batch_raster<4, true, true>;
+    default: return k_batch_raster<4, false>;
   }
 }
+// classes 8.. are the HVP render pairs (hr_edges.hip), by channel count
 void launch_batch_raster(hipStream_t st, const BatchTable* T, int cls, int blocks, size_t lds) {
+  if (cls >= raster_pair_class(1)) {
+    launch_batch_dloss(st, T, cls - raster_pair_class(1) + 1, blocks, lds);
+    return;
+  }
   hipLaunchKernelGGL(batch_raster_kernel(cls), dim3(blocks), dim3(256), lds, st, T);
 }
 int batch_raster_blocks_per_cu(int cls, size_t lds) {
+  if (cls >= raster_pair_class(1)) return batch_dloss_blocks_per_cu(cls - raster_pair_class(1) + 1, lds);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_raster_kernel(cls), 256, lds) !=
       hipSuccess)
