@@ -104,16 +104,16 @@ typedef struct {
                            pairs (an off-diagonal element drawn twice as often);
                            ignored by the other samplers and estimators; other
                            values are HR_EINVAL                                    */
-  int hvp_per_render;   /* HVP on a disk scene of at most 64 disks, 0 (default): the
-                           two shifted scenes of a draw are rendered as a pair that
-                           yields their loss difference f(+h) - f(-h) directly
-                           (coverage tested once against the midpoint disks; only
-                           pixels whose top disk can differ between the shifts are
-                           decided per shift, in FP64); then dbg_loss receives one
+  int hvp_per_render;   /* HVP on a disk scene of at most 64 disks and W + H <= 2048,
+                           0 (default): the two shifted scenes of a draw are taken
+                           as a pair that yields their loss difference f(+h) - f(-h)
+                           directly (only the pixels along the disks' edges whose
+                           top disk can differ between the shifts are visited, and
+                           decided per shift in FP64); then dbg_loss receives one
                            difference per (stream, draw, a), in the order
                            (stream*N + s)*A + a.  1: every shifted scene rendered
-                           and its loss taken separately (always so beyond 64
-                           disks).  Other values are HR_EINVAL                      */
+                           and its loss taken separately (always so for larger
+                           scenes).  Other values are HR_EINVAL                     */
 } hr_opts;
 
 /* Fills the defaults listed above. */

@@ -302,7 +302,7 @@ class Scene:
         _check(lib().hr_scene_disks(ctx.h, W, H, C_, D, ppd, None if rad is None else _p(rad),
                                     _p(colors), _p(target), C.byref(h)))
         sc = Scene(ctx, h, D * ppd, (H, W, C_))
-        sc.n_disks = D
+        sc.n_disks, sc.W, sc.H = D, W, H
         return sc
 
     @staticmethod
@@ -348,10 +348,12 @@ def n_streams(kind, n, sampler=AIS):
 
 
 def hvp_pairs(kind, scene, hvp_per_render=False):
-    """Whether an HVP on this scene renders its +-h scenes as pairs (a disk
-    scene of at most 64 disks, hvp_per_render off): then the per-render loss
-    output holds one loss difference f(+h) - f(-h) per (draw, sign)."""
-    return (kind == "hvp" and getattr(scene, "n_disks", 10 ** 9) <= 64 and not hvp_per_render)
+    """Whether an HVP on this scene takes its +-h scenes as pairs (a disk
+    scene of at most 64 disks with W + H <= 2048, hvp_per_render off): then
+    the per-render loss output holds one loss difference f(+h) - f(-h) per
+    (draw, sign)."""
+    return (kind == "hvp" and getattr(scene, "n_disks", 10 ** 9) <= 64
+            and getattr(scene, "W", 0) + getattr(scene, "H", 0) <= 2048 and not hvp_per_render)
 
 
 def estimate(kind, scene, theta, sigma, N, seed, v=None, sampler=AIS, antithetic=True,

@@ -174,6 +174,7 @@ hr_status plan_query(hr_scene* sc, int what, double sigma, uint64_t N, uint64_t 
   // an HVP on a disk scene of at most 64 disks renders its +-h scenes as
   // pairs and yields one loss difference per (draw, a)
   e.pair = (what == kHvp && sc->kind == kDisks && sc->D <= raster_pair_max_disks() &&
+            sc->W + sc->H <= raster_pair_max_side_sum() &&
             !o.hvp_per_render) ? 1 : 0;
   e.L = e.pair ? e.R / 2 : e.R;
   e.sigma = sigma;

@@ -189,7 +189,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
         // pairs per block item: half the renders (the block's four waves
         // take one pair each at a time)
         qS[q] = std::max(4, qS[q] / 2);
-        lds = std::max(lds, raster_pair_lds_bytes(sc->D));
+        lds = std::max(lds, raster_pair_lds_bytes(sc->W, sc->H));
       } else {
         lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
       }

@@ -46,6 +46,8 @@ constexpr int kEdgeQueue = 128;   // queued ring pixels: fewer than 64 + one ste
 // ranges, ring spans, box overlaps): far above the FP32 rounding of the bound
 // computations, far below a pixel.
 constexpr float kEdgeEps = 2e-5f;
+// pixel centres of images with W + H up to this are tabulated in LDS per block
+constexpr int kEdgeTab = 2048;
 
 // One wave's share of LDS
 struct EdgeWave {
@@ -89,7 +91,9 @@ __device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k,
     if (rm > 0.0) out.w = (float)(rm * rm - band);
   }
   L.rec[k] = out;
-  L.rad[k] = out.z > 0.0f ? sqrtf(out.z) : -1.0f;
+  // the hardware square root (within 1 ulp): the bounds built on it carry
+  // kEdgeEps of slack
+  L.rad[k] = out.z > 0.0f ? __builtin_amdgcn_sqrtf(out.z) : -1.0f;
 }
 
 // One ring pixel of disk k: the top disk under each shift, and the pixel's
@@ -97,9 +101,9 @@ __device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k,
 // ring of a disk above k, which counts it instead).
 template <int C>
 __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave& L,
-                                            const float4* s_col, int x, int y, int k) {
-  const float pxf = ((float)x + 0.5f) / (float)a.W;
-  const float pyf = ((float)y + 0.5f) / (float)a.H;
+                                            const float4* s_col, const float* s_cx,
+                                            const float* s_cy, int x, int y, int k) {
+  const float pxf = s_cx[x], pyf = s_cy[y];
   const unsigned long long nb = L.nbr[k];
   // a disk above k that may cover the pixel: the pixel is in that disk's ring
   // or inside it, and is counted there (or contributes nothing)
@@ -166,7 +170,8 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave& 
 // squared-error difference).
 template <int C>
 __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWave& L,
-                                          const float4* s_col) {
+                                          const float4* s_col, const float* s_cx,
+                                          const float* s_cy) {
   const int lane = threadIdx.x & 63;
   const int D = a.D, W = a.W, H = a.H;
   // lane k: disk k's record, parameters, outer radius and ring rows
@@ -195,21 +200,29 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
   if (lane == D - 1) L.off[D] = incl;
   const int total = __shfl(incl, 63, 64);
   __builtin_amdgcn_wave_barrier();
-  // lane k: the disks whose outer boxes meet disk k's
-  if (lane < D) {
-    const float4 vk = L.rec[lane];
-    const float rk = L.rad[lane];
+  // the disks whose outer boxes meet disk k's: up to 32 disks lanes k and
+  // k + 32 test half of them each, else lane k tests all
+  {
+    const bool halves = D <= 32;
+    const int k = halves ? (lane & 31) : lane;
+    const int j0 = halves && lane >= 32 ? (D + 1) / 2 : 0;
+    const int j1 = halves && lane < 32 ? (D + 1) / 2 : D;
     unsigned long long m = 0ull;
-    if (rk > 0.0f)
-      for (int j = 0; j < D; ++j) {
-        const float rj = L.rad[j];
-        const float4 vj = L.rec[j];
-        const float reach = rj + rk + 2.0f * kEdgeEps;
-        const bool meet = j != lane && rj > 0.0f && fabsf(vj.x - vk.x) <= reach &&
-                          fabsf(vj.y - vk.y) <= reach;
-        m |= meet ? (1ull << j) : 0ull;
-      }
-    L.nbr[lane] = m;
+    if (k < D) {
+      const float4 vk = L.rec[k];
+      const float rk = L.rad[k];
+      if (rk > 0.0f)
+        for (int j = j0; j < j1; ++j) {
+          const float rj = L.rad[j];
+          const float4 vj = L.rec[j];
+          const float reach = rj + rk + 2.0f * kEdgeEps;
+          const bool meet = j != k && rj > 0.0f && fabsf(vj.x - vk.x) <= reach &&
+                            fabsf(vj.y - vk.y) <= reach;
+          m |= meet ? (1ull << j) : 0ull;
+        }
+    }
+    if (halves) m |= __shfl_xor(m, 32, 64);
+    if (lane < D) L.nbr[lane] = m;
   }
   __builtin_amdgcn_wave_barrier();
 
@@ -219,7 +232,8 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     float c = 0.0f;
     if (lane < cnt_q) {
       const uint32_t xy = L.q_xy[lane];
-      c = edge_pixel<C>(a, L, s_col, (int)(xy & 0xffffu), (int)(xy >> 16), (int)L.q_k[lane]);
+      c = edge_pixel<C>(a, L, s_col, s_cx, s_cy, (int)(xy & 0xffffu), (int)(xy >> 16),
+                        (int)L.q_k[lane]);
     }
     sum += c;
     // the rest of the queue to the front
@@ -245,16 +259,15 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       kcur = k;
       v = L.rec[k];
       y = L.y0[k] + (it - L.off[k]);
-      const float py = ((float)y + 0.5f) / (float)H;
-      dy = py - v.y;
+      dy = s_cy[y] - v.y;
       const float dy2 = dy * dy;
       // |dx| < ro holds for every pixel with d^2 < outer on this row and
       // |dx| >= ri for every one with d^2 >= inner (slack: the FP32 rounding
       // of d^2 and of these bounds)
       const float slack = 0x1p-22f * (dy2 + v.z);
-      const float ro = sqrtf(fmaxf(v.z - dy2 + slack, 0.0f));
+      const float ro = __builtin_amdgcn_sqrtf(fmaxf(v.z - dy2 + slack, 0.0f));
       const float i2 = v.w - dy2 - slack;
-      const float ri = i2 > 0.0f ? sqrtf(i2) : 0.0f;
+      const float ri = i2 > 0.0f ? __builtin_amdgcn_sqrtf(i2) : 0.0f;
       // centres in [cx - ro, cx - ri] and [cx + ri, cx + ro], each widened
       x = max(0, (int)ceilf((v.x - ro - kEdgeEps) * (float)W - 0.5f));
       xe = min(W - 1, (int)floorf((v.x - ri + kEdgeEps) * (float)W - 0.5f));
@@ -269,8 +282,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       if (__builtin_amdgcn_ballot_w64(act) == 0ull) break;
       bool ring = false;
       if (act) {
-        const float px = ((float)x + 0.5f) / (float)W;
-        const float dx = px - v.x;
+        const float dx = s_cx[x] - v.x;
         const float d2 = fmaf(dy, dy, dx * dx);
         ring = d2 < v.z && !(d2 < v.w);
       }
@@ -309,17 +321,35 @@ __device__ __forceinline__ void edge_colours(const PairQuery& a, float4* s_col) 
   }
 }
 
+// the FP32 pixel centres (x + 1/2) / W and (y + 1/2) / H, as the per-render
+// rasteriser computes them, in the block's LDS (W + H <= kEdgeTab)
+__device__ __forceinline__ void edge_centres(int W, int H, float* s_cx, float* s_cy) {
+  for (int t = threadIdx.x; t < W + H; t += blockDim.x) {
+    if (t < W) s_cx[t] = ((float)t + 0.5f) / (float)W;
+    else s_cy[t - W] = ((float)(t - W) + 0.5f) / (float)H;
+  }
+}
+
+// LDS layout of a block: colour table, four waves' shares, pixel centres
+__host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
+  return (size_t)(kEdgeDisks + 1) * sizeof(float4) + 4 * sizeof(EdgeWave) +
+         (size_t)(W + H) * sizeof(float);
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void k_raster_dloss(PairQuery a) {
   extern __shared__ float4 smem[];
   if (a.skip && *a.skip) return;
   float4* s_col = smem;
   EdgeWave* s_w = (EdgeWave*)(smem + kEdgeDisks + 1);
+  float* s_cx = (float*)(s_w + 4);
+  float* s_cy = s_cx + a.W;
   edge_colours(a, s_col);
+  edge_centres(a.W, a.H, s_cx, s_cy);
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   for (uint64_t p = (uint64_t)blockIdx.x * 4 + wave; p < a.L; p += (uint64_t)gridDim.x * 4)
-    edge_pair<C>(a, p, s_w[wave], s_col);
+    edge_pair<C>(a, p, s_w[wave], s_col, s_cx, s_cy);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -344,6 +374,7 @@ __global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restric
   if (all == 0) return;   // nothing of this kind in the batch
   float4* s_col = smem;
   EdgeWave* s_w = (EdgeWave*)(smem + kEdgeDisks + 1);
+  float* s_cx = (float*)(s_w + 4);
   const int wave = threadIdx.x >> 6;
   for (int kq = 0; kq < 8; ++kq) {
     const int x = (home + kq) & 7;
@@ -386,10 +417,13 @@ __global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restric
       const uint64_t chunk = (uint64_t)sg.c0 + 8u * (it - sg.item0);
       const uint64_t p0 = chunk * (uint64_t)a.S;
       const uint64_t p1 = umin64(p0 + (uint64_t)a.S, a.L);
-      __syncthreads();   // the previous item's readers of the colour table are done
+      float* s_cy = s_cx + a.W;
+      __syncthreads();   // the previous item's readers of the tables are done
       edge_colours(a, s_col);
+      edge_centres(a.W, a.H, s_cx, s_cy);
       __syncthreads();
-      for (uint64_t p = p0 + wave; p < p1; p += 4) edge_pair<C>(a, p, s_w[wave], s_col);
+      for (uint64_t p = p0 + wave; p < p1; p += 4)
+        edge_pair<C>(a, p, s_w[wave], s_col, s_cx, s_cy);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
@@ -400,14 +434,14 @@ __global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restric
 
 }  // namespace
 
-size_t raster_pair_lds_bytes(int) {
-  return (size_t)(kEdgeDisks + 1) * sizeof(float4) + 4 * sizeof(EdgeWave);
-}
+size_t raster_pair_lds_bytes(int W, int H) { return edge_lds_bytes(W, H); }
+
+int raster_pair_max_side_sum() { return kEdgeTab; }
 
 int raster_pair_max_disks() { return kEdgeDisks; }
 
 void launch_raster_dloss(hipStream_t st, const PairQuery& a) {
-  const size_t lds = raster_pair_lds_bytes(a.D);
+  const size_t lds = edge_lds_bytes(a.W, a.H);
   // one wave per pair; the grid strides over the rest
   const uint64_t blocks = umin64((a.L + 3) / 4, 1ull << 20);
   const dim3 grid((unsigned)(blocks > 0 ? blocks : 1));

@@ -130,9 +130,11 @@ struct PairQuery {
   const int* skip;           // as EstShape::skip
 };
 void launch_raster_dloss(hipStream_t st, const PairQuery& a);
-size_t raster_pair_lds_bytes(int D);
-// largest disk count of the pair path (more disks render the HVP per render)
+size_t raster_pair_lds_bytes(int W, int H);
+// largest disk count, and largest W + H, of the pair path (larger scenes
+// render the HVP per render)
 int raster_pair_max_disks();
+int raster_pair_max_side_sum();
 // number of 16x16 wave tiles of the image: the partial stride per render
 int raster_subtiles(int W, int H);
 void launch_raster_loss(hipStream_t st, const DiskScene& s, const float4* rec, uint64_t R,
