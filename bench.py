@@ -57,8 +57,8 @@ FLOP_PER_PIXEL = 12.0
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy, valid for the kernel
 # source with this code digest (code_digest: comments and blank lines left
 # out); reported as null once the code has changed (or before it is measured).
-TRAFFIC_BYTES_PER_LAUNCH = 283450026
-TRAFFIC_SOURCE_DIGEST = "34b287836b38776bf3e5986b5bea6881b703a15411bc265a8d0df9ca28b00e44"
+TRAFFIC_BYTES_PER_LAUNCH = 56844062
+TRAFFIC_SOURCE_DIGEST = "25a4eba1529f2e57203ae1b76f54d8b0b69706025d5b05b6697bf79699358d49"
 
 
 def code_digest(path):
@@ -75,7 +75,7 @@ def code_digest(path):
 
 
 def raster_traffic():
-    src = os.path.join(ROOT, "paper_2412_03489_amd", "csrc", "hr_raster.hip")
+    src = os.path.join(ROOT, "paper_2412_03489_amd", "csrc", "hr_edges.hip")
     return TRAFFIC_BYTES_PER_LAUNCH if code_digest(src) == TRAFFIC_SOURCE_DIGEST else None
 
 
@@ -454,11 +454,12 @@ def main_section(P, ctx, args):
         "error_vs_fp64": errors,
         "cpu_baseline": None,
     }
-    # the loss pass: per loss output -- a render of the gradient, a render
-    # pair of an HVP -- its wave-tile partials are read (4 B each) and one
-    # FP64 value written; HBM-bound, against the 8 TB/s peak
+    # the loss pass of the gradient's renders (an HVP's render pairs write
+    # their loss differences directly): per render its wave-tile partials are
+    # read (4 B each) and one FP64 value written; HBM-bound, against the
+    # 8 TB/s peak
     subs = ((w.W + 15) // 16) * ((w.H + 15) // 16)
-    outputs = 2 * w.N * steps + hvps * 2 * w.N
+    outputs = 2 * w.N * red_launches
     red_bytes = outputs * (subs * 4 + 8)
     red_gbs = red_bytes / (red_ms * 1e-3) / 1e9 if red_ms > 0 else None
     line["loss_pass"] = {"bound": "hbm", "kernel": "k_tile_reduce",
