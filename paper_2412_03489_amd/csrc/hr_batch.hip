@@ -179,6 +179,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   std::vector<double> cost(nq, 0.0);
   std::vector<int> qS(nq, 0), qshape(nq, 0);
   lds = 0;
+  lds_pair = 0;
   for (int q = 0; q < nq; ++q) {
     const QueryPlan& p = items[q].plan;
     const hr_scene* sc = p.sc;
@@ -186,10 +187,13 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       raster_config(ctx, sc, p.o, p.e.R, &qS[q], &qshape[q]);
       cost[q] = (double)qS[q] * (double)(sc->D + 16);
       if (p.e.pair) {
-        // pairs per block item: half the renders (the block's four waves
-        // take one pair each at a time)
-        qS[q] = std::max(4, qS[q] / 2);
-        lds = std::max(lds, raster_pair_lds_bytes(sc->W, sc->H));
+        // pairs per block item: the block's four waves take one pair each at
+        // a time; a few per wave for large queries, one for small ones, so
+        // that every query spreads over many blocks
+        qS[q] = p.o.samples_per_block > 0
+                    ? std::max(4, p.o.samples_per_block / 2)
+                    : (int)std::min<uint64_t>(32, std::max<uint64_t>(4, 4 * (p.e.L / 16384)));
+        lds_pair = std::max(lds_pair, raster_pair_lds_bytes(sc->W, sc->H));
       } else {
         lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
       }
@@ -378,6 +382,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   }
   lds = std::max(lds, (size_t)1024);
   lds = (lds + 4095) & ~size_t(4095);   // LDS classes of 4 KiB keep the graph reusable
+  lds_pair = (std::max(lds_pair, (size_t)1024) + 4095) & ~size_t(4095);
   return HR_OK;
 }
 
@@ -408,7 +413,8 @@ void BatchSlot::launches(hipStream_t st, bool time_phases) {
   const unsigned cl = classes();
   run("batch_raster", [&] {
     for (int c = 0; c < kRasterClasses; ++c)
-      if (cl & (1u << c)) launch_batch_raster(st, T, c, raster_blocks[c], lds);
+      if (cl & (1u << c))
+        launch_batch_raster(st, T, c, raster_blocks[c], c >= raster_pair_class(1) ? lds_pair : lds);
   });
   run("batch_pt", [&] {
     for (int c = 0; c < 3; ++c)
@@ -434,14 +440,16 @@ hr_status BatchSlot::enqueue(bool use_graph, bool timing_ok) {
   (void)hipGetLastError();
   const unsigned cl = classes();
   for (int c = 0; c < kRasterClasses; ++c)
-    if (cl & (1u << c)) raster_blocks[c] = cus * batch_raster_blocks_per_cu(c, lds);
+    if (cl & (1u << c))
+      raster_blocks[c] =
+          cus * batch_raster_blocks_per_cu(c, c >= raster_pair_class(1) ? lds_pair : lds);
   HR_HIP(hipMemcpyAsync(dev, host, upload_bytes_, hipMemcpyHostToDevice, stream));
   graph_used = false;
   const bool timing = allow_timing && timing_ok && ctx->timing;
   // a one-query batch launches its per-query kernels directly: their launch
   // parameters are the query's own, so a captured sequence would not be reusable
   if (use_graph && !timing && !single_) {
-    if (exec && (exec_lds != lds || exec_classes != cl)) {
+    if (exec && (exec_lds != lds || exec_lds_pair != lds_pair || exec_classes != cl)) {
       (void)hipGraphExecDestroy(exec);
       exec = nullptr;
     }
@@ -457,6 +465,7 @@ hr_status BatchSlot::enqueue(bool use_graph, bool timing_ok) {
         return fail(HR_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
       }
       exec_lds = lds;
+      exec_lds_pair = lds_pair;
       exec_classes = cl;
     }
     HR_HIP(hipGraphLaunch(exec, stream));
@@ -532,10 +541,11 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
           // the work counters restart from zero before each timed launch
           launch_batch_sample(slot.stream, T, slot.phase_blocks);
           if (hipEventRecord(a, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }
-          for (int c = 0; c < kRasterClasses; ++c)
-            if (cl & (1u << c))
-              launch_batch_raster(slot.stream, T, c, slot.cus * batch_raster_blocks_per_cu(c, slot.lds),
-                                  slot.lds);
+          for (int c = 0; c < kRasterClasses; ++c) {
+            if (!(cl & (1u << c))) continue;
+            const size_t l = c >= raster_pair_class(1) ? slot.lds_pair : slot.lds;
+            launch_batch_raster(slot.stream, T, c, slot.cus * batch_raster_blocks_per_cu(c, l), l);
+          }
           if (hipEventRecord(b, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }
           if (hipEventSynchronize(b) != hipSuccess) { st = fail(HR_EDEVICE, "event sync"); break; }
           float ms = 0.f;
