@@ -49,15 +49,16 @@ constexpr float kEdgeEps = 2e-5f;
 // pixel centres of images with W + H up to this are tabulated in LDS per block
 constexpr int kEdgeTab = 2048;
 
-// One wave's share of LDS
+// One wave's share of LDS, for scenes of at most MD disks (32 or 64)
+template <int MD>
 struct EdgeWave {
-  float4 rec[kEdgeDisks];             // midpoint disk: cx, cy, outer^2, inner^2 (-1: none)
-  double pp[kEdgeDisks][3];           // the disk under +h: theta + h u - a tau_s
-  double pm[kEdgeDisks][3];           // and under -h (cx, cy[, r])
-  unsigned long long nbr[kEdgeDisks]; // disks whose outer boxes meet this disk's
-  float rad[kEdgeDisks];              // outer radius (-1: none)
-  int y0[kEdgeDisks];                 // first row of the disk's ring
-  int off[kEdgeDisks + 1];            // its first (disk, row) item; off[D] = all items
+  float4 rec[MD];                     // midpoint disk: cx, cy, outer^2, inner^2 (-1: none)
+  double pp[MD][3];                   // the disk under +h: theta + h u - a tau_s
+  double pm[MD][3];                   // and under -h (cx, cy[, r])
+  unsigned long long nbr[MD];         // disks whose outer boxes meet this disk's
+  float rad[MD];                      // outer radius (-1: none)
+  int y0[MD];                         // first row of the disk's ring
+  int off[MD + 1];                    // its first (disk, row) item; off[D] = all items
   uint32_t q_xy[kEdgeQueue];          // queued ring pixel: x | y << 16
   uint32_t q_k[kEdgeQueue];           // and the disk whose ring holds it
 };
@@ -65,7 +66,8 @@ struct EdgeWave {
 // Disk k of pair p: its midpoint record and its FP64 parameters under both
 // shifts, with the arithmetic of the per-render records and of the exact
 // coverage test.
-__device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k, EdgeWave& L) {
+template <int MD>
+__device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k, EdgeWave<MD>& L) {
   const int ppd = a.ppd;
   const int ai = a.A == 2 ? (int)(p & 1u) : 0;
   const uint64_t sidx = a.A == 2 ? p >> 1 : p;
@@ -99,8 +101,8 @@ __device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k,
 // One ring pixel of disk k: the top disk under each shift, and the pixel's
 // (I+ - T)^2 - (I- - T)^2 over the channels (0 if the pixel belongs to the
 // ring of a disk above k, which counts it instead).
-template <int C>
-__device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave& L,
+template <int C, int MD>
+__device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<MD>& L,
                                             const float4* s_col, const float* s_cx,
                                             const float* s_cy, int x, int y, int k) {
   const float pxf = s_cx[x], pyf = s_cy[y];
@@ -168,8 +170,8 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave& 
 
 // Pair p by one wave: f[p] = scale * (sum over the pair's pixels of the
 // squared-error difference).
-template <int C>
-__device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWave& L,
+template <int C, int MD>
+__device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWave<MD>& L,
                                           const float4* s_col, const float* s_cx,
                                           const float* s_cy) {
   const int lane = threadIdx.x & 63;
@@ -232,7 +234,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     float c = 0.0f;
     if (lane < cnt_q) {
       const uint32_t xy = L.q_xy[lane];
-      c = edge_pixel<C>(a, L, s_col, s_cx, s_cy, (int)(xy & 0xffffu), (int)(xy >> 16),
+      c = edge_pixel<C, MD>(a, L, s_col, s_cx, s_cy, (int)(xy & 0xffffu), (int)(xy >> 16),
                         (int)L.q_k[lane]);
     }
     sum += c;
@@ -331,17 +333,23 @@ __device__ __forceinline__ void edge_centres(int W, int H, float* s_cx, float* s
 }
 
 // LDS layout of a block: colour table, four waves' shares, pixel centres
+template <int MD>
 __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
-  return (size_t)(kEdgeDisks + 1) * sizeof(float4) + 4 * sizeof(EdgeWave) +
+  return (size_t)(MD + 1) * sizeof(float4) + 4 * sizeof(EdgeWave<MD>) +
          (size_t)(W + H) * sizeof(float);
 }
 
-template <int C>
-__global__ __launch_bounds__(256) void k_raster_dloss(PairQuery a) {
+// Up to 32 disks the block's LDS (16.8 KB) leaves room for 7 waves per
+// SIMD, and the kernel, latency-bound on its LDS and FP64 chains at 5, runs
+// faster at 7 (72 VGPRs, a few values spilled: 1.55 -> 1.33-1.39 ms per
+// disks32 HVP launch; 6: 1.40, 8: 1.34); with 64 disks the LDS allows 5.
+template <int C, int MD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MD == 32 ? 7 : 1)))
+void k_raster_dloss(PairQuery a) {
   extern __shared__ float4 smem[];
   if (a.skip && *a.skip) return;
   float4* s_col = smem;
-  EdgeWave* s_w = (EdgeWave*)(smem + kEdgeDisks + 1);
+  EdgeWave<MD>* s_w = (EdgeWave<MD>*)(smem + MD + 1);
   float* s_cx = (float*)(s_w + 4);
   float* s_cy = s_cx + a.W;
   edge_colours(a, s_col);
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(256) void k_raster_dloss(PairQuery a) {
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   for (uint64_t p = (uint64_t)blockIdx.x * 4 + wave; p < a.L; p += (uint64_t)gridDim.x * 4)
-    edge_pair<C>(a, p, s_w[wave], s_col, s_cx, s_cy);
+    edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -363,8 +371,11 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 // their XCD, claim items by one atomic increment each (the next one before
 // working on the current one), move on to the other queues when theirs is
 // empty, and leave after seeing all eight exhausted.
+// the 64-disk layout's LDS allows 5 blocks of four waves per CU: registers
+// for 5 waves per SIMD
 template <int C>
-__global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restrict__ T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+void k_batch_dloss(const BatchTable* __restrict__ T) {
   extern __shared__ float4 smem[];
   __shared__ unsigned long long s_item;
   const WorkQueues& W = T->raster[raster_pair_class(C)];
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restric
   for (int x = 0; x < 8; ++x) all += W.items[x];
   if (all == 0) return;   // nothing of this kind in the batch
   float4* s_col = smem;
-  EdgeWave* s_w = (EdgeWave*)(smem + kEdgeDisks + 1);
+  EdgeWave<kEdgeDisks>* s_w = (EdgeWave<kEdgeDisks>*)(smem + kEdgeDisks + 1);
   float* s_cx = (float*)(s_w + 4);
   const int wave = threadIdx.x >> 6;
   for (int kq = 0; kq < 8; ++kq) {
@@ -423,7 +434,7 @@ __global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restric
       edge_centres(a.W, a.H, s_cx, s_cy);
       __syncthreads();
       for (uint64_t p = p0 + wave; p < p1; p += 4)
-        edge_pair<C>(a, p, s_w[wave], s_col, s_cx, s_cy);
+        edge_pair<C, kEdgeDisks>(a, p, s_w[wave], s_col, s_cx, s_cy);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
@@ -434,23 +445,31 @@ __global__ __launch_bounds__(256) void k_batch_dloss(const BatchTable* __restric
 
 }  // namespace
 
-size_t raster_pair_lds_bytes(int W, int H) { return edge_lds_bytes(W, H); }
+// the persistent kernel serves every pair query of its class: the 64-disk layout
+size_t raster_pair_lds_bytes(int W, int H) { return edge_lds_bytes<kEdgeDisks>(W, H); }
 
 int raster_pair_max_side_sum() { return kEdgeTab; }
 
 int raster_pair_max_disks() { return kEdgeDisks; }
 
-void launch_raster_dloss(hipStream_t st, const PairQuery& a) {
-  const size_t lds = edge_lds_bytes(a.W, a.H);
+template <int MD>
+static void launch_dloss_md(hipStream_t st, const PairQuery& a) {
+  const size_t lds = edge_lds_bytes<MD>(a.W, a.H);
   // one wave per pair; the grid strides over the rest
   const uint64_t blocks = umin64((a.L + 3) / 4, 1ull << 20);
   const dim3 grid((unsigned)(blocks > 0 ? blocks : 1));
   switch (a.C) {
-    case 1: hipLaunchKernelGGL(k_raster_dloss<1>, grid, dim3(256), lds, st, a); break;
-    case 2: hipLaunchKernelGGL(k_raster_dloss<2>, grid, dim3(256), lds, st, a); break;
-    case 3: hipLaunchKernelGGL(k_raster_dloss<3>, grid, dim3(256), lds, st, a); break;
-    default: hipLaunchKernelGGL(k_raster_dloss<4>, grid, dim3(256), lds, st, a); break;
+    case 1: hipLaunchKernelGGL((k_raster_dloss<1, MD>), grid, dim3(256), lds, st, a); break;
+    case 2: hipLaunchKernelGGL((k_raster_dloss<2, MD>), grid, dim3(256), lds, st, a); break;
+    case 3: hipLaunchKernelGGL((k_raster_dloss<3, MD>), grid, dim3(256), lds, st, a); break;
+    default: hipLaunchKernelGGL((k_raster_dloss<4, MD>), grid, dim3(256), lds, st, a); break;
   }
+}
+
+void launch_raster_dloss(hipStream_t st, const PairQuery& a) {
+  // up to 32 disks: half the per-wave LDS, more blocks per CU
+  if (a.D <= 32) launch_dloss_md<32>(st, a);
+  else launch_dloss_md<kEdgeDisks>(st, a);
 }
 
 typedef void (*BatchDlossKernel)(const BatchTable*);
