@@ -33,10 +33,10 @@ def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch)
     B = _bench()
     src = tmp_path / "paper_2412_03489_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "hr_raster.hip").write_text("int g() { return 1; }\n")
+    (src / "hr_edges.hip").write_text("int g() { return 1; }\n")
     monkeypatch.setattr(B, "ROOT", str(tmp_path))
     assert B.raster_traffic() is None
-    monkeypatch.setattr(B, "TRAFFIC_SOURCE_DIGEST", B.code_digest(str(src / "hr_raster.hip")))
+    monkeypatch.setattr(B, "TRAFFIC_SOURCE_DIGEST", B.code_digest(str(src / "hr_edges.hip")))
     assert B.raster_traffic() == B.TRAFFIC_BYTES_PER_LAUNCH
 
 
