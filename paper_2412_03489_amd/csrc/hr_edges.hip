@@ -49,13 +49,27 @@ constexpr float kEdgeEps = 2e-5f;
 // pixel centres of images with W + H up to this are tabulated in LDS per block
 constexpr int kEdgeTab = 2048;
 
+// Bit masks over the disks: 32-bit words up to 32 disks (single-instruction
+// bit scans), else 64-bit
+template <int MD> struct EdgeMask;
+template <> struct EdgeMask<32> {
+  typedef uint32_t T;
+  __device__ static int low(T m) { return __builtin_ctz(m); }
+  __device__ static int high(T m) { return 31 - __builtin_clz(m); }
+};
+template <> struct EdgeMask<64> {
+  typedef unsigned long long T;
+  __device__ static int low(T m) { return __builtin_ctzll(m); }
+  __device__ static int high(T m) { return 63 - __builtin_clzll(m); }
+};
+
 // One wave's share of LDS, for scenes of at most MD disks (32 or 64)
 template <int MD>
 struct EdgeWave {
   float4 rec[MD];                     // midpoint disk: cx, cy, outer^2, inner^2 (-1: none)
   double pp[MD][3];                   // the disk under +h: theta + h u - a tau_s
   double pm[MD][3];                   // and under -h (cx, cy[, r])
-  unsigned long long nbr[MD];         // disks whose outer boxes meet this disk's
+  typename EdgeMask<MD>::T nbr[MD];   // disks whose outer boxes meet this disk's
   float rad[MD];                      // outer radius (-1: none)
   int y0[MD];                         // first row of the disk's ring
   int off[MD + 1];                    // its first (disk, row) item; off[D] = all items
@@ -104,26 +118,29 @@ __device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k,
 template <int C, int MD>
 __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<MD>& L,
                                             const float4* s_col, const float* s_cx,
-                                            const float* s_cy, int x, int y, int k) {
+                                            const float* s_cy, const double* s_cxd, int x, int y,
+                                            int k) {
+  typedef EdgeMask<MD> M;
+  typedef typename M::T Mask;
   const float pxf = s_cx[x], pyf = s_cy[y];
-  const unsigned long long nb = L.nbr[k];
+  const Mask nb = L.nbr[k];
   // a disk above k that may cover the pixel: the pixel is in that disk's ring
   // or inside it, and is counted there (or contributes nothing)
-  unsigned long long up = k < 63 ? nb & (~0ull << (k + 1)) : 0ull;
+  Mask up = k < MD - 1 ? nb & (~Mask(0) << (k + 1)) : Mask(0);
   while (up) {
-    const int j = __builtin_ctzll(up);
+    const int j = M::low(up);
     up &= up - 1;
     const float4 v = L.rec[j];
     const float dx = pxf - v.x, dy = pyf - v.y;
     if (fmaf(dy, dy, dx * dx) < v.z) return 0.0f;
   }
   // the top disk below k that surely covers the pixel (-1: the background)
-  const unsigned long long below = nb & ((1ull << k) - 1ull);
-  unsigned long long dn = below;
+  const Mask below = nb & ((Mask(1) << k) - Mask(1));
+  Mask dn = below;
   int ks = -1;
   while (dn) {
-    const int j = 63 - __builtin_clzll(dn);
-    dn &= ~(1ull << j);
+    const int j = M::high(dn);
+    dn &= ~(Mask(1) << j);
     const float4 v = L.rec[j];
     const float dx = pxf - v.x, dy = pyf - v.y;
     if (fmaf(dy, dy, dx * dx) < v.w) { ks = j; break; }
@@ -131,8 +148,8 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<M
   // exact decisions, from k down: k first (it may cover the pixel), then the
   // disks between ks and k that may (their FP32 test against the outer
   // radius rules out the others for both shifts)
-  const double pxd = ((double)x + 0.5) / (double)a.W;
-  const double pyd = ((double)y + 0.5) / (double)a.H;
+  const double pxd = s_cxd ? s_cxd[x] : ((double)x + 0.5) / (double)a.W;
+  const double pyd = s_cxd ? s_cxd[a.W + y] : ((double)y + 0.5) / (double)a.H;
   int top_p = ks, top_m = ks;
   bool done_p = false, done_m = false;
   auto exact = [&](int j) {
@@ -144,10 +161,10 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<M
     if (!done_m && rm > 0.0 && dxm * dxm + dym * dym < rm * rm) { top_m = j; done_m = true; }
   };
   exact(k);
-  unsigned long long cand = ks < 0 ? below : below & ~((2ull << ks) - 1ull);
-  while (cand != 0ull && !(done_p && done_m)) {
-    const int j = 63 - __builtin_clzll(cand);
-    cand &= ~(1ull << j);
+  Mask cand = ks < 0 ? below : below & ~((Mask(2) << ks) - Mask(1));
+  while (cand != Mask(0) && !(done_p && done_m)) {
+    const int j = M::high(cand);
+    cand &= ~(Mask(1) << j);
     const float4 v = L.rec[j];
     const float dx = pxf - v.x, dy = pyf - v.y;
     if (!(fmaf(dy, dy, dx * dx) < v.z)) continue;   // neither shift covers
@@ -173,7 +190,7 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<M
 template <int C, int MD>
 __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWave<MD>& L,
                                           const float4* s_col, const float* s_cx,
-                                          const float* s_cy) {
+                                          const float* s_cy, const double* s_cxd) {
   const int lane = threadIdx.x & 63;
   const int D = a.D, W = a.W, H = a.H;
   // lane k: disk k's record, parameters, outer radius and ring rows
@@ -209,7 +226,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     const int k = halves ? (lane & 31) : lane;
     const int j0 = halves && lane >= 32 ? (D + 1) / 2 : 0;
     const int j1 = halves && lane < 32 ? (D + 1) / 2 : D;
-    unsigned long long m = 0ull;
+    typename EdgeMask<MD>::T m = 0;
     if (k < D) {
       const float4 vk = L.rec[k];
       const float rk = L.rad[k];
@@ -220,7 +237,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
           const float reach = rj + rk + 2.0f * kEdgeEps;
           const bool meet = j != k && rj > 0.0f && fabsf(vj.x - vk.x) <= reach &&
                             fabsf(vj.y - vk.y) <= reach;
-          m |= meet ? (1ull << j) : 0ull;
+          m |= meet ? (typename EdgeMask<MD>::T(1) << j) : 0;
         }
     }
     if (halves) m |= __shfl_xor(m, 32, 64);
@@ -234,7 +251,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     float c = 0.0f;
     if (lane < cnt_q) {
       const uint32_t xy = L.q_xy[lane];
-      c = edge_pixel<C, MD>(a, L, s_col, s_cx, s_cy, (int)(xy & 0xffffu), (int)(xy >> 16),
+      c = edge_pixel<C, MD>(a, L, s_col, s_cx, s_cy, s_cxd, (int)(xy & 0xffffu), (int)(xy >> 16),
                         (int)L.q_k[lane]);
     }
     sum += c;
@@ -324,19 +341,24 @@ __device__ __forceinline__ void edge_colours(const PairQuery& a, float4* s_col) 
 }
 
 // the FP32 pixel centres (x + 1/2) / W and (y + 1/2) / H, as the per-render
-// rasteriser computes them, in the block's LDS (W + H <= kEdgeTab)
-__device__ __forceinline__ void edge_centres(int W, int H, float* s_cx, float* s_cy) {
+// rasteriser computes them, in the block's LDS (W + H <= kEdgeTab), and, if
+// s_cxd is given, the FP64 ones of the exact test (W x-centres, then H)
+__device__ __forceinline__ void edge_centres(int W, int H, float* s_cx, float* s_cy,
+                                             double* s_cxd) {
   for (int t = threadIdx.x; t < W + H; t += blockDim.x) {
     if (t < W) s_cx[t] = ((float)t + 0.5f) / (float)W;
     else s_cy[t - W] = ((float)(t - W) + 0.5f) / (float)H;
+    if (s_cxd) s_cxd[t] = t < W ? ((double)t + 0.5) / (double)W : ((double)(t - W) + 0.5) / (double)H;
   }
 }
 
-// LDS layout of a block: colour table, four waves' shares, pixel centres
+// LDS layout of a block: colour table, four waves' shares, FP32 pixel
+// centres, and with up to 32 disks (room to spare) the FP64 ones too
 template <int MD>
 __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
-  return (size_t)(MD + 1) * sizeof(float4) + 4 * sizeof(EdgeWave<MD>) +
-         (size_t)(W + H) * sizeof(float);
+  const size_t f = (size_t)(MD + 1) * sizeof(float4) + 4 * sizeof(EdgeWave<MD>) +
+                   (size_t)(W + H) * sizeof(float);
+  return MD == 32 ? ((f + 7) & ~(size_t)7) + (size_t)(W + H) * sizeof(double) : f;
 }
 
 // Up to 32 disks the block's LDS (16.8 KB) leaves room for 7 waves per
@@ -352,12 +374,14 @@ void k_raster_dloss(PairQuery a) {
   EdgeWave<MD>* s_w = (EdgeWave<MD>*)(smem + MD + 1);
   float* s_cx = (float*)(s_w + 4);
   float* s_cy = s_cx + a.W;
+  double* s_cxd = nullptr;
+  if (MD == 32) s_cxd = (double*)(((uintptr_t)(s_cy + a.H) + 7) & ~(uintptr_t)7);
   edge_colours(a, s_col);
-  edge_centres(a.W, a.H, s_cx, s_cy);
+  edge_centres(a.W, a.H, s_cx, s_cy, s_cxd);
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   for (uint64_t p = (uint64_t)blockIdx.x * 4 + wave; p < a.L; p += (uint64_t)gridDim.x * 4)
-    edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy);
+    edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy, s_cxd);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -431,10 +455,10 @@ void k_batch_dloss(const BatchTable* __restrict__ T) {
       float* s_cy = s_cx + a.W;
       __syncthreads();   // the previous item's readers of the tables are done
       edge_colours(a, s_col);
-      edge_centres(a.W, a.H, s_cx, s_cy);
+      edge_centres(a.W, a.H, s_cx, s_cy, nullptr);
       __syncthreads();
       for (uint64_t p = p0 + wave; p < p1; p += 4)
-        edge_pair<C, kEdgeDisks>(a, p, s_w[wave], s_col, s_cx, s_cy);
+        edge_pair<C, kEdgeDisks>(a, p, s_w[wave], s_col, s_cx, s_cy, nullptr);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
