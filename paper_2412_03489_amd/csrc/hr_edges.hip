@@ -67,14 +67,19 @@ template <> struct EdgeMask<64> {
 template <int MD>
 struct EdgeWave {
   float4 rec[MD];                     // midpoint disk: cx, cy, outer^2, inner^2 (-1: none)
-  double pp[MD][3];                   // the disk under +h: theta + h u - a tau_s
-  double pm[MD][3];                   // and under -h (cx, cy[, r])
-  typename EdgeMask<MD>::T nbr[MD];   // disks whose outer boxes meet this disk's
+  // the disk under +h (theta + h u - a tau_s) and under -h: cx, cy and r^2
+  // (-1 where r <= 0: no pixel is covered)
+  double pp[MD][3];
+  double pm[MD][3];
+  // disks whose outer boxes meet this disk's, per quadrant of its box that
+  // they reach: [dx >= 0 | (dy >= 0) << 1] for a pixel at (dx, dy) from its
+  // centre
+  typename EdgeMask<MD>::T nbr[MD][4];
   float rad[MD];                      // outer radius (-1: none)
   int y0[MD];                         // first row of the disk's ring
   int off[MD + 1];                    // its first (disk, row) item; off[D] = all items
   uint32_t q_xy[kEdgeQueue];          // queued ring pixel: x | y << 16
-  uint32_t q_k[kEdgeQueue];           // and the disk whose ring holds it
+  uint32_t q_k[kEdgeQueue];           // and the disk whose ring holds it | quadrant << 8
 };
 
 // Disk k of pair p: its midpoint record and its FP64 parameters under both
@@ -87,14 +92,21 @@ __device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k,
   const uint64_t sidx = a.A == 2 ? p >> 1 : p;
   const double* t = a.tau + sidx * (uint64_t)a.n;
   const double sa = ai == 0 ? 1.0 : -1.0;
-  double m[3] = {0.0, 0.0, 0.0};
+  double m[3] = {0.0, 0.0, 0.0}, vp[3], vm[3];
   for (int q = 0; q < ppd; ++q) {
     const int j = k * ppd + q;
     const double th = a.theta[j], uj = a.u[j], tj = t[j];
     m[q] = th - sa * tj;
-    L.pp[k][q] = (th + a.h * uj) - sa * tj;
-    L.pm[k][q] = (th + (-a.h) * uj) - sa * tj;
+    vp[q] = (th + a.h * uj) - sa * tj;
+    vm[q] = (th + (-a.h) * uj) - sa * tj;
   }
+  if (ppd != 3) vp[2] = vm[2] = (double)a.radius[k];
+  L.pp[k][0] = vp[0];
+  L.pp[k][1] = vp[1];
+  L.pp[k][2] = vp[2] > 0.0 ? vp[2] * vp[2] : -1.0;
+  L.pm[k][0] = vm[0];
+  L.pm[k][1] = vm[1];
+  L.pm[k][2] = vm[2] > 0.0 ? vm[2] * vm[2] : -1.0;
   const double rad = ppd == 3 ? m[2] : (double)a.radius[k];
   const double ux = a.u[k * ppd], uy = a.u[k * ppd + 1], ur = ppd == 3 ? a.u[k * ppd + 2] : 0.0;
   const double e = a.h * (sqrt(ux * ux + uy * uy) + fabs(ur));
@@ -119,11 +131,13 @@ template <int C, int MD>
 __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<MD>& L,
                                             const float4* s_col, const float* s_cx,
                                             const float* s_cy, const double* s_cxd, int x, int y,
-                                            int k) {
+                                            int k, int quad) {
   typedef EdgeMask<MD> M;
   typedef typename M::T Mask;
   const float pxf = s_cx[x], pyf = s_cy[y];
-  const Mask nb = L.nbr[k];
+  // only the neighbours that reach the pixel's quadrant of disk k's box can
+  // cover it
+  const Mask nb = L.nbr[k][quad];
   // a disk above k that may cover the pixel: the pixel is in that disk's ring
   // or inside it, and is counted there (or contributes nothing)
   Mask up = k < MD - 1 ? nb & (~Mask(0) << (k + 1)) : Mask(0);
@@ -153,12 +167,10 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<M
   int top_p = ks, top_m = ks;
   bool done_p = false, done_m = false;
   auto exact = [&](int j) {
-    const double rp = a.ppd == 3 ? L.pp[j][2] : (double)a.radius[j];
-    const double rm = a.ppd == 3 ? L.pm[j][2] : (double)a.radius[j];
     const double dxp = pxd - L.pp[j][0], dyp = pyd - L.pp[j][1];
     const double dxm = pxd - L.pm[j][0], dym = pyd - L.pm[j][1];
-    if (!done_p && rp > 0.0 && dxp * dxp + dyp * dyp < rp * rp) { top_p = j; done_p = true; }
-    if (!done_m && rm > 0.0 && dxm * dxm + dym * dym < rm * rm) { top_m = j; done_m = true; }
+    if (!done_p && dxp * dxp + dyp * dyp < L.pp[j][2]) { top_p = j; done_p = true; }
+    if (!done_m && dxm * dxm + dym * dym < L.pm[j][2]) { top_m = j; done_m = true; }
   };
   exact(k);
   Mask cand = ks < 0 ? below : below & ~((Mask(2) << ks) - Mask(1));
@@ -219,14 +231,17 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
   if (lane == D - 1) L.off[D] = incl;
   const int total = __shfl(incl, 63, 64);
   __builtin_amdgcn_wave_barrier();
-  // the disks whose outer boxes meet disk k's: up to 32 disks lanes k and
+  // the disks whose outer boxes meet disk k's, per quadrant of disk k's box
+  // that they reach (a disk that may cover a pixel at x >= cx_k reaches
+  // cx_j + r_j + slack >= cx_k, and so on): up to 32 disks lanes k and
   // k + 32 test half of them each, else lane k tests all
   {
+    typedef typename EdgeMask<MD>::T Mask;
     const bool halves = D <= 32;
     const int k = halves ? (lane & 31) : lane;
     const int j0 = halves && lane >= 32 ? (D + 1) / 2 : 0;
     const int j1 = halves && lane < 32 ? (D + 1) / 2 : D;
-    typename EdgeMask<MD>::T m = 0;
+    Mask m[4] = {0, 0, 0, 0};
     if (k < D) {
       const float4 vk = L.rec[k];
       const float rk = L.rad[k];
@@ -237,11 +252,21 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
           const float reach = rj + rk + 2.0f * kEdgeEps;
           const bool meet = j != k && rj > 0.0f && fabsf(vj.x - vk.x) <= reach &&
                             fabsf(vj.y - vk.y) <= reach;
-          m |= meet ? (typename EdgeMask<MD>::T(1) << j) : 0;
+          const Mask bit = meet ? Mask(1) << j : Mask(0);
+          const float rs = rj + 2.0f * kEdgeEps;
+          const bool east = vj.x + rs >= vk.x, west = vj.x - rs <= vk.x;
+          const bool north = vj.y + rs >= vk.y, south = vj.y - rs <= vk.y;
+          m[0] |= west && south ? bit : Mask(0);
+          m[1] |= east && south ? bit : Mask(0);
+          m[2] |= west && north ? bit : Mask(0);
+          m[3] |= east && north ? bit : Mask(0);
         }
     }
-    if (halves) m |= __shfl_xor(m, 32, 64);
-    if (lane < D) L.nbr[lane] = m;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (halves) m[q] |= __shfl_xor(m[q], 32, 64);
+      if (lane < D) L.nbr[lane][q] = m[q];
+    }
   }
   __builtin_amdgcn_wave_barrier();
 
@@ -251,8 +276,9 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     float c = 0.0f;
     if (lane < cnt_q) {
       const uint32_t xy = L.q_xy[lane];
+      const uint32_t kq = L.q_k[lane];
       c = edge_pixel<C, MD>(a, L, s_col, s_cx, s_cy, s_cxd, (int)(xy & 0xffffu), (int)(xy >> 16),
-                        (int)L.q_k[lane]);
+                            (int)(kq & 0xffu), (int)(kq >> 8));
     }
     sum += c;
     // the rest of the queue to the front
@@ -300,17 +326,19 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       const bool act = x <= xe;
       if (__builtin_amdgcn_ballot_w64(act) == 0ull) break;
       bool ring = false;
+      uint32_t quad = 0;
       if (act) {
         const float dx = s_cx[x] - v.x;
         const float d2 = fmaf(dy, dy, dx * dx);
         ring = d2 < v.z && !(d2 < v.w);
+        quad = (dx >= 0.0f ? 1u : 0u) | (dy >= 0.0f ? 2u : 0u);
       }
       const uint64_t b = __builtin_amdgcn_ballot_w64(ring);
       if (ring) {
         const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)b, qlen));
         L.q_xy[pos] = (uint32_t)x | ((uint32_t)y << 16);
-        L.q_k[pos] = (uint32_t)k;
+        L.q_k[pos] = (uint32_t)k | quad << 8;
       }
       qlen += (uint32_t)__builtin_popcountll(b);
       __builtin_amdgcn_wave_barrier();
@@ -361,10 +389,11 @@ __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
   return MD == 32 ? ((f + 7) & ~(size_t)7) + (size_t)(W + H) * sizeof(double) : f;
 }
 
-// Up to 32 disks the block's LDS (16.8 KB) leaves room for 7 waves per
-// SIMD, and the kernel, latency-bound on its LDS and FP64 chains at 5, runs
-// faster at 7 (72 VGPRs, a few values spilled: 1.55 -> 1.33-1.39 ms per
-// disks32 HVP launch; 6: 1.40, 8: 1.34); with 64 disks the LDS allows 5.
+// Up to 32 disks the block's LDS (22.1 KB at 256 x 256) leaves room for 7
+// waves per SIMD, and the kernel, latency-bound on its LDS and FP64 chains
+// at 5, runs faster at 7 (72 VGPRs, a few values spilled; per disks32 HVP
+// launch 1.17-1.18 ms, against 1.25 at 6 and 1.22 at 8); with 64 disks the
+// LDS allows 5.
 template <int C, int MD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MD == 32 ? 7 : 1)))
 void k_raster_dloss(PairQuery a) {
