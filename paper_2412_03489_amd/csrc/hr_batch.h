@@ -35,10 +35,14 @@ struct BatchSlot {
   void* ws = nullptr;              // query workspaces, back to back
   size_t ws_bytes = 0;
   hipGraphExec_t exec = nullptr;   // the captured launch sequence
-  size_t exec_lds = 0, exec_lds_pair = 0;
+  size_t exec_lds = 0, exec_lds_pair = 0, exec_lds_pair32 = 0;
   unsigned exec_classes = 0;       // render classes launched by the captured sequence
   size_t lds = 0;                  // dynamic LDS of the persistent rasteriser
-  size_t lds_pair = 0;             // and of its render-pair classes
+  size_t lds_pair = 0;             // and of its render-pair classes (64-disk layout,
+  size_t lds_pair32 = 0;           //   32-disk layout)
+  size_t class_lds(int c) const {
+    return !raster_is_pair_class(c) ? lds : (c >= raster_pair_class(1, 32) ? lds_pair32 : lds_pair);
+  }
   bool graph_used = false;
   bool allow_timing = true;        // phase timers (batch entry point only)
   int nq_ = 0;

@@ -180,6 +180,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   std::vector<int> qS(nq, 0), qshape(nq, 0);
   lds = 0;
   lds_pair = 0;
+  lds_pair32 = 0;
   for (int q = 0; q < nq; ++q) {
     const QueryPlan& p = items[q].plan;
     const hr_scene* sc = p.sc;
@@ -193,7 +194,8 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
         qS[q] = p.o.samples_per_block > 0
                     ? std::max(4, p.o.samples_per_block / 2)
                     : (int)std::min<uint64_t>(32, std::max<uint64_t>(4, 4 * (p.e.L / 16384)));
-        lds_pair = std::max(lds_pair, raster_pair_lds_bytes(sc->W, sc->H));
+        size_t& lp = sc->D <= 32 ? lds_pair32 : lds_pair;
+        lp = std::max(lp, raster_pair_lds_bytes(sc->W, sc->H, sc->D));
       } else {
         lds = std::max(lds, raster_lds_bytes(sc->D, qS[q]));
       }
@@ -229,7 +231,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
       a = RasterQuery{};
       a.W = sc->W; a.H = sc->H; a.C = sc->C; a.D = sc->D; a.S = qS[q];
       raster_geometry(a, qshape[q]);
-      const int cls = p.e.pair ? raster_pair_class(sc->C) : raster_class(sc->C, sc->D);
+      const int cls = p.e.pair ? raster_pair_class(sc->C, sc->D) : raster_class(sc->C, sc->D);
       // a pair item covers the whole image
       add_segments(rq[cls], rchunks[cls], q, (p.e.L + qS[q] - 1) / qS[q], p.e.pair ? 1 : a.tiles);
     } else if (sc->kind == kPT) {
@@ -383,6 +385,7 @@ hr_status BatchSlot::build(std::vector<BatchItem>& items) {
   lds = std::max(lds, (size_t)1024);
   lds = (lds + 4095) & ~size_t(4095);   // LDS classes of 4 KiB keep the graph reusable
   lds_pair = (std::max(lds_pair, (size_t)1024) + 4095) & ~size_t(4095);
+  lds_pair32 = (std::max(lds_pair32, (size_t)1024) + 4095) & ~size_t(4095);
   return HR_OK;
 }
 
@@ -414,7 +417,7 @@ void BatchSlot::launches(hipStream_t st, bool time_phases) {
   run("batch_raster", [&] {
     for (int c = 0; c < kRasterClasses; ++c)
       if (cl & (1u << c))
-        launch_batch_raster(st, T, c, raster_blocks[c], c >= raster_pair_class(1) ? lds_pair : lds);
+        launch_batch_raster(st, T, c, raster_blocks[c], class_lds(c));
   });
   run("batch_pt", [&] {
     for (int c = 0; c < 3; ++c)
@@ -441,15 +444,15 @@ hr_status BatchSlot::enqueue(bool use_graph, bool timing_ok) {
   const unsigned cl = classes();
   for (int c = 0; c < kRasterClasses; ++c)
     if (cl & (1u << c))
-      raster_blocks[c] =
-          cus * batch_raster_blocks_per_cu(c, c >= raster_pair_class(1) ? lds_pair : lds);
+      raster_blocks[c] = cus * batch_raster_blocks_per_cu(c, class_lds(c));
   HR_HIP(hipMemcpyAsync(dev, host, upload_bytes_, hipMemcpyHostToDevice, stream));
   graph_used = false;
   const bool timing = allow_timing && timing_ok && ctx->timing;
   // a one-query batch launches its per-query kernels directly: their launch
   // parameters are the query's own, so a captured sequence would not be reusable
   if (use_graph && !timing && !single_) {
-    if (exec && (exec_lds != lds || exec_lds_pair != lds_pair || exec_classes != cl)) {
+    if (exec && (exec_lds != lds || exec_lds_pair != lds_pair || exec_lds_pair32 != lds_pair32 ||
+                 exec_classes != cl)) {
       (void)hipGraphExecDestroy(exec);
       exec = nullptr;
     }
@@ -466,6 +469,7 @@ hr_status BatchSlot::enqueue(bool use_graph, bool timing_ok) {
       }
       exec_lds = lds;
       exec_lds_pair = lds_pair;
+      exec_lds_pair32 = lds_pair32;
       exec_classes = cl;
     }
     HR_HIP(hipGraphLaunch(exec, stream));
@@ -543,7 +547,7 @@ hr_status autotune_raster(BatchSlot& slot, const std::vector<BatchItem>& items) 
           if (hipEventRecord(a, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }
           for (int c = 0; c < kRasterClasses; ++c) {
             if (!(cl & (1u << c))) continue;
-            const size_t l = c >= raster_pair_class(1) ? slot.lds_pair : slot.lds;
+            const size_t l = slot.class_lds(c);
             launch_batch_raster(slot.stream, T, c, slot.cus * batch_raster_blocks_per_cu(c, l), l);
           }
           if (hipEventRecord(b, slot.stream) != hipSuccess) { st = fail(HR_EDEVICE, "event"); break; }

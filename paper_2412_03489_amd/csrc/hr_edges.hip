@@ -420,24 +420,26 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 }
 
 // Persistent form over the eight work queues of one pair class (channel
-// count): an item is (query, chunk of S pairs); blocks start on the queue of
-// their XCD, claim items by one atomic increment each (the next one before
-// working on the current one), move on to the other queues when theirs is
-// empty, and leave after seeing all eight exhausted.
-// the 64-disk layout's LDS allows 5 blocks of four waves per CU: registers
-// for 5 waves per SIMD
-template <int C>
+// count and LDS layout; the 32-disk layout's queues hold scenes of up to 32
+// disks only): an item is (query, chunk of S pairs); blocks start on the
+// queue of their XCD, claim items by one atomic increment each (the next one
+// before working on the current one), move on to the other queues when
+// theirs is empty, and leave after seeing all eight exhausted.
+// Registers for 5 waves per SIMD with either layout: the LDS of the largest
+// query of the batch decides the blocks per CU, and with 32 disks asking for
+// 7 (more spills) or 6 was no faster on the 64 uneven instances.
+template <int C, int MD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 void k_batch_dloss(const BatchTable* __restrict__ T) {
   extern __shared__ float4 smem[];
   __shared__ unsigned long long s_item;
-  const WorkQueues& W = T->raster[raster_pair_class(C)];
+  const WorkQueues& W = T->raster[raster_pair_class(C, MD)];
   const int home = blockIdx.x & 7;
   uint64_t all = 0;
   for (int x = 0; x < 8; ++x) all += W.items[x];
   if (all == 0) return;   // nothing of this kind in the batch
   float4* s_col = smem;
-  EdgeWave<kEdgeDisks>* s_w = (EdgeWave<kEdgeDisks>*)(smem + kEdgeDisks + 1);
+  EdgeWave<MD>* s_w = (EdgeWave<MD>*)(smem + MD + 1);
   float* s_cx = (float*)(s_w + 4);
   const int wave = threadIdx.x >> 6;
   for (int kq = 0; kq < 8; ++kq) {
@@ -482,12 +484,14 @@ void k_batch_dloss(const BatchTable* __restrict__ T) {
       const uint64_t p0 = chunk * (uint64_t)a.S;
       const uint64_t p1 = umin64(p0 + (uint64_t)a.S, a.L);
       float* s_cy = s_cx + a.W;
+      double* s_cxd = nullptr;
+      if (MD == 32) s_cxd = (double*)(((uintptr_t)(s_cy + a.H) + 7) & ~(uintptr_t)7);
       __syncthreads();   // the previous item's readers of the tables are done
       edge_colours(a, s_col);
-      edge_centres(a.W, a.H, s_cx, s_cy, nullptr);
+      edge_centres(a.W, a.H, s_cx, s_cy, s_cxd);
       __syncthreads();
       for (uint64_t p = p0 + wave; p < p1; p += 4)
-        edge_pair<C, kEdgeDisks>(a, p, s_w[wave], s_col, s_cx, s_cy, nullptr);
+        edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy, s_cxd);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
@@ -498,8 +502,11 @@ void k_batch_dloss(const BatchTable* __restrict__ T) {
 
 }  // namespace
 
-// the persistent kernel serves every pair query of its class: the 64-disk layout
-size_t raster_pair_lds_bytes(int W, int H) { return edge_lds_bytes<kEdgeDisks>(W, H); }
+// LDS of a pair query in the persistent kernel of its class (the layout by
+// disk count, as raster_pair_class assigns it)
+size_t raster_pair_lds_bytes(int W, int H, int D) {
+  return D <= 32 ? edge_lds_bytes<32>(W, H) : edge_lds_bytes<kEdgeDisks>(W, H);
+}
 
 int raster_pair_max_side_sum() { return kEdgeTab; }
 
@@ -526,22 +533,26 @@ void launch_raster_dloss(hipStream_t st, const PairQuery& a) {
 }
 
 typedef void (*BatchDlossKernel)(const BatchTable*);
-static BatchDlossKernel batch_dloss_kernel(int C) {
-  switch (C) {
-    case 1: return k_batch_dloss<1>;
-    case 2: return k_batch_dloss<2>;
-    case 3: return k_batch_dloss<3>;
-    default: return k_batch_dloss<4>;
+static BatchDlossKernel batch_dloss_kernel(int cls) {
+  switch (cls) {
+    case raster_pair_class(1, 64): return k_batch_dloss<1, 64>;
+    case raster_pair_class(2, 64): return k_batch_dloss<2, 64>;
+    case raster_pair_class(3, 64): return k_batch_dloss<3, 64>;
+    case raster_pair_class(4, 64): return k_batch_dloss<4, 64>;
+    case raster_pair_class(1, 32): return k_batch_dloss<1, 32>;
+    case raster_pair_class(2, 32): return k_batch_dloss<2, 32>;
+    case raster_pair_class(3, 32): return k_batch_dloss<3, 32>;
+    default: return k_batch_dloss<4, 32>;
   }
 }
 
-void launch_batch_dloss(hipStream_t st, const BatchTable* T, int C, int blocks, size_t lds) {
-  hipLaunchKernelGGL(batch_dloss_kernel(C), dim3(blocks), dim3(256), lds, st, T);
+void launch_batch_dloss(hipStream_t st, const BatchTable* T, int cls, int blocks, size_t lds) {
+  hipLaunchKernelGGL(batch_dloss_kernel(cls), dim3(blocks), dim3(256), lds, st, T);
 }
 
-int batch_dloss_blocks_per_cu(int C, size_t lds) {
+int batch_dloss_blocks_per_cu(int cls, size_t lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_dloss_kernel(C), 256, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_dloss_kernel(cls), 256, lds) !=
       hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;

@@ -130,7 +130,7 @@ struct PairQuery {
   const int* skip;           // as EstShape::skip
 };
 void launch_raster_dloss(hipStream_t st, const PairQuery& a);
-size_t raster_pair_lds_bytes(int W, int H);
+size_t raster_pair_lds_bytes(int W, int H, int D);
 // largest disk count, and largest W + H, of the pair path (larger scenes
 // render the HVP per render)
 int raster_pair_max_disks();
@@ -232,10 +232,13 @@ enum BatchPhase { kPhSample = 0, kPhRecords, kPhAnalytic, kPhReduce, kPhPrep, kP
 // Raster items are queued by class -- channel count and whether all disks
 // fit one wavefront -- and each class has its own persistent kernel, which
 // holds only that variant's registers.
-constexpr int kRasterClasses = 12;
+constexpr int kRasterClasses = 16;
 __host__ __device__ inline int raster_class(int C, int D) { return (C - 1) * 2 + (D > 64 ? 1 : 0); }
-// HVP render pairs (at most 64 disks) by channel count
-__host__ __device__ inline int raster_pair_class(int C) { return 8 + (C - 1); }
+// HVP render pairs (at most 64 disks) by channel count and LDS layout:
+// 8..11 the 64-disk layout, 12..15 the 32-disk one, which serves scenes of up
+// to 32 disks only
+__host__ __device__ constexpr int raster_pair_class(int C, int D) { return (D <= 32 ? 12 : 8) + (C - 1); }
+__host__ __device__ constexpr bool raster_is_pair_class(int cls) { return cls >= 8; }
 constexpr int kWorkCounters = 8 * (kRasterClasses + 3);   // 8 per queue set
 
 struct BatchTable {
@@ -284,8 +287,8 @@ void launch_batch_finalize(hipStream_t st, const BatchTable* T, int blocks);
 // occupancy of the persistent raster kernel (blocks per CU) for a given LDS size
 int batch_raster_blocks_per_cu(int cls, size_t lds);
 // the persistent form of the render-pair kernel, by channel count C
-void launch_batch_dloss(hipStream_t st, const BatchTable* T, int C, int blocks, size_t lds);
-int batch_dloss_blocks_per_cu(int C, size_t lds);
+void launch_batch_dloss(hipStream_t st, const BatchTable* T, int cls, int blocks, size_t lds);
+int batch_dloss_blocks_per_cu(int cls, size_t lds);
 int batch_pt_blocks_per_cu(int nr);
 // path tracer constants for device-resident scenes
 size_t pt_const_bytes();

@@ -726,14 +726,14 @@ static BatchRasterKernel batch_raster_kernel(int cls) {
 }
 // classes 8.. are the HVP render pairs (hr_edges.hip), by channel count
 void launch_batch_raster(hipStream_t st, const BatchTable* T, int cls, int blocks, size_t lds) {
-  if (cls >= raster_pair_class(1)) {
-    launch_batch_dloss(st, T, cls - raster_pair_class(1) + 1, blocks, lds);
+  if (raster_is_pair_class(cls)) {
+    launch_batch_dloss(st, T, cls, blocks, lds);
     return;
   }
   hipLaunchKernelGGL(batch_raster_kernel(cls), dim3(blocks), dim3(256), lds, st, T);
 }
 int batch_raster_blocks_per_cu(int cls, size_t lds) {
-  if (cls >= raster_pair_class(1)) return batch_dloss_blocks_per_cu(cls - raster_pair_class(1) + 1, lds);
+  if (raster_is_pair_class(cls)) return batch_dloss_blocks_per_cu(cls, lds);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_raster_kernel(cls), 256, lds) !=
       hipSuccess)
