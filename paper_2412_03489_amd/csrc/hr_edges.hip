@@ -391,9 +391,8 @@ __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
 
 // Up to 32 disks the block's LDS (22.1 KB at 256 x 256) leaves room for 7
 // waves per SIMD, and the kernel, latency-bound on its LDS and FP64 chains
-// at 5, runs faster at 7 (72 VGPRs, a few values spilled; per disks32 HVP
-// launch 1.17-1.18 ms, against 1.25 at 6 and 1.22 at 8); with 64 disks the
-// LDS allows 5.
+// at 5, runs faster at 7 (54 VGPRs, no spills); with 64 disks the LDS
+// allows 5.
 template <int C, int MD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MD == 32 ? 7 : 1)))
 void k_raster_dloss(PairQuery a) {
@@ -408,9 +407,11 @@ void k_raster_dloss(PairQuery a) {
   edge_colours(a, s_col);
   edge_centres(a.W, a.H, s_cx, s_cy, s_cxd);
   __syncthreads();
+  // one pair per wave, no loop: values set up for the pair die with it
+  // instead of living across a loop (which costs spilled registers)
   const int wave = threadIdx.x >> 6;
-  for (uint64_t p = (uint64_t)blockIdx.x * 4 + wave; p < a.L; p += (uint64_t)gridDim.x * 4)
-    edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy, s_cxd);
+  const uint64_t p = ((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wave;
+  if (p < a.L) edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy, s_cxd);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -515,9 +516,10 @@ int raster_pair_max_disks() { return kEdgeDisks; }
 template <int MD>
 static void launch_dloss_md(hipStream_t st, const PairQuery& a) {
   const size_t lds = edge_lds_bytes<MD>(a.W, a.H);
-  // one wave per pair; the grid strides over the rest
-  const uint64_t blocks = umin64((a.L + 3) / 4, 1ull << 20);
-  const dim3 grid((unsigned)(blocks > 0 ? blocks : 1));
+  // one wave per pair: rows of up to 2^20 blocks
+  const uint64_t blocks = std::max<uint64_t>((a.L + 3) / 4, 1);
+  const uint64_t gx = umin64(blocks, 1ull << 20);
+  const dim3 grid((unsigned)gx, (unsigned)((blocks + gx - 1) / gx));
   switch (a.C) {
     case 1: hipLaunchKernelGGL((k_raster_dloss<1, MD>), grid, dim3(256), lds, st, a); break;
     case 2: hipLaunchKernelGGL((k_raster_dloss<2, MD>), grid, dim3(256), lds, st, a); break;
