@@ -48,6 +48,7 @@ constexpr int kEdgeQueue = 128;   // queued ring pixels: fewer than 64 + one ste
 constexpr float kEdgeEps = 2e-5f;
 // pixel centres of images with W + H up to this are tabulated in LDS per block
 constexpr int kEdgeTab = 2048;
+static_assert(kEdgeTab <= 2048 && kEdgeDisks <= 64, "a queued pixel packs x, y and k in 28 bits");
 
 // Bit masks over the disks: 32-bit words up to 32 disks (single-instruction
 // bit scans), else 64-bit
@@ -75,11 +76,11 @@ struct EdgeWave {
   // they reach: [dx >= 0 | (dy >= 0) << 1] for a pixel at (dx, dy) from its
   // centre
   typename EdgeMask<MD>::T nbr[MD][4];
-  float rad[MD];                      // outer radius (-1: none)
   int y0[MD];                         // first row of the disk's ring
   int off[MD + 1];                    // its first (disk, row) item; off[D] = all items
-  uint32_t q_xy[kEdgeQueue];          // queued ring pixel: x | y << 16
-  uint32_t q_k[kEdgeQueue];           // and the disk whose ring holds it | quadrant << 8
+  // queued ring pixel: x | y << 11 | disk whose ring holds it << 22 |
+  // quadrant << 28 (W, H < 2048)
+  uint32_t q[kEdgeQueue];
 };
 
 // Disk k of pair p: its midpoint record and its FP64 parameters under both
@@ -119,9 +120,12 @@ __device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k,
     if (rm > 0.0) out.w = (float)(rm * rm - band);
   }
   L.rec[k] = out;
-  // the hardware square root (within 1 ulp): the bounds built on it carry
-  // kEdgeEps of slack
-  L.rad[k] = out.z > 0.0f ? __builtin_amdgcn_sqrtf(out.z) : -1.0f;
+}
+
+// outer radius of a record (-1: none): the hardware square root (within 1
+// ulp); the bounds built on it carry kEdgeEps of slack
+__device__ __forceinline__ float edge_rad(const float4& v) {
+  return v.z > 0.0f ? __builtin_amdgcn_sqrtf(v.z) : -1.0f;
 }
 
 // One ring pixel of disk k: the top disk under each shift, and the pixel's
@@ -211,7 +215,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     edge_disk(a, p, lane, L);
     const float4 v = L.rec[lane];
     if (v.z > 0.0f) {
-      const float R = L.rad[lane];
+      const float R = edge_rad(v);
       const int y0 = max(0, (int)floorf((v.y - R - kEdgeEps) * (float)H - 0.5f));
       const int y1 = min(H - 1, (int)ceilf((v.y + R + kEdgeEps) * (float)H - 0.5f));
       cnt = max(0, y1 - y0 + 1);
@@ -244,11 +248,11 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     Mask m[4] = {0, 0, 0, 0};
     if (k < D) {
       const float4 vk = L.rec[k];
-      const float rk = L.rad[k];
+      const float rk = edge_rad(vk);
       if (rk > 0.0f)
         for (int j = j0; j < j1; ++j) {
-          const float rj = L.rad[j];
           const float4 vj = L.rec[j];
+          const float rj = edge_rad(vj);
           const float reach = rj + rk + 2.0f * kEdgeEps;
           const bool meet = j != k && rj > 0.0f && fabsf(vj.x - vk.x) <= reach &&
                             fabsf(vj.y - vk.y) <= reach;
@@ -275,19 +279,17 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
   auto process = [&](int cnt_q) {
     float c = 0.0f;
     if (lane < cnt_q) {
-      const uint32_t xy = L.q_xy[lane];
-      const uint32_t kq = L.q_k[lane];
-      c = edge_pixel<C, MD>(a, L, s_col, s_cx, s_cy, s_cxd, (int)(xy & 0xffffu), (int)(xy >> 16),
-                            (int)(kq & 0xffu), (int)(kq >> 8));
+      const uint32_t e = L.q[lane];
+      c = edge_pixel<C, MD>(a, L, s_col, s_cx, s_cy, s_cxd, (int)(e & 0x7ffu),
+                            (int)((e >> 11) & 0x7ffu), (int)((e >> 22) & 0x3fu), (int)(e >> 28));
     }
     sum += c;
     // the rest of the queue to the front
     const int rest = (int)qlen - cnt_q;
     if (lane < rest) {
-      const uint32_t xy = L.q_xy[cnt_q + lane], kk = L.q_k[cnt_q + lane];
+      const uint32_t e = L.q[cnt_q + lane];
       __builtin_amdgcn_wave_barrier();
-      L.q_xy[lane] = xy;
-      L.q_k[lane] = kk;
+      L.q[lane] = e;
     }
     qlen -= (uint32_t)cnt_q;
     __builtin_amdgcn_wave_barrier();
@@ -337,8 +339,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       if (ring) {
         const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)b, qlen));
-        L.q_xy[pos] = (uint32_t)x | ((uint32_t)y << 16);
-        L.q_k[pos] = (uint32_t)k | quad << 8;
+        L.q[pos] = (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)k << 22) | quad << 28;
       }
       qlen += (uint32_t)__builtin_popcountll(b);
       __builtin_amdgcn_wave_barrier();
@@ -389,9 +390,10 @@ __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
   return MD == 32 ? ((f + 7) & ~(size_t)7) + (size_t)(W + H) * sizeof(double) : f;
 }
 
-// Up to 32 disks the block's LDS (22.1 KB at 256 x 256) leaves room for 7
-// waves per SIMD, and the kernel, latency-bound on its LDS and FP64 chains
-// at 5, runs faster at 7 (54 VGPRs, no spills); with 64 disks the LDS
+// Up to 32 disks the block's LDS (19.6 KB at 256 x 256) leaves room for 8
+// blocks of four waves per CU, and the kernel (54 VGPRs, no spills), latency-
+// bound on its LDS and FP64 chains, runs at that occupancy; the 7 asked for
+// keeps the register budget from dropping below 72.  With 64 disks the LDS
 // allows 5.
 template <int C, int MD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MD == 32 ? 7 : 1)))
