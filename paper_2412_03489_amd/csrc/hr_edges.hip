@@ -76,7 +76,6 @@ struct EdgeWave {
   // they reach: [dx >= 0 | (dy >= 0) << 1] for a pixel at (dx, dy) from its
   // centre
   typename EdgeMask<MD>::T nbr[MD][4];
-  int y0[MD];                         // first row of the disk's ring
   int off[MD + 1];                    // its first (disk, row) item; off[D] = all items
   // queued ring pixel: x | y << 11 | disk whose ring holds it << 22 |
   // quadrant << 28 (W, H < 2048)
@@ -128,17 +127,48 @@ __device__ __forceinline__ float edge_rad(const float4& v) {
   return v.z > 0.0f ? __builtin_amdgcn_sqrtf(v.z) : -1.0f;
 }
 
+// first row of a disk's ring (its outer box widened by kEdgeEps)
+__device__ __forceinline__ int edge_row0(const float4& v, float R, int H) {
+  return max(0, (int)floorf((v.y - R - kEdgeEps) * (float)H - 0.5f));
+}
+
+// Pixel centres tabulated in the block's LDS (W + H <= kEdgeTab; x-centres,
+// then y): the FP32 ones of the per-render rasteriser, ((float)x + 0.5f) / W,
+// and the FP64 ones of the exact test, (x + 0.5) / W.  The 32-disk layout
+// keeps only the FP64 table and rounds it to FP32: both divisions round
+// correctly, and the quotient (2x + 1) / 2W (W < 2^11) lies at least 2^-37
+// (relative) away from every FP32 rounding midpoint it does not equal, far
+// beyond the FP64 rounding, so the rounded FP64 centre is the FP32 centre.
+// The 64-disk layout keeps only the FP32 table and divides in FP64 where it
+// needs the exact centre.
+template <int MD>
+struct EdgeCentres {
+  const void* tab;
+  int W, H;
+  __device__ float fx(int x) const {
+    return MD == 32 ? (float)((const double*)tab)[x] : ((const float*)tab)[x];
+  }
+  __device__ float fy(int y) const {
+    return MD == 32 ? (float)((const double*)tab)[W + y] : ((const float*)tab)[W + y];
+  }
+  __device__ double dx(int x) const {
+    return MD == 32 ? ((const double*)tab)[x] : ((double)x + 0.5) / (double)W;
+  }
+  __device__ double dy(int y) const {
+    return MD == 32 ? ((const double*)tab)[W + y] : ((double)y + 0.5) / (double)H;
+  }
+};
+
 // One ring pixel of disk k: the top disk under each shift, and the pixel's
 // (I+ - T)^2 - (I- - T)^2 over the channels (0 if the pixel belongs to the
 // ring of a disk above k, which counts it instead).
 template <int C, int MD>
 __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<MD>& L,
-                                            const float4* s_col, const float* s_cx,
-                                            const float* s_cy, const double* s_cxd, int x, int y,
-                                            int k, int quad) {
+                                            const float4* s_col, const EdgeCentres<MD>& ct,
+                                            int x, int y, int k, int quad) {
   typedef EdgeMask<MD> M;
   typedef typename M::T Mask;
-  const float pxf = s_cx[x], pyf = s_cy[y];
+  const float pxf = ct.fx(x), pyf = ct.fy(y);
   // only the neighbours that reach the pixel's quadrant of disk k's box can
   // cover it
   const Mask nb = L.nbr[k][quad];
@@ -166,8 +196,7 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<M
   // exact decisions, from k down: k first (it may cover the pixel), then the
   // disks between ks and k that may (their FP32 test against the outer
   // radius rules out the others for both shifts)
-  const double pxd = s_cxd ? s_cxd[x] : ((double)x + 0.5) / (double)a.W;
-  const double pyd = s_cxd ? s_cxd[a.W + y] : ((double)y + 0.5) / (double)a.H;
+  const double pxd = ct.dx(x), pyd = ct.dy(y);
   int top_p = ks, top_m = ks;
   bool done_p = false, done_m = false;
   auto exact = [&](int j) {
@@ -205,8 +234,7 @@ __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<M
 // squared-error difference).
 template <int C, int MD>
 __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWave<MD>& L,
-                                          const float4* s_col, const float* s_cx,
-                                          const float* s_cy, const double* s_cxd) {
+                                          const float4* s_col, const EdgeCentres<MD>& ct) {
   const int lane = threadIdx.x & 63;
   const int D = a.D, W = a.W, H = a.H;
   // lane k: disk k's record, parameters, outer radius and ring rows
@@ -216,12 +244,9 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     const float4 v = L.rec[lane];
     if (v.z > 0.0f) {
       const float R = edge_rad(v);
-      const int y0 = max(0, (int)floorf((v.y - R - kEdgeEps) * (float)H - 0.5f));
+      const int y0 = edge_row0(v, R, H);
       const int y1 = min(H - 1, (int)ceilf((v.y + R + kEdgeEps) * (float)H - 0.5f));
       cnt = max(0, y1 - y0 + 1);
-      L.y0[lane] = y0;
-    } else {
-      L.y0[lane] = 0;
     }
   }
   // first item of each disk (exclusive prefix sum over the lanes)
@@ -280,7 +305,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     float c = 0.0f;
     if (lane < cnt_q) {
       const uint32_t e = L.q[lane];
-      c = edge_pixel<C, MD>(a, L, s_col, s_cx, s_cy, s_cxd, (int)(e & 0x7ffu),
+      c = edge_pixel<C, MD>(a, L, s_col, ct, (int)(e & 0x7ffu),
                             (int)((e >> 11) & 0x7ffu), (int)((e >> 22) & 0x3fu), (int)(e >> 28));
     }
     sum += c;
@@ -305,8 +330,8 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       while (L.off[k + 1] <= it) ++k;
       kcur = k;
       v = L.rec[k];
-      y = L.y0[k] + (it - L.off[k]);
-      dy = s_cy[y] - v.y;
+      y = edge_row0(v, edge_rad(v), H) + (it - L.off[k]);
+      dy = ct.fy(y) - v.y;
       const float dy2 = dy * dy;
       // |dx| < ro holds for every pixel with d^2 < outer on this row and
       // |dx| >= ri for every one with d^2 >= inner (slack: the FP32 rounding
@@ -330,7 +355,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       bool ring = false;
       uint32_t quad = 0;
       if (act) {
-        const float dx = s_cx[x] - v.x;
+        const float dx = ct.fx(x) - v.x;
         const float d2 = fmaf(dy, dy, dx * dx);
         ring = d2 < v.z && !(d2 < v.w);
         quad = (dx >= 0.0f ? 1u : 0u) | (dy >= 0.0f ? 2u : 0u);
@@ -369,32 +394,36 @@ __device__ __forceinline__ void edge_colours(const PairQuery& a, float4* s_col) 
   }
 }
 
-// the FP32 pixel centres (x + 1/2) / W and (y + 1/2) / H, as the per-render
-// rasteriser computes them, in the block's LDS (W + H <= kEdgeTab), and, if
-// s_cxd is given, the FP64 ones of the exact test (W x-centres, then H)
-__device__ __forceinline__ void edge_centres(int W, int H, float* s_cx, float* s_cy,
-                                             double* s_cxd) {
+// the block's pixel-centre table (see EdgeCentres) at tab
+template <int MD>
+__device__ __forceinline__ EdgeCentres<MD> edge_centres(int W, int H, void* tab) {
   for (int t = threadIdx.x; t < W + H; t += blockDim.x) {
-    if (t < W) s_cx[t] = ((float)t + 0.5f) / (float)W;
-    else s_cy[t - W] = ((float)(t - W) + 0.5f) / (float)H;
-    if (s_cxd) s_cxd[t] = t < W ? ((double)t + 0.5) / (double)W : ((double)(t - W) + 0.5) / (double)H;
+    const int i = t < W ? t : t - W, n = t < W ? W : H;
+    if (MD == 32) ((double*)tab)[t] = ((double)i + 0.5) / (double)n;
+    else ((float*)tab)[t] = ((float)i + 0.5f) / (float)n;
   }
+  EdgeCentres<MD> ct;
+  ct.tab = tab;
+  ct.W = W;
+  ct.H = H;
+  return ct;
 }
 
-// LDS layout of a block: colour table, four waves' shares, FP32 pixel
-// centres, and with up to 32 disks (room to spare) the FP64 ones too
+// LDS layout of a block: colour table, four waves' shares, pixel centres
+// (FP64 with up to 32 disks, else FP32)
 template <int MD>
 __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
-  const size_t f = (size_t)(MD + 1) * sizeof(float4) + 4 * sizeof(EdgeWave<MD>) +
-                   (size_t)(W + H) * sizeof(float);
-  return MD == 32 ? ((f + 7) & ~(size_t)7) + (size_t)(W + H) * sizeof(double) : f;
+  static_assert(((MD + 1) * sizeof(float4) + 4 * sizeof(EdgeWave<MD>)) % 8 == 0,
+                "the centre table starts 8-byte aligned");
+  return (size_t)(MD + 1) * sizeof(float4) + 4 * sizeof(EdgeWave<MD>) +
+         (size_t)(W + H) * (MD == 32 ? sizeof(double) : sizeof(float));
 }
 
-// Up to 32 disks the block's LDS (19.6 KB at 256 x 256) leaves room for 8
-// blocks of four waves per CU, and the kernel (54 VGPRs, no spills), latency-
-// bound on its LDS and FP64 chains, runs at that occupancy; the 7 asked for
-// keeps the register budget from dropping below 72.  With 64 disks the LDS
-// allows 5.
+// Up to 32 disks the block's LDS (17.1 KB at 256 x 256) leaves room for 9
+// blocks of four waves per CU (50 VGPRs, no spills); the kernel, latency-
+// bound on its LDS and FP64 chains, ran faster with each step from 5 to 8
+// waves per SIMD and no faster at 9.  The 7 asked for keeps the register
+// budget from dropping below 72.  With 64 disks the LDS allows 5.
 template <int C, int MD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MD == 32 ? 7 : 1)))
 void k_raster_dloss(PairQuery a) {
@@ -402,18 +431,14 @@ void k_raster_dloss(PairQuery a) {
   if (a.skip && *a.skip) return;
   float4* s_col = smem;
   EdgeWave<MD>* s_w = (EdgeWave<MD>*)(smem + MD + 1);
-  float* s_cx = (float*)(s_w + 4);
-  float* s_cy = s_cx + a.W;
-  double* s_cxd = nullptr;
-  if (MD == 32) s_cxd = (double*)(((uintptr_t)(s_cy + a.H) + 7) & ~(uintptr_t)7);
   edge_colours(a, s_col);
-  edge_centres(a.W, a.H, s_cx, s_cy, s_cxd);
+  const EdgeCentres<MD> ct = edge_centres<MD>(a.W, a.H, s_w + 4);
   __syncthreads();
   // one pair per wave, no loop: values set up for the pair die with it
   // instead of living across a loop (which costs spilled registers)
   const int wave = threadIdx.x >> 6;
   const uint64_t p = ((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wave;
-  if (p < a.L) edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy, s_cxd);
+  if (p < a.L) edge_pair<C, MD>(a, p, s_w[wave], s_col, ct);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -443,7 +468,6 @@ void k_batch_dloss(const BatchTable* __restrict__ T) {
   if (all == 0) return;   // nothing of this kind in the batch
   float4* s_col = smem;
   EdgeWave<MD>* s_w = (EdgeWave<MD>*)(smem + MD + 1);
-  float* s_cx = (float*)(s_w + 4);
   const int wave = threadIdx.x >> 6;
   for (int kq = 0; kq < 8; ++kq) {
     const int x = (home + kq) & 7;
@@ -486,15 +510,11 @@ void k_batch_dloss(const BatchTable* __restrict__ T) {
       const uint64_t chunk = (uint64_t)sg.c0 + 8u * (it - sg.item0);
       const uint64_t p0 = chunk * (uint64_t)a.S;
       const uint64_t p1 = umin64(p0 + (uint64_t)a.S, a.L);
-      float* s_cy = s_cx + a.W;
-      double* s_cxd = nullptr;
-      if (MD == 32) s_cxd = (double*)(((uintptr_t)(s_cy + a.H) + 7) & ~(uintptr_t)7);
       __syncthreads();   // the previous item's readers of the tables are done
       edge_colours(a, s_col);
-      edge_centres(a.W, a.H, s_cx, s_cy, s_cxd);
+      const EdgeCentres<MD> ct = edge_centres<MD>(a.W, a.H, s_w + 4);
       __syncthreads();
-      for (uint64_t p = p0 + wave; p < p1; p += 4)
-        edge_pair<C, MD>(a, p, s_w[wave], s_col, s_cx, s_cy, s_cxd);
+      for (uint64_t p = p0 + wave; p < p1; p += 4) edge_pair<C, MD>(a, p, s_w[wave], s_col, ct);
       if (threadIdx.x == 0) s_item = next;
       __syncthreads();
       it = uniform64(s_item);
