@@ -57,8 +57,14 @@ FLOP_PER_PIXEL = 12.0
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy, valid for the kernel
 # source with this code digest (code_digest: comments and blank lines left
 # out); reported as null once the code has changed (or before it is measured).
-TRAFFIC_BYTES_PER_LAUNCH = 56844062
-TRAFFIC_SOURCE_DIGEST = "25a4eba1529f2e57203ae1b76f54d8b0b69706025d5b05b6697bf79699358d49"
+TRAFFIC_BYTES_PER_LAUNCH = 56814370
+TRAFFIC_SOURCE_DIGEST = "72b2b952c4d33b4c0216ea639b73192341ce6d4b96e6ba25b916d3fadb1b0202"
+# SQ counters of the same kernel source (rocprofv3 --pmc, mean of the step's
+# 10 launches): VALU instructions per launch (131072 pairs), VALU
+# instructions per CU and GRBM_GUI_ACTIVE cycle, and lane activity
+# (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)); null once the code changes
+COUNTERS_PER_LAUNCH = {"valu_insts": 766184446, "valu_per_cu_cycle": 1.271,
+                       "lane_activity": 0.607}
 
 
 def code_digest(path):
@@ -77,6 +83,10 @@ def code_digest(path):
 def raster_traffic():
     src = os.path.join(ROOT, "paper_2412_03489_amd", "csrc", "hr_edges.hip")
     return TRAFFIC_BYTES_PER_LAUNCH if code_digest(src) == TRAFFIC_SOURCE_DIGEST else None
+
+
+def raster_counters():
+    return dict(COUNTERS_PER_LAUNCH) if raster_traffic() is not None else None
 
 
 def golden(name):
@@ -445,7 +455,12 @@ def main_section(P, ctx, args):
                      "traffic": raster_traffic(), "kernel": "k_raster_dloss",
                      "avg_launch_ms": round(avg_ms, 4), "launches": int(launches),
                      "flop_per_pixel": FLOP_PER_PIXEL,
-                     "renders_per_launch": 4 * w.N},
+                     "renders_per_launch": 4 * w.N,
+                     # the kernel decides only the pixels along the disks'
+                     # edges, so the rate per perturbed pixel can exceed the
+                     # FP32 peak; VALU issue is its bound
+                     "per_pixel_equivalent": True,
+                     "counters": raster_counters()},
         "roofline_gradient": {"bound": "alu", "kernel": "k_raster_loss",
                               "achieved": round(g_achieved, 3), "peak": PEAK_FP32_TFLOPS,
                               "unit": "TFLOP/s", "frac": round(g_achieved / PEAK_FP32_TFLOPS, 4),

@@ -1,6 +1,6 @@
-"""Host logic of bench.py (no GPU): the measured raster traffic stays valid
-across comment edits of the kernel source and is reported as null once its
-code changes; more than one GPU is refused with a message."""
+"""Host logic of bench.py (no GPU): the measured raster traffic and counters
+stay valid across comment edits of the kernel source and are reported as null
+once its code changes; more than one GPU is refused with a message."""
 import importlib.util
 import os
 import subprocess
@@ -36,8 +36,10 @@ def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch)
     (src / "hr_edges.hip").write_text("int g() { return 1; }\n")
     monkeypatch.setattr(B, "ROOT", str(tmp_path))
     assert B.raster_traffic() is None
+    assert B.raster_counters() is None
     monkeypatch.setattr(B, "TRAFFIC_SOURCE_DIGEST", B.code_digest(str(src / "hr_edges.hip")))
     assert B.raster_traffic() == B.TRAFFIC_BYTES_PER_LAUNCH
+    assert B.raster_counters() == B.COUNTERS_PER_LAUNCH
 
 
 def test_more_than_one_gpu_is_refused():
