@@ -1,5 +1,6 @@
 """Edge cases of the disk path against the oracle on the same draws: a 1x1
-image, the maximum disk count, a 4096x4096 image, the rasteriser's disk-count
+image, the maximum disk count, a 4096x4096 image, the render pairs' largest
+images (W + H = 2048) and the first size past them, the rasteriser's disk-count
 boundaries (32 / 33: two renders per cull or one; 64 / 65: one wavefront of
 disks or several), odd render counts, nothing covered (disks outside the
 image or with non-positive radii), and extreme sigma.  Bar as in the parity suite: 1e-4
@@ -102,6 +103,15 @@ def test_large_image(P, ctx):
     """4096 x 4096, one channel: 16.8 M pixels per render."""
     w = make(4096, 4096, 4, C=1, seed=11, centre=(0.2, 0.8), radius=(0.1, 0.2))
     check(P, ctx, w, kinds=("grad", "hvp"), N=2)
+
+
+@pytest.mark.parametrize("W,H,D", [(2040, 8, 12), (8, 2040, 40), (1024, 1024, 20), (1025, 1024, 6)])
+def test_render_pairs_at_the_image_size_limit(P, ctx, W, H, D):
+    """The HVP's render pairs up to W + H = 2048 (pixel coordinates packed in 11
+    bits each; 32- and 64-disk layouts), and one pixel beyond it, where the
+    per-render path takes over."""
+    w = make(W, H, D, C=1, seed=W + 3 * H + D, radius=(0.02, 0.1))
+    check(P, ctx, w, kinds=("hvp",), N=4)
 
 
 def test_nothing_covered(P, ctx):
