@@ -136,9 +136,10 @@ __device__ __forceinline__ int edge_row0(const float4& v, float R, int H) {
 // then y): the FP32 ones of the per-render rasteriser, ((float)x + 0.5f) / W,
 // and the FP64 ones of the exact test, (x + 0.5) / W.  The 32-disk layout
 // keeps only the FP64 table and rounds it to FP32: both divisions round
-// correctly, and the quotient (2x + 1) / 2W (W < 2^11) lies at least 2^-37
-// (relative) away from every FP32 rounding midpoint it does not equal, far
-// beyond the FP64 rounding, so the rounded FP64 centre is the FP32 centre.
+// correctly, and a quotient (2i + 1) / 2n (n = W or H, n < 2^11) lies at
+// least 2^-37 (relative) away from every FP32 rounding midpoint it does not
+// equal (a midpoint has 25 significant bits), far beyond the FP64 rounding,
+// so the rounded FP64 centre is the FP32 centre.
 // The 64-disk layout keeps only the FP32 table and divides in FP64 where it
 // needs the exact centre.
 template <int MD>
@@ -237,7 +238,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
                                           const float4* s_col, const EdgeCentres<MD>& ct) {
   const int lane = threadIdx.x & 63;
   const int D = a.D, W = a.W, H = a.H;
-  // lane k: disk k's record, parameters, outer radius and ring rows
+  // lane k: disk k's record and parameters, and the number of its ring's rows
   int cnt = 0;
   if (lane < D) {
     edge_disk(a, p, lane, L);
