@@ -27,10 +27,11 @@
 // Work decomposition: one wave per pair.  Lane k builds disk k's record and
 // its FP64 parameters under both shifts in LDS, the disks whose outer boxes
 // meet its own (the only ones that can cover a pixel of its ring), and its
-// ring's rows; the waves then take (disk, row) items 64 at a time, test the
-// few pixel centres of each row's ring spans one step at a time, and queue
-// the ring pixels in LDS; 64 queued pixels are decided at a time, one per
-// lane.  Each lane sums its pixels' contributions in FP32 in queue order and
+// ring's rows; the waves then take (disk, row) items 64 at a time and queue
+// the few pixel centres of each row's ring spans in LDS, one per lane per
+// step (the spans hold hardly more pixels than the ring, about 1.01 per ring
+// pixel); 64 queued pixels are tested and decided at a time, one per lane.
+// Each lane sums its pixels' contributions in FP32 in queue order and
 // the wave adds the 64 sums in FP64 in a fixed order, so the result does not
 // depend on the launch shape or on the batch a query runs in.
 #include "hr_device.h"
@@ -41,7 +42,7 @@ namespace hr {
 namespace {
 
 constexpr int kEdgeDisks = 64;    // disks of a scene on this path: one per lane
-constexpr int kEdgeQueue = 128;   // queued ring pixels: fewer than 64 + one step's 64
+constexpr int kEdgeQueue = 128;   // queued span pixels: fewer than 64 + one step's 64
 // Absolute slack, in image units, on every bound derived from a record (row
 // ranges, ring spans, box overlaps): far above the FP32 rounding of the bound
 // computations, far below a pixel.
@@ -77,8 +78,8 @@ struct EdgeWave {
   // centre
   typename EdgeMask<MD>::T nbr[MD][4];
   int off[MD + 1];                    // its first (disk, row) item; off[D] = all items
-  // queued ring pixel: x | y << 11 | disk whose ring holds it << 22 |
-  // quadrant << 28 (W, H < 2048)
+  // queued pixel of a ring span: x | y << 11 | the ring's disk << 22 (W, H <
+  // 2048)
   uint32_t q[kEdgeQueue];
 };
 
@@ -160,19 +161,28 @@ struct EdgeCentres {
   }
 };
 
-// One ring pixel of disk k: the top disk under each shift, and the pixel's
-// (I+ - T)^2 - (I- - T)^2 over the channels (0 if the pixel belongs to the
-// ring of a disk above k, which counts it instead).
+// One pixel of a ring span of disk k: if it is in the ring, the top disk
+// under each shift and the pixel's (I+ - T)^2 - (I- - T)^2 over the channels
+// (0 if the pixel belongs to the ring of a disk above k, which counts it
+// instead); 0 outside the ring.  The ring test is the FP32 test of every
+// other "maybe" and "sure" decision, so each pixel is counted in at most one
+// disk's ring.
 template <int C, int MD>
 __device__ __forceinline__ float edge_pixel(const PairQuery& a, const EdgeWave<MD>& L,
                                             const float4* s_col, const EdgeCentres<MD>& ct,
-                                            int x, int y, int k, int quad) {
+                                            int x, int y, int k) {
   typedef EdgeMask<MD> M;
   typedef typename M::T Mask;
   const float pxf = ct.fx(x), pyf = ct.fy(y);
+  // a pixel of one of disk k's row spans: in its ring (inner <= d^2 <
+  // outer), or contributing nothing here
+  const float4 vk = L.rec[k];
+  const float dxk = pxf - vk.x, dyk = pyf - vk.y;
+  const float d2k = fmaf(dyk, dyk, dxk * dxk);
+  if (!(d2k < vk.z) || d2k < vk.w) return 0.0f;
   // only the neighbours that reach the pixel's quadrant of disk k's box can
   // cover it
-  const Mask nb = L.nbr[k][quad];
+  const Mask nb = L.nbr[k][(dxk >= 0.0f ? 1 : 0) | (dyk >= 0.0f ? 2 : 0)];
   // a disk above k that may cover the pixel: the pixel is in that disk's ring
   // or inside it, and is counted there (or contributes nothing)
   Mask up = k < MD - 1 ? nb & (~Mask(0) << (k + 1)) : Mask(0);
@@ -306,8 +316,8 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     float c = 0.0f;
     if (lane < cnt_q) {
       const uint32_t e = L.q[lane];
-      c = edge_pixel<C, MD>(a, L, s_col, ct, (int)(e & 0x7ffu),
-                            (int)((e >> 11) & 0x7ffu), (int)((e >> 22) & 0x3fu), (int)(e >> 28));
+      c = edge_pixel<C, MD>(a, L, s_col, ct, (int)(e & 0x7ffu), (int)((e >> 11) & 0x7ffu),
+                            (int)(e >> 22));
     }
     sum += c;
     // the rest of the queue to the front
@@ -324,15 +334,15 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
   int kcur = 0;   // items are in disk order: a lane's disk only moves up
   for (int base = 0; base < total; base += 64) {
     const int it = base + lane;
-    int x = 1, xe = 0, xc = 1, xd = 0, y = 0, k = kcur;
-    float4 v = make_float4(0.f, 0.f, -1.f, -1.f);
-    float dy = 0.0f;
+    int x = 1, xe = 0, xc = 1, xd = 0, k = kcur;
+    uint32_t yk = 0;   // the queued word's bits fixed by the item: y, k
     if (it < total) {
       while (L.off[k + 1] <= it) ++k;
       kcur = k;
-      v = L.rec[k];
-      y = edge_row0(v, edge_rad(v), H) + (it - L.off[k]);
-      dy = ct.fy(y) - v.y;
+      const float4 v = L.rec[k];
+      const int y = edge_row0(v, edge_rad(v), H) + (it - L.off[k]);
+      yk = ((uint32_t)y << 11) | ((uint32_t)k << 22);
+      const float dy = ct.fy(y) - v.y;
       const float dy2 = dy * dy;
       // |dx| < ro holds for every pixel with d^2 < outer on this row and
       // |dx| >= ri for every one with d^2 >= inner (slack: the FP32 rounding
@@ -349,23 +359,17 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       if (xc <= xe) xc = xe + 1;   // no pixel is tested twice
       if (x > xe) { x = xc; xe = xd; xc = 1; xd = 0; }
     }
-    // one pixel per lane per step, the queue drained 64 at a time
+    // the spans' pixels queued one per lane per step (the spans hold hardly
+    // more than the ring: the ring test comes with the decision), the queue
+    // drained 64 at a time
     for (;;) {
       const bool act = x <= xe;
-      if (__builtin_amdgcn_ballot_w64(act) == 0ull) break;
-      bool ring = false;
-      uint32_t quad = 0;
+      const uint64_t b = __builtin_amdgcn_ballot_w64(act);
+      if (b == 0ull) break;
       if (act) {
-        const float dx = ct.fx(x) - v.x;
-        const float d2 = fmaf(dy, dy, dx * dx);
-        ring = d2 < v.z && !(d2 < v.w);
-        quad = (dx >= 0.0f ? 1u : 0u) | (dy >= 0.0f ? 2u : 0u);
-      }
-      const uint64_t b = __builtin_amdgcn_ballot_w64(ring);
-      if (ring) {
         const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)b, qlen));
-        L.q[pos] = (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)k << 22) | quad << 28;
+        L.q[pos] = (uint32_t)x | yk;
       }
       qlen += (uint32_t)__builtin_popcountll(b);
       __builtin_amdgcn_wave_barrier();
@@ -421,7 +425,7 @@ __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
 }
 
 // Up to 32 disks the block's LDS (17.1 KB at 256 x 256) leaves room for 9
-// blocks of four waves per CU (50 VGPRs, no spills); the kernel, latency-
+// blocks of four waves per CU (46 VGPRs, no spills); the kernel, latency-
 // bound on its LDS and FP64 chains, ran faster with each step from 5 to 8
 // waves per SIMD and no faster at 9.  The 7 asked for keeps the register
 // budget from dropping below 72.  With 64 disks the LDS allows 5.
