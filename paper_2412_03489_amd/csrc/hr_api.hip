@@ -221,7 +221,7 @@ QueryBufs carve(const QueryPlan& p, void* base) {
 
 void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBufs& qb,
                   const double* d_theta, const double* d_v, double* d_out, int S, int shape,
-                  bool timing) {
+                  bool timing, bool keep_draws) {
   const hr_scene* sc = pl.sc;
   const hr_opts& o = pl.o;
   const EstShape& e = pl.e;
@@ -243,7 +243,7 @@ void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBu
   void* acc = qb.acc;
 
   if (what == kHvp || what == kHvpLimit)
-    T("sample", [&] { launch_sample_vnorm(s, e, tau, d_v, u, vnorm); });
+    T("sample", [&] { launch_sample_vnorm(s, e, tau, d_v, u, vnorm, !keep_draws); });
   else
     T("sample", [&] { launch_sample(s, e, tau); });
   const int spb = S;
@@ -307,9 +307,12 @@ const char* est_range(int what) {
   }
 }
 
+// keep_draws: an HVP whose draws the previous query of the same plan left in
+// the workspace (the products of one CG solve share their seed)
 hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, uint64_t N,
                   uint64_t seed, const double* d_v, const hr_opts& o_in, double* d_out,
-                  double* h_dbg, double* h_tau, const int* skip = nullptr) {
+                  double* h_dbg, double* h_tau, const int* skip = nullptr,
+                  bool keep_draws = false) {
   TraceRange range(est_range(what));
   QueryPlan pl;
   hr_status st = plan_query(sc, what, sigma, N, seed, d_v != nullptr, o_in, &pl);
@@ -325,11 +328,14 @@ hr_status run_est(hr_scene* sc, int what, const double* d_theta, double sigma, u
   if (pl.total > ctx->budget)
     return fail(HR_ENOMEM, "request needs " + std::to_string(pl.total) +
                                " bytes of workspace, budget is " + std::to_string(ctx->budget));
+  void* const ws_before = ctx->ws;
   st = ensure(ctx, &ctx->ws, &ctx->ws_bytes, pl.total);
   if (st) return st;
+  if (ctx->ws != ws_before) keep_draws = false;   // a new workspace holds no draws
   const QueryBufs qb = carve(pl, ctx->ws);
   hipStream_t s = ctx->stream;
-  launch_query(ctx, s, pl, qb, d_theta, d_v, d_out, o.samples_per_block, o.raster_tile, true);
+  launch_query(ctx, s, pl, qb, d_theta, d_v, d_out, o.samples_per_block, o.raster_tile, true,
+               keep_draws);
   double* tau = qb.tau;
   double* f = qb.f;
   HR_HIP(hipGetLastError());
@@ -894,9 +900,11 @@ hr_status hr_newton_cg_step_dev(hr_scene* sc, double* d_theta, double sigma, uin
       launch_newton_full(s, n, Hm, g, no.trust_radius, no.eig_floor, work, d, cs);
     } else {
       launch_cg_init(s, n, g, no.trust_radius, no.modified, no.eig_floor, r, pv, d, cs);
+      // every product draws with the same seed, so the first product's draws
+      // stay in the workspace for the others (nothing between them writes it)
       for (int k = 0; k < no.cg_iters; ++k) {
         e = run_est(sc, no.hvp_limit ? kHvpLimit : kHvp, d_theta, sigma, N, seed, pv, o, Hp,
-                    nullptr, nullptr, &cs->stop);
+                    nullptr, nullptr, &cs->stop, k > 0);
         if (e) return e;
         launch_cg_update(s, n, Hp, r, pv, d, cs);
       }

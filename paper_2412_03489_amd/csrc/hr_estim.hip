@@ -564,8 +564,8 @@ void launch_sample(hipStream_t st, const EstShape& e, double* tau) {
 }
 
 void launch_sample_vnorm(hipStream_t st, const EstShape& e, double* tau, const double* v,
-                         double* u, double* vnorm) {
-  const uint64_t total = e.streams * e.N * (uint64_t)e.n;
+                         double* u, double* vnorm, bool draws) {
+  const uint64_t total = draws ? e.streams * e.N * (uint64_t)e.n : 0;
   hipLaunchKernelGGL(k_sample_vnorm, dim3(grid_for(total, 256)), dim3(256), 0, st, e.n, e.K,
                      e.hessk, e.mix_n2, e.sampler, e.N, e.seed, e.sigma, total, tau, v, u, vnorm,
                      e.skip);

@@ -38,9 +38,10 @@ struct EstShape {
 
 // ---- sampling ----
 void launch_sample(hipStream_t st, const EstShape& e, double* tau);
-// sampling with |v| and v / |v| of an HVP query computed by block 0
+// sampling with |v| and v / |v| of an HVP query computed by block 0; with
+// draws false only |v| and v / |v| (tau already holds the query's draws)
 void launch_sample_vnorm(hipStream_t st, const EstShape& e, double* tau, const double* v,
-                         double* u, double* vnorm);
+                         double* u, double* vnorm, bool draws = true);
 
 // ---- renders ----
 // Half-width of the band around r^2 outside which the FP32 and the FP64

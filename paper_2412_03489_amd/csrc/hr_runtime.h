@@ -166,10 +166,12 @@ QueryBufs carve(const QueryPlan& p, void* base);
 // The kernels of one planned query on stream s, its workspace carved as qb;
 // theta, v (or nullptr) and the output are device pointers.  S and shape pick
 // the raster configuration (0: library choice).  With timing, the launches
-// are timed under the per-query kernel names (ctx->stream must be s).
+// are timed under the per-query kernel names (ctx->stream must be s).  With
+// keep_draws an HVP query does not sample: qb.tau already holds its draws (a
+// query of the same plan, seed included, wrote them into this workspace).
 void launch_query(hr_ctx* ctx, hipStream_t s, const QueryPlan& pl, const QueryBufs& qb,
                   const double* d_theta, const double* d_v, double* d_out, int S, int shape,
-                  bool timing);
+                  bool timing, bool keep_draws = false);
 
 }  // namespace rt
 }  // namespace hr
