@@ -57,14 +57,14 @@ FLOP_PER_PIXEL = 12.0
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 256 MiB copy, valid for the kernel
 # source with this code digest (code_digest: comments and blank lines left
 # out); reported as null once the code has changed (or before it is measured).
-TRAFFIC_BYTES_PER_LAUNCH = 56815795
-TRAFFIC_SOURCE_DIGEST = "9e96b9e0c69f5f3469ec6bbf4e02865fde83a0baae63c4eb6efb1361ba2c3cd0"
+TRAFFIC_BYTES_PER_LAUNCH = 56815075
+TRAFFIC_SOURCE_DIGEST = "9e16c4411464b8edfbc5c75948d831571bb90950294de1965e129fce815d7944"
 # SQ counters of the same kernel source (rocprofv3 --pmc, mean of the step's
 # 10 launches): VALU instructions per launch (131072 pairs), VALU
 # instructions per CU and GRBM_GUI_ACTIVE cycle, and lane activity
 # (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)); null once the code changes
-COUNTERS_PER_LAUNCH = {"valu_insts": 634187257, "valu_per_cu_cycle": 1.222,
-                       "lane_activity": 0.657}
+COUNTERS_PER_LAUNCH = {"valu_insts": 626283457, "valu_per_cu_cycle": 1.229,
+                       "lane_activity": 0.650}
 
 
 def code_digest(path):

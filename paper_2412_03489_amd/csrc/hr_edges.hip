@@ -77,6 +77,7 @@ struct EdgeWave {
   // they reach: [dx >= 0 | (dy >= 0) << 1] for a pixel at (dx, dy) from its
   // centre
   typename EdgeMask<MD>::T nbr[MD][4];
+  float rad[MD];                      // outer radius (-1: none)
   int off[MD + 1];                    // its first (disk, row) item; off[D] = all items
   // queued pixel of a ring span: x | y << 11 | the ring's disk << 22 (W, H <
   // 2048)
@@ -120,12 +121,9 @@ __device__ __forceinline__ void edge_disk(const PairQuery& a, uint64_t p, int k,
     if (rm > 0.0) out.w = (float)(rm * rm - band);
   }
   L.rec[k] = out;
-}
-
-// outer radius of a record (-1: none): the hardware square root (within 1
-// ulp); the bounds built on it carry kEdgeEps of slack
-__device__ __forceinline__ float edge_rad(const float4& v) {
-  return v.z > 0.0f ? __builtin_amdgcn_sqrtf(v.z) : -1.0f;
+  // the outer radius, by the hardware square root (within 1 ulp): the bounds
+  // built on it carry kEdgeEps of slack
+  L.rad[k] = out.z > 0.0f ? __builtin_amdgcn_sqrtf(out.z) : -1.0f;
 }
 
 // first row of a disk's ring (its outer box widened by kEdgeEps)
@@ -254,7 +252,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     edge_disk(a, p, lane, L);
     const float4 v = L.rec[lane];
     if (v.z > 0.0f) {
-      const float R = edge_rad(v);
+      const float R = L.rad[lane];
       const int y0 = edge_row0(v, R, H);
       const int y1 = min(H - 1, (int)ceilf((v.y + R + kEdgeEps) * (float)H - 0.5f));
       cnt = max(0, y1 - y0 + 1);
@@ -284,11 +282,11 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
     Mask m[4] = {0, 0, 0, 0};
     if (k < D) {
       const float4 vk = L.rec[k];
-      const float rk = edge_rad(vk);
+      const float rk = L.rad[k];
       if (rk > 0.0f)
         for (int j = j0; j < j1; ++j) {
           const float4 vj = L.rec[j];
-          const float rj = edge_rad(vj);
+          const float rj = L.rad[j];
           const float reach = rj + rk + 2.0f * kEdgeEps;
           const bool meet = j != k && rj > 0.0f && fabsf(vj.x - vk.x) <= reach &&
                             fabsf(vj.y - vk.y) <= reach;
@@ -340,7 +338,7 @@ __device__ __forceinline__ void edge_pair(const PairQuery& a, uint64_t p, EdgeWa
       while (L.off[k + 1] <= it) ++k;
       kcur = k;
       const float4 v = L.rec[k];
-      const int y = edge_row0(v, edge_rad(v), H) + (it - L.off[k]);
+      const int y = edge_row0(v, L.rad[k], H) + (it - L.off[k]);
       yk = ((uint32_t)y << 11) | ((uint32_t)k << 22);
       const float dy = ct.fy(y) - v.y;
       const float dy2 = dy * dy;
@@ -424,10 +422,10 @@ __host__ __device__ inline size_t edge_lds_bytes(int W, int H) {
          (size_t)(W + H) * (MD == 32 ? sizeof(double) : sizeof(float));
 }
 
-// Up to 32 disks the block's LDS (17.1 KB at 256 x 256) leaves room for 9
+// Up to 32 disks the block's LDS (17.6 KB at 256 x 256) leaves room for 8
 // blocks of four waves per CU (46 VGPRs, no spills); the kernel, latency-
 // bound on its LDS and FP64 chains, ran faster with each step from 5 to 8
-// waves per SIMD and no faster at 9.  The 7 asked for keeps the register
+// waves per SIMD and no faster at 9 (a layout without the radius table).  The 7 asked for keeps the register
 // budget from dropping below 72.  With 64 disks the LDS allows 5.
 template <int C, int MD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MD == 32 ? 7 : 1)))
