@@ -52,6 +52,9 @@ def scenes(P, ctx):
     out["c4"] = (w4, gpu_disks(ctx, w4, disk_target(w4)))
     w2 = small_disks(W=33, H=47, D=9, C=2, seed=6)
     out["c2"] = (w2, gpu_disks(ctx, w2, disk_target(w2)))
+    # 33 to 64 disks: the render pairs' 64-disk layout
+    w48 = small_disks(W=45, H=52, D=48, C=3, seed=9)
+    out["d48"] = (w48, gpu_disks(ctx, w48, disk_target(w48)))
     wp = WL.pt_spheres()
     tgt = pt_target(wp, spp=64, W=32, H=24)
     out["pt"] = (wp, P.Scene.pt(ctx, 32, 24, 2, wp.desc, tgt))
@@ -71,6 +74,7 @@ def mixed_queries(scenes):
     _, sq = scenes["quad"]
     _, sn = scenes["neggauss"]
     w2, s2 = scenes["c2"]
+    w48, s48 = scenes["d48"]
     vr = wr.v / np.linalg.norm(wr.v)
     vp = np.array([1.0, 0.2, -0.5, 0.3, 0.0, 0.7])
     return [
@@ -104,6 +108,8 @@ def mixed_queries(scenes):
              v=np.array([0.6, -0.8])),
         dict(scene=s4, kind="hvp", theta=w4.theta0, sigma=0.03, N=20, seed=19, v=w4.v,
              hvp_per_render=True),
+        dict(scene=s48, kind="hvp", theta=w48.theta0, sigma=0.02, N=50, seed=20,
+             v=w48.v / np.linalg.norm(w48.v)),
     ]
 
 
