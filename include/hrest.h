@@ -257,8 +257,9 @@ hr_status hr_est_hvp_dev(hr_scene* sc, const double* d_theta, double sigma, uint
  * workspace in a fixed array of 64 MiB that every GPU the library runs on
  * holds from context creation until the process ends; the call makes no
  * allocation.  The caller passes inputs and output as for hr_est_hvp_dev.
- * Requests whose workspace exceeds 64 MiB (on the 256x256 RGB, 32-disk
- * scene: about 16k draws) return HR_ENOMEM.  Every call on one GPU uses the
+ * Requests whose workspace exceeds 64 MiB return HR_ENOMEM (on the 256x256
+ * RGB, 32-disk scene: about 79k draws by render pairs, 9.5k with
+ * hvp_per_render).  Every call on one GPU uses the
  * same array: calls that overlap on one GPU (other streams, other contexts
  * of the device) race and must be ordered by the caller. */
 hr_status hr_est_hvp_dev_noalloc(hr_scene* sc, const double* d_theta, double sigma, uint64_t N,
