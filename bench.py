@@ -65,6 +65,11 @@ TRAFFIC_SOURCE_DIGEST = "9e16c4411464b8edfbc5c75948d831571bb90950294de1965e129fc
 # (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)); null once the code changes
 COUNTERS_PER_LAUNCH = {"valu_insts": 626283457, "valu_per_cu_cycle": 1.229,
                        "lane_activity": 0.650}
+# the same counters of the gradient's per-render kernel (k_raster_loss, 131072
+# renders per launch), valid for the rasteriser source with this digest
+GRADIENT_COUNTERS_PER_LAUNCH = {"valu_insts": 1574085178, "valu_per_cu_cycle": 0.997,
+                                "lane_activity": 0.978}
+GRADIENT_SOURCE_DIGEST = "3dab424d78be75391800e75b8beae93e6966f334696d37011efe1eb4c360ea6e"
 
 
 def code_digest(path):
@@ -87,6 +92,12 @@ def raster_traffic():
 
 def raster_counters():
     return dict(COUNTERS_PER_LAUNCH) if raster_traffic() is not None else None
+
+
+def gradient_counters():
+    src = os.path.join(ROOT, "paper_2412_03489_amd", "csrc", "hr_raster.hip")
+    ok = code_digest(src) == GRADIENT_SOURCE_DIGEST
+    return dict(GRADIENT_COUNTERS_PER_LAUNCH) if ok else None
 
 
 def golden(name):
@@ -465,7 +476,10 @@ def main_section(P, ctx, args):
                               "achieved": round(g_achieved, 3), "peak": PEAK_FP32_TFLOPS,
                               "unit": "TFLOP/s", "frac": round(g_achieved / PEAK_FP32_TFLOPS, 4),
                               "avg_launch_ms": round(g_avg_ms, 4), "launches": int(g_launches),
-                              "renders_per_launch": 2 * w.N},
+                              "renders_per_launch": 2 * w.N,
+                              # at the VALU issue limit (one non-packed
+                              # instruction per CU-cycle)
+                              "counters": gradient_counters()},
         "error_vs_fp64": errors,
         "cpu_baseline": None,
     }
