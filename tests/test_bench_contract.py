@@ -42,6 +42,17 @@ def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch)
     assert B.raster_counters() == B.COUNTERS_PER_LAUNCH
 
 
+def test_gradient_counters_only_for_the_measured_source(tmp_path, monkeypatch):
+    B = _bench()
+    src = tmp_path / "paper_2412_03489_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "hr_raster.hip").write_text("int h() { return 2; }\n")
+    monkeypatch.setattr(B, "ROOT", str(tmp_path))
+    assert B.gradient_counters() is None
+    monkeypatch.setattr(B, "GRADIENT_SOURCE_DIGEST", B.code_digest(str(src / "hr_raster.hip")))
+    assert B.gradient_counters() == B.GRADIENT_COUNTERS_PER_LAUNCH
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
