@@ -87,6 +87,19 @@ def test_disks32_hvp_full(P, disks32, which, fp64):
     assert err < TOL
 
 
+def test_disks32_hvp_full_rendered_one_by_one(P, disks32):
+    """The same HVP with every shifted scene rendered and its loss taken
+    separately (hvp_per_render): 262144 renders through the per-render
+    rasteriser and the loss pass instead of the render pairs."""
+    w, sc = disks32
+    ref = golden("disks32_hvp")
+    say(f"disks32 HVP rendered one by one N={w.N}")
+    hv = P.estimate("hvp", sc, w.theta0, w.sigma, w.N, w.seed, v=ref["v"], hvp_per_render=True)
+    err = rel_inf(hv, ref["out"])
+    say(f"  error vs FP64 oracle: rel_inf = {err:.3e}")
+    assert err < TOL
+
+
 @pytest.mark.parametrize("fp64", [False, True])
 def test_disks32_benchmarked_newton_step(P, disks32, fp64):
     w, sc = disks32
