@@ -10,6 +10,7 @@ oracle's own renders at theta*, stored as FP32):
   disks32_hvp       HVP along the workload's v, same query
   disks32_hvp_mg    HVP along -g (g = disks32_grad): the first product of
                     the Newton-CG step below
+  disks32_hvp_limit the limit-kernel HVP along the workload's v, same query
   disks32_newton    one Newton-CG step (1 gradient + 10 HVPs, Hessian
                     modification inside CG, trust radius 0.05), seed 3
   pt_hess           full 6x6 Hessian of the path-traced spheres scene,
@@ -89,6 +90,14 @@ def item_disks32_hvp_mg():
          inputs=digest(w.theta0, tgt, -g), seconds=time.time() - t0)
 
 
+def item_disks32_hvp_limit():
+    w, tgt, sc = disks32_scene()
+    t0 = time.time()
+    hv = O.estimate("hvp_limit", sc, w.theta0, w.sigma, w.N, w.seed, v=w.v)
+    save("disks32_hvp_limit", out=hv, v=w.v, N=w.N, seed=w.seed, sigma=w.sigma,
+         inputs=digest(w.theta0, tgt, w.v), seconds=time.time() - t0)
+
+
 def item_disks32_newton():
     w, tgt, sc = disks32_scene()
     t0 = time.time()
@@ -125,7 +134,8 @@ def item_uneven():
 
 
 ITEMS = {"disks32_grad": item_disks32_grad, "disks32_hvp": item_disks32_hvp,
-         "disks32_hvp_mg": item_disks32_hvp_mg, "pt_hess": item_pt_hess,
+         "disks32_hvp_mg": item_disks32_hvp_mg, "disks32_hvp_limit": item_disks32_hvp_limit,
+         "pt_hess": item_pt_hess,
          "uneven": item_uneven, "disks32_newton": item_disks32_newton}
 
 if __name__ == "__main__":

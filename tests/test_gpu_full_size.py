@@ -87,6 +87,18 @@ def test_disks32_hvp_full(P, disks32, which, fp64):
     assert err < TOL
 
 
+def test_disks32_hvp_limit_full(P, disks32):
+    """The limit-kernel HVP (one render per draw and sign, the kernel's
+    v-weighted lobe sums) at the full size."""
+    w, sc = disks32
+    ref = golden("disks32_hvp_limit")
+    say(f"disks32 limit-kernel HVP N={w.N}")
+    hv = P.estimate("hvp_limit", sc, w.theta0, w.sigma, w.N, w.seed, v=ref["v"])
+    err = rel_inf(hv, ref["out"])
+    say(f"  error vs FP64 oracle: rel_inf = {err:.3e}")
+    assert err < TOL
+
+
 def test_disks32_hvp_full_rendered_one_by_one(P, disks32):
     """The same HVP with every shifted scene rendered and its loss taken
     separately (hvp_per_render): 262144 renders through the per-render
